@@ -1,0 +1,232 @@
+#!/usr/bin/env python3
+"""Benchmark of the CG detection + precoding hot path on one MI355X.
+
+One step = one TDD slot over a batch of F frames of the named workload:
+uplink soft-output detection (Gram + matched filter, K CG iterations with
+in-loop SINR, max-log LLRs) followed by downlink CG precoding with power
+normalization on the same (reciprocal) channels.  Inputs are seeded
+synthetic frames already resident in HBM; the batch (default 16 frames,
+~0.7 GB) is larger than the 256 MB Infinity Cache, so HBM is what is timed.
+
+Prints progress to stderr and ONE JSON line to stdout.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--workload mixed_128x16]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
+METRIC = "MMSE-CG subcarrier-solves/s + LLR Gbit/s at B=128,U=16; p50/p99 frame latency"
+CFG_INDEX = {"small_32x8": 1, "plain_128x8": 2, "mixed_128x16": 3, "mixed_128x32": 3,
+             "corr_256x32": 5}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def detect_bytes_per_sc(B, U, S, m, elem_bytes=8):
+    """Algorithmic HBM bytes of detection per subcarrier: read H and Y once,
+    write the LLRs (FP32)."""
+    return elem_bytes * B * U + elem_bytes * B * S + 4 * U * S * m
+
+
+def precode_bytes_per_sc(B, U, S, elem_bytes=8):
+    """Read H and T, write Q (complex64)."""
+    return elem_bytes * B * U + 8 * U * S + 8 * B * S
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="mixed_128x16")
+    ap.add_argument("--frames", type=int, default=16, help="frames per step (batch)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-latency", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the path shards by subcarrier with no "
+              "cross-GPU exchange, and multi-GPU runs are not part of this build "
+              "(use --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    from paper_1404_0424_amd import api
+    from paper_1404_0424_amd import workload as W
+
+    wl = W.WORKLOADS[args.workload]
+    F = args.frames
+    n = wl.n_sc * F
+    snr = wl.snr_db[0] if len(wl.snr_db) == 1 else 10.0
+    t = time.perf_counter()
+    rng = W.rng_for(CFG_INDEX.get(wl.name, 9), 0)
+    up = W.uplink_frame(rng, n, wl.B, wl.U, wl.S, wl.m, snr, channel=wl.channel,
+                        rho_bs=wl.rho_bs, rho_ue=wl.rho_ue)
+    dn = W.downlink_frame(rng, n, wl.B, wl.U, wl.S, wl.m, snr, H=up.H)
+    log(f"generated {F} frames of {wl.name} in {time.perf_counter() - t:.1f}s")
+
+    dev = torch.device("cuda:0")
+    H = torch.from_numpy(up.H.astype(np.complex64)).to(dev)
+    Y = torch.from_numpy(up.Y.astype(np.complex64)).to(dev)
+    T = torch.from_numpy(dn.T.astype(np.complex64)).to(dev)
+    llr = torch.empty((n, wl.U, wl.S, wl.m), dtype=torch.float32, device=dev)
+    Q = torch.empty((n, wl.B, wl.S), dtype=torch.complex64, device=dev)
+    scalar = "f64" if wl.scalar_f64 else "f32"
+    n0, es, beta, K, m = up.n0, up.es, dn.beta, wl.K, wl.m
+
+    def run_steps(Hx, Yx, steps, record=True):
+        evs = []
+        for _ in range(steps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e2 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            api.detect_cg(Hx, Yx, n0, es, K, m, "approx", scalar, out={"llr": llr})
+            e1.record()
+            api.precode_cg(Hx, T, beta, K, normalize=True, scalar_prec=scalar, qnorm=False, out=Q)
+            e2.record()
+            evs.append((e0, e1, e2))
+        return evs
+
+    def timed(Hx, Yx, label):
+        run_steps(Hx, Yx, args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        evs = run_steps(Hx, Yx, args.steps)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps
+        det = float(np.mean([a.elapsed_time(b) for a, b, _ in evs])) / 1e3
+        pre = float(np.mean([b.elapsed_time(c) for _, b, c in evs])) / 1e3
+        log(f"{label}: {wall * 1e3:.3f} ms/step (detect {det * 1e3:.3f} ms, "
+            f"precode {pre * 1e3:.3f} ms)")
+        return wall, det, pre
+
+    wall, det_s, pre_s = timed(H, Y, "complex64")
+    solves = 2 * n * wl.S                      # uplink + downlink CG solves per step
+    llr_bits = n * wl.S * wl.U * wl.m
+    det_bytes = detect_bytes_per_sc(wl.B, wl.U, wl.S, wl.m) * n
+    pre_bytes = precode_bytes_per_sc(wl.B, wl.U, wl.S) * n
+    achieved = det_bytes / det_s / 1e9
+
+    result = {
+        "metric": METRIC,
+        "value": solves / wall,
+        "unit": "subcarrier-solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if scalar == "f32" else "f32 (f64 CG scalars)",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "B": wl.B, "U": wl.U, "subcarriers_per_frame": wl.n_sc,
+                   "S": wl.S, "qam_bits": wl.m, "K": wl.K, "snr_db": snr, "channel": wl.channel,
+                   "frames_per_step": F, "step": "uplink detection + downlink precoding",
+                   "storage": "complex64"},
+        "llr_gbit_s": llr_bits / wall / 1e9,
+        "uplink": {"solves_per_s": n * wl.S / det_s, "llr_gbit_s": llr_bits / det_s / 1e9,
+                   "kernel_ms": det_s * 1e3, "hbm_gbs": achieved},
+        "downlink": {"solves_per_s": n * wl.S / pre_s, "kernel_ms": pre_s * 1e3,
+                     "hbm_gbs": pre_bytes / pre_s / 1e9},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "detect_approx_kernel",
+                     "bytes_per_subcarrier": detect_bytes_per_sc(wl.B, wl.U, wl.S, wl.m),
+                     "subcarriers_per_launch": n},
+    }
+
+    if not args.no_variants:
+        variants = {}
+        for dt in ("f16", "bf16"):
+            H16, Y16 = api.convert(H, dt), api.convert(Y, dt)
+            torch.cuda.synchronize()
+            w2, d2, p2 = timed(H16, Y16, dt)
+            b16 = detect_bytes_per_sc(wl.B, wl.U, wl.S, wl.m, elem_bytes=4) * n
+            variants[dt] = {"solves_per_s": solves / w2, "ms_per_step": w2 * 1e3,
+                            "uplink_solves_per_s": n * wl.S / d2,
+                            "llr_gbit_s": llr_bits / w2 / 1e9,
+                            "detect_kernel_ms": d2 * 1e3, "detect_hbm_gbs": b16 / d2 / 1e9,
+                            "precode_kernel_ms": p2 * 1e3,
+                            "storage": f"{dt} H and Y, FP32 accumulate and CG"}
+            del H16, Y16
+        result["variants"] = variants
+
+    if not args.no_latency:
+        # one frame (wl.n_sc subcarriers) on an idle GPU: UL detect + DL precode
+        H1, Y1, T1 = H[:wl.n_sc], Y[:wl.n_sc], T[:wl.n_sc]
+        l1 = torch.empty((wl.n_sc, wl.U, wl.S, wl.m), dtype=torch.float32, device=dev)
+        Q1 = torch.empty((wl.n_sc, wl.B, wl.S), dtype=torch.complex64, device=dev)
+        lat = []
+        for i in range(60):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            api.detect_cg(H1, Y1, n0, es, K, m, "approx", scalar, out={"llr": l1})
+            api.precode_cg(H1, T1, beta, K, normalize=True, scalar_prec=scalar, qnorm=False, out=Q1)
+            e1.record()
+            torch.cuda.synchronize()
+            if i >= 10:
+                lat.append(e0.elapsed_time(e1))
+        result["frame_latency_ms"] = {"p50": float(np.percentile(lat, 50)),
+                                      "p99": float(np.percentile(lat, 99)),
+                                      "what": "one frame, UL detect + DL precode, idle GPU"}
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(up, dn, wl, llr, Q, args.cpu_seconds)
+
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(up, dn, wl, llr_gpu, Q_gpu, seconds):
+    """The FP64 oracle on the host, single-threaded, on a bounded sample of the
+    same workload; also reports the GPU's error against it on that sample."""
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from oracle import mimo_oracle as O
+    from threadpoolctl import threadpool_limits
+    chunk = 32
+    rng = np.random.default_rng(0)
+    done = 0
+    el = eq = None
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            idx = np.sort(rng.choice(up.H.shape[0], chunk, replace=False))
+            r = O.detect_cg(up.H[idx], up.Y[idx], up.n0, up.es, wl.K, wl.m, "approx")
+            p = O.precode_cg(up.H[idx], dn.T[idx], dn.beta, wl.K, normalize=True)
+            done += chunk
+            if el is None:
+                llr_h = llr_gpu[idx].cpu().numpy().astype(np.float64)
+                Q_h = Q_gpu[idx].cpu().numpy().astype(np.complex128)
+                d = np.max(np.abs(llr_h - r["llr"]), axis=-1) / np.maximum(
+                    1.0, np.max(np.abs(r["llr"]), axis=-1))
+                el = float(d.max())
+                eq = float(np.max(np.linalg.norm(Q_h - p["Q"], axis=1)
+                                  / np.linalg.norm(p["Q"], axis=1)))
+        el_s = time.perf_counter() - t0
+    solves = 2 * done * wl.S
+    log(f"cpu oracle: {done} subcarriers in {el_s:.1f}s")
+    return {"value": solves / el_s, "unit": "subcarrier-solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} random subcarriers of the timed batch ({wl.S} symbols each), "
+                      f"uplink detection + downlink precoding, numpy FP64, 1 thread",
+            "gpu_error_vs_oracle_on_sample": {"eps_llr": el, "eps_q": eq}}
+
+
+if __name__ == "__main__":
+    main()

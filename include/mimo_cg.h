@@ -1,0 +1,168 @@
+/*
+ * mimo_cg.h -- C ABI of the MI355X (gfx950) library for conjugate-gradient
+ * soft-output MMSE detection and CG precoding in massive MIMO.
+ *
+ * Method: B. Yin, M. Wu, J. R. Cavallaro, C. Studer, "Conjugate
+ * Gradient-based Soft-Output Detection and Precoding in Massive MIMO
+ * Systems" (Sec. II system models, Sec. III and Algorithm 1).
+ *
+ * General rules for every entry point
+ *  - Data pointers are DEVICE pointers (HBM) owned by the caller; the library
+ *    never frees or retains them past the call.  Outputs must not alias
+ *    inputs.  Pointers must be 16-byte aligned.
+ *  - Calls validate their arguments synchronously and return a negative
+ *    mimo_status before anything is enqueued.  Valid calls enqueue kernels
+ *    on `stream` (a hipStream_t passed as void*; NULL = the default stream)
+ *    and return MIMO_OK without waiting.  A device fault surfaces as a HIP
+ *    error at the caller's next synchronization; a launch failure returns
+ *    MIMO_EHIP and mimo_last_error() names it.
+ *  - The library allocates no device memory.
+ *  - Complex numbers are interleaved {re, im}.  complex64 = 2 x float.
+ *  - All arrays are dense and row-major, indexed by subcarrier first:
+ *      H    [n_sc][B][U]   uplink channel H_u (B x U per subcarrier);
+ *                          the downlink channel is H_d = H_u^H (Sec. II-B)
+ *      Y    [n_sc][B][S]   S receive vectors y (columns) sharing one H
+ *      T    [n_sc][U][S]   S downlink symbol vectors t (complex64)
+ *      A    [n_sc][U][U]   regularized Gram matrix (complex64)
+ *      b    [n_sc][U][S]   matched-filter outputs (complex64)
+ *      xhat [n_sc][U][S]   equalized symbols v_K (complex64)
+ *      mu, sinr [n_sc][U][S]  equalized gain and post-equalization SINR
+ *      llr  [n_sc][U][S][qam_bits]
+ *      Q    [n_sc][B][S]   precoded vectors q (or s = q/||q||), complex64
+ *      qnorm [n_sc][S]     ||q||_2 of each precoded vector
+ *  - Reduced-precision channel/receive storage (MIMO_C16, MIMO_CBF16) uses
+ *    the blocked layout written by mimo_convert: for a [n][R][C] complex
+ *    array (R = B, a multiple of 8), element (n, r, c) sits in block
+ *    [n][r/8][part][c][r%8] with part 0 = real, part 1 = imaginary, i.e.
+ *    8 consecutive antennas of one column are contiguous per part.
+ */
+#ifndef MIMO_CG_H
+#define MIMO_CG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MIMO_MAX_USERS 32   /* largest U supported */
+#define MIMO_MAX_ANTENNAS 4096
+
+typedef struct mimo_shape {
+  int32_t B;     /* base-station antennas, U <= B <= MIMO_MAX_ANTENNAS */
+  int32_t U;     /* single-antenna users, 1 <= U <= MIMO_MAX_USERS */
+  int32_t S;     /* right-hand sides per subcarrier (OFDM symbols), >= 1 */
+  int32_t K;     /* CG iterations (Algorithm 1), 1 <= K <= 1024 */
+  int64_t n_sc;  /* independent subcarrier systems, >= 0 (0 = no-op) */
+} mimo_shape;
+
+/* Storage type of H (and Y) */
+enum { MIMO_C32 = 0, MIMO_C16 = 1, MIMO_CBF16 = 2 };
+/* In-loop SINR computation (Sec. III-C) */
+enum { MIMO_SINR_APPROX = 0, MIMO_SINR_EXACT = 1 };
+/* Precision of the CG scalar recurrences (||r||^2, p^H e, alpha, beta) */
+enum { MIMO_SCALAR_F32 = 0, MIMO_SCALAR_F64 = 1 };
+/* Operations, for mimo_workspace_bytes */
+enum { MIMO_OP_GRAM_MF = 0, MIMO_OP_DETECT = 1, MIMO_OP_PRECODE = 2 };
+
+typedef enum mimo_status {
+  MIMO_OK = 0,
+  MIMO_EINVAL = -1,        /* bad pointer, size, or parameter value */
+  MIMO_EUNSUPPORTED = -2,  /* valid per the paper but not built here */
+  MIMO_EWORKSPACE = -3,    /* workspace missing or too small */
+  MIMO_EHIP = -4           /* HIP runtime error at launch */
+} mimo_status;
+
+/*
+ * mimo_gram_mf -- regularized Gram matrix and matched filter.
+ * Algorithm 1, initialization (detection): A = H^H H + reg I and b = H^H y
+ * for every column y of Y (eq. (8)).  With reg = N0/E_s this is the uplink
+ * system; with reg = beta it is the precoding matrix of eq. (16) by
+ * reciprocity (H_d H_d^H = H_u^H H_u).
+ *   H      [n_sc][B][U], storage type in_dtype
+ *   Y      [n_sc][B][S], storage type in_dtype, or NULL (then b is not written)
+ *   reg    >= 0, added to the diagonal
+ *   A      out, complex64 [n_sc][U][U]; the upper triangle is computed, the
+ *          lower triangle is its conjugate mirror, the diagonal is real
+ *   b      out, complex64 [n_sc][U][S], or NULL
+ * Uses shape->B, U, S, n_sc (K is ignored).
+ */
+int mimo_gram_mf(const mimo_shape* shape, const void* H, const void* Y,
+                 int in_dtype, float reg, void* A, void* b, void* stream);
+
+/*
+ * mimo_detect_cg -- CG-based soft-output MMSE detection (Sec. III-B/C).
+ * Per subcarrier and right-hand side: A = H^H H + (n0/es) I, b = H^H y,
+ * K iterations of Algorithm 1 (v_0 = 0, r_0 = p_0 = b), xhat = v_K; the
+ * equalized gain mu and SINR rho tracked inside the recursion, either
+ *   MIMO_SINR_APPROX: eq. (13) with A replaced by its diagonal D, giving
+ *     mu_i = L~_ii G_ii (eq. (14)) and rho_i = G_ii / N0 (eq. (15)); or
+ *   MIMO_SINR_EXACT: the CG-equivalent matrix L_K of eqs. (9), (12), with
+ *     mu_i = (L_K G)_ii and rho_i = mu_i^2 / nu_i^2 (Sec. III-C-1);
+ * then max-log LLRs (eq. (4)) of z = xhat/mu over square Gray QAM:
+ *   llr[..][b] = rho * (min_{a in X_b^0} |z-a|^2 - min_{a in X_b^1} |z-a|^2)
+ * (positive favours bit 1).  Constellation: per axis, levels
+ * 2j-(L-1), j=0..L-1, L = 2^(qam_bits/2), labelled by the Gray code of j
+ * (MSB first); bits [0, qam_bits/2) are the in-phase label, the rest the
+ * quadrature label; scaled to average energy es.
+ * Degenerate systems: a right-hand side whose residual norm is 0 freezes
+ * (alpha = beta = 0); mu = 0 gives z = 0 and rho = G_ii / N0.
+ *   n0 > 0, es > 0; qam_bits in {2, 4, 6, 8}
+ *   scalar_prec  MIMO_SCALAR_F32 or MIMO_SCALAR_F64 (CG scalars in FP64,
+ *                vectors stay FP32)
+ *   llr   out, float [n_sc][U][S][qam_bits]            (required)
+ *   xhat  out, complex64 [n_sc][U][S] or NULL
+ *   mu    out, float [n_sc][U][S] or NULL
+ *   sinr  out, float [n_sc][U][S] or NULL
+ *   workspace / workspace_bytes: may be NULL / 0 when
+ *         mimo_workspace_bytes(shape, MIMO_OP_DETECT, sinr_mode) is 0.
+ */
+int mimo_detect_cg(const mimo_shape* shape, const void* H, const void* Y,
+                   int in_dtype, float n0, float es, int qam_bits,
+                   int sinr_mode, int scalar_prec, float* llr, void* xhat,
+                   float* mu, float* sinr, void* workspace,
+                   size_t workspace_bytes, void* stream);
+
+/*
+ * mimo_precode_cg -- CG-based linear precoding (Sec. III-D).
+ * Solves (H_d H_d^H + beta I) v = t (eq. (16)) by K iterations of
+ * Algorithm 1 and returns q = H_d^H v = H_u v (Algorithm 1 output);
+ * beta = 0 is zero forcing, beta = N0/E_s the MMSE precoder of eq. (6).
+ * With normalize != 0 the output is s = q / ||q||_2 per vector (Sec. II-B;
+ * ||q|| = 0 gives s = 0).  qnorm receives ||q||_2 either way.
+ *   H  [n_sc][B][U] storage type in_dtype;  T complex64 [n_sc][U][S]
+ *   beta >= 0;  Q out complex64 [n_sc][B][S];  qnorm out float [n_sc][S] or NULL
+ */
+int mimo_precode_cg(const mimo_shape* shape, const void* H, const void* T,
+                    int in_dtype, float beta, int normalize, int scalar_prec,
+                    void* Q, float* qnorm, void* workspace,
+                    size_t workspace_bytes, void* stream);
+
+/*
+ * mimo_convert -- channel / receive-vector ingest into reduced precision.
+ * Rounds a complex64 array [n][R][C] (R rows = antennas, a multiple of 8)
+ * to FP16 or BF16 with round-to-nearest-even and writes the blocked layout
+ * described above (dst_dtype MIMO_C16 or MIMO_CBF16).  dst holds
+ * n*R*C*2 16-bit values.  Storage format only; no method arithmetic.
+ */
+int mimo_convert(const void* src, void* dst, int dst_dtype, int64_t n,
+                 int32_t R, int32_t C, void* stream);
+
+/* Device workspace (bytes) that an operation needs; 0 means none. */
+size_t mimo_workspace_bytes(const mimo_shape* shape, int op, int sinr_mode);
+
+/* Static description of a status code. */
+const char* mimo_status_string(int status);
+
+/* Text of the last error recorded by this thread (validation or HIP). */
+const char* mimo_last_error(void);
+
+/* Library version string. */
+const char* mimo_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MIMO_CG_H */

@@ -1,0 +1,77 @@
+"""ctypes loader for libmimocg.so (the C ABI declared in include/mimo_cg.h).
+
+Loading fails loudly when the library has not been built: there is no
+fallback implementation anywhere in the package.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmimocg.so")
+
+MIMO_C32, MIMO_C16, MIMO_CBF16 = 0, 1, 2
+MIMO_SINR_APPROX, MIMO_SINR_EXACT = 0, 1
+MIMO_SCALAR_F32, MIMO_SCALAR_F64 = 0, 1
+MIMO_OP_GRAM_MF, MIMO_OP_DETECT, MIMO_OP_PRECODE = 0, 1, 2
+MIMO_OK, MIMO_EINVAL, MIMO_EUNSUPPORTED, MIMO_EWORKSPACE, MIMO_EHIP = 0, -1, -2, -3, -4
+MIMO_MAX_USERS = 32
+
+
+class MimoShape(ctypes.Structure):
+    _fields_ = [("B", ctypes.c_int32), ("U", ctypes.c_int32), ("S", ctypes.c_int32),
+                ("K", ctypes.c_int32), ("n_sc", ctypes.c_int64)]
+
+
+class MimoError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"[{status}] {message}")
+        self.status = status
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_f = ctypes.c_float
+_i = ctypes.c_int
+_sz = ctypes.c_size_t
+_shape_p = ctypes.POINTER(MimoShape)
+
+_SIGNATURES = {
+    "mimo_gram_mf": (_i, [_shape_p, _vp, _vp, _i, _f, _vp, _vp, _vp]),
+    "mimo_detect_cg": (_i, [_shape_p, _vp, _vp, _i, _f, _f, _i, _i, _i, _vp, _vp, _vp, _vp,
+                            _vp, _sz, _vp]),
+    "mimo_precode_cg": (_i, [_shape_p, _vp, _vp, _i, _f, _i, _i, _vp, _vp, _vp, _sz, _vp]),
+    "mimo_convert": (_i, [_vp, _vp, _i, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _vp]),
+    "mimo_workspace_bytes": (_sz, [_shape_p, _i, _i]),
+    "mimo_status_string": (ctypes.c_char_p, [_i]),
+    "mimo_last_error": (ctypes.c_char_p, []),
+    "mimo_version": (ctypes.c_char_p, []),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library (built by paper_1404_0424_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_1404_0424_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int) -> None:
+    if status != MIMO_OK:
+        L = lib()
+        msg = (L.mimo_last_error() or b"").decode() or L.mimo_status_string(status).decode()
+        raise MimoError(status, msg)
+
+
+def shape(B: int, U: int, S: int, K: int, n_sc: int) -> MimoShape:
+    return MimoShape(int(B), int(U), int(S), int(K), int(n_sc))

@@ -1,0 +1,161 @@
+"""Torch-facing binding of the C ABI: argument marshalling only.
+
+Device memory and streams come from PyTorch; every step of the computation
+runs in the library's HIP kernels.  Tensors follow the layouts documented in
+include/mimo_cg.h (complex64 tensors, or the blocked 16-bit storage returned
+by :func:`convert`).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import torch
+
+from . import _lib as L
+
+
+@dataclasses.dataclass
+class Packed16:
+    """Complex [n][R][C] array in blocked FP16/BF16 storage (mimo_convert)."""
+    data: torch.Tensor     # int16, shape (n, R // 8, 2, C, 8)
+    dtype_code: int        # MIMO_C16 or MIMO_CBF16
+    n: int
+    R: int
+    C: int
+
+    @property
+    def device(self):
+        return self.data.device
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _check_c64(t, name, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.complex64:
+        raise TypeError(f"{name} must be complex64, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on a GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def _channel(H):
+    """(pointer, dtype code, n, B, U) of a complex64 or packed channel."""
+    if isinstance(H, Packed16):
+        return H.data.data_ptr(), H.dtype_code, H.n, H.R, H.C
+    _check_c64(H, "H")
+    if H.dim() != 3:
+        raise ValueError("H must be (n_sc, B, U)")
+    n, B, U = H.shape
+    return H.data_ptr(), L.MIMO_C32, n, B, U
+
+
+def _rhs(Y, code, n, B):
+    if isinstance(Y, Packed16):
+        if Y.dtype_code != code or Y.n != n or Y.R != B:
+            raise ValueError("Y storage must match H (dtype, n_sc, B)")
+        return Y.data.data_ptr(), Y.C
+    if code != L.MIMO_C32:
+        raise ValueError("H is packed 16-bit, so Y must be packed the same way")
+    _check_c64(Y, "Y")
+    if Y.dim() != 3 or Y.shape[0] != n or Y.shape[1] != B:
+        raise ValueError("Y must be (n_sc, B, S)")
+    return Y.data_ptr(), Y.shape[2]
+
+
+def convert(X: torch.Tensor, dtype: str = "f16", stream=None) -> Packed16:
+    """Round a complex64 (n, R, C) tensor to blocked FP16 / BF16 storage."""
+    _check_c64(X, "X")
+    n, R, C = X.shape
+    code = {"f16": L.MIMO_C16, "bf16": L.MIMO_CBF16}[dtype]
+    out = torch.empty((n, R // 8, 2, C, 8), dtype=torch.int16, device=X.device)
+    L.check(L.lib().mimo_convert(X.data_ptr(), out.data_ptr(), code, n, R, C, _stream(stream)))
+    return Packed16(out, code, n, R, C)
+
+
+def gram_mf(H, Y=None, reg: float = 0.0, stream=None):
+    """A = H^H H + reg I and b = H^H Y.  Returns (A, b) (b is None without Y)."""
+    hp, code, n, B, U = _channel(H)
+    yp, S = (None, 1) if Y is None else _rhs(Y, code, n, B)
+    dev = H.device
+    A = torch.empty((n, U, U), dtype=torch.complex64, device=dev)
+    b = None if Y is None else torch.empty((n, U, S), dtype=torch.complex64, device=dev)
+    shp = L.shape(B, U, S, 1, n)
+    L.check(L.lib().mimo_gram_mf(shp, hp, yp, code, float(reg), A.data_ptr(), _ptr(b),
+                                 _stream(stream)))
+    return A, b
+
+
+def detect_cg(H, Y, n0: float, es: float, K: int, qam_bits: int, sinr_mode: str = "approx",
+              scalar_prec: str = "f32", xhat: bool = False, mu: bool = False,
+              sinr: bool = False, out=None, stream=None) -> dict:
+    """CG soft-output MMSE detection.  Returns a dict with 'llr' and the
+    optional 'xhat', 'mu', 'sinr' tensors.  ``out`` may hold preallocated
+    tensors under the same keys."""
+    hp, code, n, B, U = _channel(H)
+    yp, S = _rhs(Y, code, n, B)
+    dev = H.device
+    out = {} if out is None else dict(out)
+    res = {}
+
+    def get(key, shape, dtype, want):
+        if not want and key not in out:
+            return None
+        t = out.get(key)
+        if t is None:
+            t = torch.empty(shape, dtype=dtype, device=dev)
+        elif tuple(t.shape) != tuple(shape) or t.dtype != dtype or not t.is_contiguous():
+            raise ValueError(f"out['{key}'] must be contiguous {dtype} {shape}")
+        res[key] = t
+        return t
+
+    llr = get("llr", (n, U, S, qam_bits), torch.float32, True)
+    xh = get("xhat", (n, U, S), torch.complex64, xhat)
+    mu_t = get("mu", (n, U, S), torch.float32, mu)
+    sn = get("sinr", (n, U, S), torch.float32, sinr)
+    mode = {"approx": L.MIMO_SINR_APPROX, "exact": L.MIMO_SINR_EXACT}[sinr_mode]
+    prec = {"f32": L.MIMO_SCALAR_F32, "f64": L.MIMO_SCALAR_F64}[scalar_prec]
+    shp = L.shape(B, U, S, K, n)
+    L.check(L.lib().mimo_detect_cg(shp, hp, yp, code, float(n0), float(es), int(qam_bits), mode,
+                                   prec, llr.data_ptr(), _ptr(xh), _ptr(mu_t), _ptr(sn), None, 0,
+                                   _stream(stream)))
+    return res
+
+
+def precode_cg(H, T: torch.Tensor, beta: float, K: int, normalize: bool = False,
+               scalar_prec: str = "f32", qnorm: bool = True, out=None, stream=None):
+    """CG precoding q = H_u v with (G + beta I) v = t.  Returns (Q, qnorm)."""
+    hp, code, n, B, U = _channel(H)
+    _check_c64(T, "T")
+    if T.dim() != 3 or T.shape[0] != n or T.shape[1] != U:
+        raise ValueError("T must be (n_sc, U, S)")
+    S = T.shape[2]
+    dev = T.device
+    Q = torch.empty((n, B, S), dtype=torch.complex64, device=dev) if out is None else out
+    if tuple(Q.shape) != (n, B, S) or Q.dtype != torch.complex64:
+        raise ValueError("out must be complex64 (n_sc, B, S)")
+    qn = torch.empty((n, S), dtype=torch.float32, device=dev) if qnorm else None
+    prec = {"f32": L.MIMO_SCALAR_F32, "f64": L.MIMO_SCALAR_F64}[scalar_prec]
+    shp = L.shape(B, U, S, K, n)
+    L.check(L.lib().mimo_precode_cg(shp, hp, T.data_ptr(), code, float(beta), int(bool(normalize)),
+                                    prec, Q.data_ptr(), _ptr(qn), None, 0, _stream(stream)))
+    return Q, qn
+
+
+def workspace_bytes(B, U, S, K, n_sc, op: str = "detect", sinr_mode: str = "approx") -> int:
+    opc = {"gram_mf": L.MIMO_OP_GRAM_MF, "detect": L.MIMO_OP_DETECT,
+           "precode": L.MIMO_OP_PRECODE}[op]
+    mode = {"approx": L.MIMO_SINR_APPROX, "exact": L.MIMO_SINR_EXACT}[sinr_mode]
+    return int(L.lib().mimo_workspace_bytes(L.shape(B, U, S, K, n_sc), opc, mode))

@@ -1,0 +1,184 @@
+// Public C entry points (include/mimo_cg.h): argument validation, kernel
+// selection and launch.  No device memory is allocated here.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "../../include/mimo_cg.h"
+#include "kernels.hpp"
+
+namespace {
+
+thread_local char g_last_error[512] = "";
+
+int fail(int status, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+  return status;
+}
+
+int hip_status(hipError_t e, const char* what) {
+  if (e == hipSuccess) return MIMO_OK;
+  return fail(MIMO_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+int check_shape(const mimo_shape* s, bool need_k) {
+  if (!s) return fail(MIMO_EINVAL, "shape is NULL");
+  if (s->U < 1 || s->U > MIMO_MAX_USERS)
+    return fail(s->U > MIMO_MAX_USERS ? MIMO_EUNSUPPORTED : MIMO_EINVAL,
+                "U=%d outside [1, %d]", s->U, MIMO_MAX_USERS);
+  if (s->B < s->U) return fail(MIMO_EINVAL, "B=%d < U=%d", s->B, s->U);
+  if (s->B > MIMO_MAX_ANTENNAS)
+    return fail(MIMO_EUNSUPPORTED, "B=%d > %d", s->B, MIMO_MAX_ANTENNAS);
+  if (s->S < 1) return fail(MIMO_EINVAL, "S=%d < 1", s->S);
+  if (s->n_sc < 0) return fail(MIMO_EINVAL, "n_sc=%lld < 0", (long long)s->n_sc);
+  if (need_k && (s->K < 1 || s->K > 1024)) return fail(MIMO_EINVAL, "K=%d outside [1, 1024]", s->K);
+  return MIMO_OK;
+}
+
+int check_dtype(int in_dtype, int B) {
+  if (in_dtype != MIMO_C32 && in_dtype != MIMO_C16 && in_dtype != MIMO_CBF16)
+    return fail(MIMO_EINVAL, "in_dtype=%d unknown", in_dtype);
+  if (in_dtype != MIMO_C32 && (B % 8) != 0)
+    return fail(MIMO_EINVAL, "16-bit storage needs B %% 8 == 0 (B=%d)", B);
+  return MIMO_OK;
+}
+
+int check_ptr(const void* p, const char* name, bool required) {
+  if (!p) return required ? fail(MIMO_EINVAL, "%s is NULL", name) : MIMO_OK;
+  if (!aligned16(p)) return fail(MIMO_EINVAL, "%s is not 16-byte aligned", name);
+  return MIMO_OK;
+}
+
+#define CHECK(x)              \
+  do {                        \
+    const int st_ = (x);      \
+    if (st_ != MIMO_OK) return st_; \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char* mimo_version(void) { return "mimo_cg 0.1 gfx950"; }
+
+const char* mimo_last_error(void) { return g_last_error; }
+
+const char* mimo_status_string(int status) {
+  switch (status) {
+    case MIMO_OK: return "ok";
+    case MIMO_EINVAL: return "invalid argument";
+    case MIMO_EUNSUPPORTED: return "unsupported configuration";
+    case MIMO_EWORKSPACE: return "workspace missing or too small";
+    case MIMO_EHIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+size_t mimo_workspace_bytes(const mimo_shape* shape, int op, int sinr_mode) {
+  (void)shape;
+  (void)op;
+  (void)sinr_mode;
+  return 0;   // every kernel keeps its per-subcarrier state in LDS / registers
+}
+
+int mimo_gram_mf(const mimo_shape* shape, const void* H, const void* Y, int in_dtype, float reg,
+                 void* A, void* b, void* stream) {
+  g_last_error[0] = 0;
+  CHECK(check_shape(shape, false));
+  CHECK(check_dtype(in_dtype, shape->B));
+  if (!(reg >= 0.f) || !std::isfinite(reg)) return fail(MIMO_EINVAL, "reg=%g must be >= 0", reg);
+  CHECK(check_ptr(H, "H", true));
+  CHECK(check_ptr(Y, "Y", false));
+  CHECK(check_ptr(A, "A", true));
+  CHECK(check_ptr(b, "b", false));
+  if (b && !Y) return fail(MIMO_EINVAL, "b requested without Y");
+  if (shape->n_sc == 0) return MIMO_OK;
+  mimo::GramParams p{H, Y, shape->B, shape->U, shape->S, shape->n_sc, reg, (float2*)A, (float2*)b};
+  return hip_status(mimo::launch_gram_mf(p, in_dtype, (hipStream_t)stream), "gram_mf launch");
+}
+
+int mimo_detect_cg(const mimo_shape* shape, const void* H, const void* Y, int in_dtype, float n0,
+                   float es, int qam_bits, int sinr_mode, int scalar_prec, float* llr, void* xhat,
+                   float* mu, float* sinr, void* workspace, size_t workspace_bytes,
+                   void* stream) {
+  g_last_error[0] = 0;
+  CHECK(check_shape(shape, true));
+  CHECK(check_dtype(in_dtype, shape->B));
+  if (!(n0 > 0.f) || !std::isfinite(n0)) return fail(MIMO_EINVAL, "n0=%g must be > 0", n0);
+  if (!(es > 0.f) || !std::isfinite(es)) return fail(MIMO_EINVAL, "es=%g must be > 0", es);
+  if (qam_bits != 2 && qam_bits != 4 && qam_bits != 6 && qam_bits != 8)
+    return fail(MIMO_EUNSUPPORTED, "qam_bits=%d not in {2,4,6,8}", qam_bits);
+  if (sinr_mode != MIMO_SINR_APPROX && sinr_mode != MIMO_SINR_EXACT)
+    return fail(MIMO_EINVAL, "sinr_mode=%d unknown", sinr_mode);
+  if (scalar_prec != MIMO_SCALAR_F32 && scalar_prec != MIMO_SCALAR_F64)
+    return fail(MIMO_EINVAL, "scalar_prec=%d unknown", scalar_prec);
+  CHECK(check_ptr(H, "H", true));
+  CHECK(check_ptr(Y, "Y", true));
+  CHECK(check_ptr(llr, "llr", true));
+  CHECK(check_ptr(xhat, "xhat", false));
+  CHECK(check_ptr(mu, "mu", false));
+  CHECK(check_ptr(sinr, "sinr", false));
+  const size_t need = mimo_workspace_bytes(shape, MIMO_OP_DETECT, sinr_mode);
+  if (need > 0 && (!workspace || workspace_bytes < need))
+    return fail(MIMO_EWORKSPACE, "workspace needs %zu bytes", need);
+  if (shape->n_sc == 0) return MIMO_OK;
+  const int M = 1 << qam_bits;
+  mimo::DetectParams p{H, Y, shape->B, shape->U, shape->S, shape->K, shape->n_sc,
+                       n0 / es, n0, es, std::sqrt(es * 3.0f / (2.0f * (float)(M - 1))),
+                       llr, (float2*)xhat, mu, sinr};
+  const int f64 = scalar_prec == MIMO_SCALAR_F64;
+  hipError_t e = sinr_mode == MIMO_SINR_EXACT
+                     ? mimo::launch_detect_exact(p, in_dtype, f64, qam_bits, (hipStream_t)stream)
+                     : mimo::launch_detect_approx(p, in_dtype, f64, qam_bits, (hipStream_t)stream);
+  return hip_status(e, "detect_cg launch");
+}
+
+int mimo_precode_cg(const mimo_shape* shape, const void* H, const void* T, int in_dtype,
+                    float beta, int normalize, int scalar_prec, void* Q, float* qnorm,
+                    void* workspace, size_t workspace_bytes, void* stream) {
+  g_last_error[0] = 0;
+  CHECK(check_shape(shape, true));
+  CHECK(check_dtype(in_dtype, shape->B));
+  if (!(beta >= 0.f) || !std::isfinite(beta)) return fail(MIMO_EINVAL, "beta=%g must be >= 0", beta);
+  if (scalar_prec != MIMO_SCALAR_F32 && scalar_prec != MIMO_SCALAR_F64)
+    return fail(MIMO_EINVAL, "scalar_prec=%d unknown", scalar_prec);
+  CHECK(check_ptr(H, "H", true));
+  CHECK(check_ptr(T, "T", true));
+  CHECK(check_ptr(Q, "Q", true));
+  CHECK(check_ptr(qnorm, "qnorm", false));
+  const size_t need = mimo_workspace_bytes(shape, MIMO_OP_PRECODE, 0);
+  if (need > 0 && (!workspace || workspace_bytes < need))
+    return fail(MIMO_EWORKSPACE, "workspace needs %zu bytes", need);
+  if (shape->n_sc == 0) return MIMO_OK;
+  mimo::PrecodeParams p{H, (const float2*)T, shape->B, shape->U, shape->S, shape->K,
+                        shape->n_sc, beta, normalize ? 1 : 0, (float2*)Q, qnorm};
+  return hip_status(mimo::launch_precode(p, in_dtype, scalar_prec == MIMO_SCALAR_F64,
+                                         (hipStream_t)stream),
+                    "precode_cg launch");
+}
+
+int mimo_convert(const void* src, void* dst, int dst_dtype, int64_t n, int32_t R, int32_t C,
+                 void* stream) {
+  g_last_error[0] = 0;
+  if (dst_dtype != MIMO_C16 && dst_dtype != MIMO_CBF16)
+    return fail(MIMO_EINVAL, "dst_dtype=%d must be MIMO_C16 or MIMO_CBF16", dst_dtype);
+  if (n < 0 || R < 8 || (R % 8) != 0 || C < 1)
+    return fail(MIMO_EINVAL, "bad extents n=%lld R=%d C=%d (R must be a positive multiple of 8)",
+                (long long)n, R, C);
+  CHECK(check_ptr(src, "src", true));
+  CHECK(check_ptr(dst, "dst", true));
+  if (n == 0) return MIMO_OK;
+  return hip_status(mimo::launch_convert((const float2*)src, (uint16_t*)dst, dst_dtype, n, R, C,
+                                         (hipStream_t)stream),
+                    "convert launch");
+}
+
+}  // extern "C"

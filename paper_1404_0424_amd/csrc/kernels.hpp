@@ -1,0 +1,66 @@
+// Kernel parameter blocks and host-side launchers (C++ linkage, internal to
+// the library; the public entry points are in abi.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mimo {
+
+struct DetectParams {
+  const void* H;        // [n_sc][B][U] storage per in_dtype
+  const void* Y;        // [n_sc][B][S]
+  int B, U, S, K;
+  int64_t n_sc;
+  float reg;            // N0 / E_s
+  float n0;             // N0
+  float es;             // E_s
+  float scale;          // constellation level unit sqrt(3 E_s / (2 (M - 1)))
+  float* llr;           // [n_sc][U][S][m]
+  float2* xhat;         // [n_sc][U][S] or null
+  float* mu;            // [n_sc][U][S] or null
+  float* sinr;          // [n_sc][U][S] or null
+};
+
+struct PrecodeParams {
+  const void* H;        // [n_sc][B][U]
+  const float2* T;      // [n_sc][U][S]
+  int B, U, S, K;
+  int64_t n_sc;
+  float beta;
+  int normalize;
+  float2* Q;            // [n_sc][B][S]
+  float* qnorm;         // [n_sc][S] or null
+};
+
+struct GramParams {
+  const void* H;
+  const void* Y;        // may be null
+  int B, U, S;
+  int64_t n_sc;
+  float reg;
+  float2* A;            // [n_sc][U][U]
+  float2* b;            // [n_sc][U][S] or null
+};
+
+hipError_t launch_detect_approx(const DetectParams& p, int in_dtype, int scalar_f64, int m_bits,
+                                hipStream_t stream);
+hipError_t launch_detect_exact(const DetectParams& p, int in_dtype, int scalar_f64, int m_bits,
+                               hipStream_t stream);
+hipError_t launch_precode(const PrecodeParams& p, int in_dtype, int scalar_f64,
+                          hipStream_t stream);
+hipError_t launch_gram_mf(const GramParams& p, int in_dtype, hipStream_t stream);
+hipError_t launch_convert(const float2* src, uint16_t* dst, int dst_dtype, int64_t n, int R,
+                          int C, hipStream_t stream);
+
+// Grid for one-wavefront-per-subcarrier kernels (4 waves per block); the
+// kernels loop over subcarriers with a grid stride, so any n_sc is covered.
+inline unsigned int wave_grid(int64_t n_sc) {
+  int64_t blocks = (n_sc + 3) / 4;
+  const int64_t cap = 1 << 20;
+  if (blocks > cap) blocks = cap;
+  if (blocks < 1) blocks = 1;
+  return (unsigned int)blocks;
+}
+
+}  // namespace mimo

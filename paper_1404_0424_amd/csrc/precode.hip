@@ -1,0 +1,168 @@
+// Fused CG-P kernel (Sec. III-D): Gram on MFMA, K CG iterations on
+// (H_d H_d^H + beta I) v = t, then q = H_d^H v = H_u v on MFMA, with the
+// optional power normalization s = q / ||q|| (Sec. II-B).  One wavefront per
+// subcarrier.
+//
+// ||q||^2 = v^H H^H H v = v^H G v is formed in the CG layout from one more
+// mat-vec with A (v^H A v - beta ||v||^2), so each output tile is written
+// once, already scaled.
+#include "cg_core.hpp"
+#include "gram_phase.hpp"
+#include "kernels.hpp"
+
+namespace mimo {
+
+// One element H[b][u] of a subcarrier's channel as complex FP32.
+__device__ __forceinline__ float2 load_h(InC32, const void* Hn, int b, int u, int U) {
+  return ((const float2*)Hn)[(size_t)b * U + u];
+}
+__device__ __forceinline__ float2 load_h(InF16, const void* Hn, int b, int u, int U) {
+  const _Float16* p = (const _Float16*)Hn + ((size_t)(2 * (b >> 3)) * U + u) * 8 + (b & 7);
+  return make_float2((float)p[0], (float)p[(size_t)U * 8]);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t x) {
+  return __builtin_bit_cast(float, (uint32_t)x << 16);
+}
+__device__ __forceinline__ float2 load_h(InBF16, const void* Hn, int b, int u, int U) {
+  const uint16_t* p = (const uint16_t*)Hn + ((size_t)(2 * (b >> 3)) * U + u) * 8 + (b & 7);
+  return make_float2(bf16_to_f32(p[0]), bf16_to_f32(p[(size_t)U * 8]));
+}
+
+template <int W, typename IN, typename ST>
+__global__ __launch_bounds__(256, 2) void precode_kernel(PrecodeParams prm) {
+  constexpr int NU = 16 * W;
+  constexpr int AST = NU + 2;
+  __shared__ __align__(16) float2 A_s[kWavesPerBlock][NU * AST];
+  __shared__ __align__(16) float2 P_s[kWavesPerBlock][16 * AST];
+  __shared__ float G_s[kWavesPerBlock][NU];
+  __shared__ float N_s[kWavesPerBlock][16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  float2* As = A_s[wv];
+  float2* Ps = P_s[wv];
+  float* Gs = G_s[wv];
+  float* Ns = N_s[wv];
+  const int B = prm.B, U = prm.U, S = prm.S;
+  const float beta = prm.beta;
+
+  for (int64_t n = (int64_t)blockIdx.x * kWavesPerBlock + wv; n < prm.n_sc;
+       n += (int64_t)gridDim.x * kWavesPerBlock) {
+    const void* Hn = offset_sc(IN{}, prm.H, n, B, U);
+    for (int s0 = 0; s0 < S; s0 += 16) {
+      // ---- A = H_d H_d^H + beta I = G + beta I (Algorithm 1, initialization)
+      if (s0 == 0) {
+        GramAcc<W> acc;
+        acc.clear();
+        gram_mf<W, true, false>(IN{}, Hn, nullptr, B, U, S, 0, c, g, acc);
+        store_gram_lds<W>(acc, As, Gs, AST, beta, c, g);
+      }
+      // b = t
+      float2 b[W][4];
+#pragma unroll
+      for (int w = 0; w < W; ++w)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int u = 16 * w + c, s = s0 + 4 * g + j;
+          b[w][j] = (u < U && s < S) ? prm.T[((size_t)n * U + u) * S + s] : make_float2(0.f, 0.f);
+        }
+      wave_lds_sync();
+
+      CGState<W, ST> st;
+      cg_init<W, ST>(st, b);
+      for (int k = 0; k < prm.K; ++k) {
+        ST al[4], be[4];
+        cg_step<W, ST>(st, As, Ps, AST, c, g, al, be);
+      }
+
+      // ---- ||q||^2 = v^H G v ; V staged in Ps for the output contraction
+      stage_vec<W>(Ps, AST, c, g, st.v);
+      wave_lds_sync();
+      float2 e[W][4];
+      matvec<W>(As, Ps, AST, c, g, e);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        ST part = ST(0);
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          const float2 v = st.v[w][j];
+          part += (ST)v.x * (ST)e[w][j].x + (ST)v.y * (ST)e[w][j].y -
+                  (ST)beta * ((ST)v.x * (ST)v.x + (ST)v.y * (ST)v.y);
+        }
+        const ST qq = row_sum16(part);
+        if (c == 0) Ns[4 * g + j] = (float)(qq > ST(0) ? qq : ST(0));
+      }
+      wave_lds_sync();
+
+      // ---- q = H_u v (Algorithm 1 output) on MFMA: rows = antennas,
+      // columns = right-hand sides, k = users (k-group g takes users
+      // 16 w + 4 g + t, t = 0..3, so a lane reads 4 adjacent users of a row).
+      const int s = s0 + c;
+      const float nrm2 = Ns[c];
+      const float scl = prm.normalize ? (nrm2 > 0.f ? 1.0f / sqrtf(nrm2) : 0.f) : 1.0f;
+      for (int b0 = 0; b0 < B; b0 += 16) {
+        f4 qr = zero4(), qi = zero4();
+        const int brow = b0 + c;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          float2 hv[4], vv[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int u = 16 * w + 4 * g + t;
+            hv[t] = (brow < B && u < U) ? load_h(IN{}, Hn, brow, u, U) : make_float2(0.f, 0.f);
+            vv[t] = Ps[c * AST + u];
+          }
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            qr = mfma4(hv[t].x, vv[t].x, qr);
+            qr = mfma4(-hv[t].y, vv[t].y, qr);
+            qi = mfma4(hv[t].x, vv[t].y, qi);
+            qi = mfma4(hv[t].y, vv[t].x, qi);
+          }
+        }
+        if (s < S) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int bb = b0 + 4 * g + j;
+            if (bb < B) prm.Q[((size_t)n * B + bb) * S + s] = make_float2(qr[j] * scl, qi[j] * scl);
+          }
+        }
+      }
+      if (prm.qnorm && c == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int ss = s0 + 4 * g + j;
+          if (ss < S) prm.qnorm[(size_t)n * S + ss] = sqrtf(Ns[4 * g + j]);
+        }
+      }
+      wave_lds_sync();
+    }
+  }
+}
+
+template <int W, typename IN>
+static hipError_t launch_st(const PrecodeParams& p, int f64, hipStream_t stream) {
+  const dim3 grid(wave_grid(p.n_sc)), block(kWave * kWavesPerBlock);
+  if (f64)
+    hipLaunchKernelGGL((precode_kernel<W, IN, double>), grid, block, 0, stream, p);
+  else
+    hipLaunchKernelGGL((precode_kernel<W, IN, float>), grid, block, 0, stream, p);
+  return hipGetLastError();
+}
+
+template <int W>
+static hipError_t launch_in(const PrecodeParams& p, int in_dtype, int f64, hipStream_t stream) {
+  switch (in_dtype) {
+    case 0: return launch_st<W, InC32>(p, f64, stream);
+    case 1: return launch_st<W, InF16>(p, f64, stream);
+    case 2: return launch_st<W, InBF16>(p, f64, stream);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_precode(const PrecodeParams& p, int in_dtype, int scalar_f64,
+                          hipStream_t stream) {
+  if (p.U <= 16) return launch_in<1>(p, in_dtype, scalar_f64, stream);
+  return launch_in<2>(p, in_dtype, scalar_f64, stream);
+}
+
+}  // namespace mimo

@@ -1,0 +1,117 @@
+"""The C ABI on the CPU: the library loads, exports every entry point that
+include/mimo_cg.h declares, and rejects invalid arguments synchronously
+(before any HIP call).  No kernel runs here."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1404_0424_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mimo_cg.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mimo_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for need in ("mimo_gram_mf", "mimo_detect_cg", "mimo_precode_cg", "mimo_convert",
+                 "mimo_workspace_bytes", "mimo_status_string", "mimo_last_error"):
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    exported = set(re.findall(r"\bT (mimo_\w+)", out))
+    assert set(_declared()) <= exported
+
+
+def test_header_constants_match_binding():
+    src = open(HEADER).read()
+    assert f"#define MIMO_MAX_USERS {L.MIMO_MAX_USERS}" in src
+    for name in ("MIMO_C32", "MIMO_C16", "MIMO_CBF16", "MIMO_SINR_APPROX", "MIMO_SINR_EXACT",
+                 "MIMO_SCALAR_F32", "MIMO_SCALAR_F64", "MIMO_OK", "MIMO_EINVAL",
+                 "MIMO_EUNSUPPORTED", "MIMO_EWORKSPACE", "MIMO_EHIP"):
+        m = re.search(rf"\b{name}\s*=\s*(-?\d+)", src)
+        assert m and int(m.group(1)) == getattr(L, name), name
+
+
+# fake, aligned, never-dereferenced device addresses for validation tests
+P = 0x100000
+P2 = 0x200000
+
+
+def _detect(shape, **kw):
+    a = dict(H=P, Y=P, dt=0, n0=0.5, es=1.0, m=4, mode=0, prec=0, llr=P2, xhat=None, mu=None,
+             sinr=None)
+    a.update(kw)
+    return L.lib().mimo_detect_cg(shape, a["H"], a["Y"], a["dt"], a["n0"], a["es"], a["m"],
+                                  a["mode"], a["prec"], a["llr"], a["xhat"], a["mu"], a["sinr"],
+                                  None, 0, None)
+
+
+@pytest.mark.parametrize("shape,kw,status", [
+    ((32, 8, 1, 3, 4), dict(n0=0.0), L.MIMO_EINVAL),
+    ((32, 8, 1, 3, 4), dict(n0=float("nan")), L.MIMO_EINVAL),
+    ((32, 8, 1, 3, 4), dict(es=-1.0), L.MIMO_EINVAL),
+    ((32, 8, 1, 3, 4), dict(m=3), L.MIMO_EUNSUPPORTED),
+    ((32, 8, 1, 3, 4), dict(m=10), L.MIMO_EUNSUPPORTED),
+    ((32, 8, 1, 3, 4), dict(mode=2), L.MIMO_EINVAL),
+    ((32, 8, 1, 3, 4), dict(prec=7), L.MIMO_EINVAL),
+    ((32, 8, 1, 3, 4), dict(dt=5), L.MIMO_EINVAL),
+    ((30, 8, 1, 3, 4), dict(dt=1), L.MIMO_EINVAL),          # 16-bit needs B % 8 == 0
+    ((32, 8, 1, 3, 4), dict(H=None), L.MIMO_EINVAL),
+    ((32, 8, 1, 3, 4), dict(Y=None), L.MIMO_EINVAL),
+    ((32, 8, 1, 3, 4), dict(llr=None), L.MIMO_EINVAL),
+    ((32, 8, 1, 3, 4), dict(H=P + 8), L.MIMO_EINVAL),        # misaligned
+    ((32, 8, 1, 0, 4), {}, L.MIMO_EINVAL),                   # K < 1
+    ((32, 8, 0, 3, 4), {}, L.MIMO_EINVAL),                   # S < 1
+    ((4, 8, 1, 3, 4), {}, L.MIMO_EINVAL),                    # B < U
+    ((32, 0, 1, 3, 4), {}, L.MIMO_EINVAL),                   # U < 1
+    ((64, 33, 1, 3, 4), {}, L.MIMO_EUNSUPPORTED),            # U > MIMO_MAX_USERS
+    ((32, 8, 1, 3, -1), {}, L.MIMO_EINVAL),                  # n_sc < 0
+])
+def test_detect_rejects_invalid_arguments(shape, kw, status):
+    st = _detect(L.shape(*shape), **kw)
+    assert st == status
+    assert L.lib().mimo_last_error()
+
+
+def test_zero_subcarriers_is_a_noop():
+    assert _detect(L.shape(32, 8, 14, 3, 0)) == L.MIMO_OK
+
+
+def test_precode_gram_convert_validation():
+    lib = L.lib()
+    s = L.shape(32, 8, 2, 3, 4)
+    assert lib.mimo_precode_cg(s, P, P, 0, -0.1, 0, 0, P2, None, None, 0, None) == L.MIMO_EINVAL
+    assert lib.mimo_precode_cg(s, P, None, 0, 0.1, 0, 0, P2, None, None, 0, None) == L.MIMO_EINVAL
+    assert lib.mimo_precode_cg(s, P, P, 0, 0.1, 0, 0, None, None, None, 0, None) == L.MIMO_EINVAL
+    assert lib.mimo_precode_cg(L.shape(32, 8, 2, 3, 0), P, P, 0, 0.0, 1, 1, P2, None, None, 0,
+                               None) == L.MIMO_OK
+    assert lib.mimo_gram_mf(s, P, None, 0, -1.0, P2, None, None) == L.MIMO_EINVAL
+    assert lib.mimo_gram_mf(s, P, None, 0, 0.5, P2, P2, None) == L.MIMO_EINVAL   # b without Y
+    assert lib.mimo_gram_mf(L.shape(32, 8, 2, 3, 0), P, P, 0, 0.5, P2, P2, None) == L.MIMO_OK
+    assert lib.mimo_convert(P, P2, 0, 4, 32, 8, None) == L.MIMO_EINVAL          # dst not 16-bit
+    assert lib.mimo_convert(P, P2, 1, 4, 30, 8, None) == L.MIMO_EINVAL          # R % 8
+    assert lib.mimo_convert(P, P2, 2, 0, 32, 8, None) == L.MIMO_OK
+    assert lib.mimo_workspace_bytes(s, 1, 0) == 0
+
+
+def test_status_strings():
+    lib = L.lib()
+    for st in (0, -1, -2, -3, -4):
+        assert lib.mimo_status_string(st)
+    assert b"unknown" in lib.mimo_status_string(99)
+    assert lib.mimo_version().startswith(b"mimo_cg")

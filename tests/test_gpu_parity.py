@@ -1,0 +1,262 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
+the same seeded inputs.  Sizes span several 16-user / 16-rhs tiles, the
+4-wave blocks with a ragged last block, ragged antenna counts, more than 16
+right-hand sides (two rhs chunks), and the degenerate cases."""
+import zlib
+
+import numpy as np
+import pytest
+
+from oracle import mimo_oracle as O
+from paper_1404_0424_amd import workload as W
+
+from _parity import (TOL_L, TOL_X, blocked16, dev, host, llr_err, rel_err_scalar,
+                     rel_err_vec)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1404_0424_amd import _lib
+    _lib.lib()       # fail loudly if the library is missing
+
+
+def api():
+    from paper_1404_0424_amd import api as A
+    return A
+
+
+# (name, n_sc, B, U, S, m, K, snr_db, channel)
+DETECT_CASES = [
+    ("small_32x8", 64, 32, 8, 1, 4, 3, 10.0, "iid"),
+    ("plain_128x8_0dB", 48, 128, 8, 14, 6, 3, 0.0, "iid"),
+    ("plain_128x8_10dB", 48, 128, 8, 14, 6, 3, 10.0, "iid"),
+    ("plain_128x8_20dB", 48, 128, 8, 14, 6, 3, 20.0, "iid"),
+    ("mixed_128x16", 64, 128, 16, 14, 6, 4, 15.0, "iid"),
+    ("mixed_128x32", 40, 128, 32, 14, 6, 4, 15.0, "iid"),
+    ("corr_256x32", 24, 256, 32, 14, 8, 6, 25.0, "kronecker"),
+    ("ragged_30x5_S17", 37, 30, 5, 17, 2, 5, 5.0, "iid"),
+    ("ragged_20x20", 13, 20, 20, 3, 4, 7, 12.0, "iid"),
+    ("single_user", 9, 6, 1, 2, 8, 1, 10.0, "iid"),
+    # square B = U, kappa(A) ~ 9.  The approximate tracker evaluates the
+    # degree-K CG polynomial at d_i; near K = U on a square channel that
+    # amplifies the rounding of alpha_k, beta_k (FP32 scalars alone move mu by
+    # ~2.6% at K = U = 16), so K = U is checked in exact mode below.
+    ("square_16x16", 11, 16, 16, 5, 4, 4, 15.0, "iid"),
+    # converges to round-off before K: exercises the zero-residual guard
+    ("converged_16x16_0dB", 11, 16, 16, 5, 4, 16, 0.0, "iid"),
+]
+
+
+def _uplink(case, seed=0):
+    name, n, B, U, S, m, K, snr, ch = case
+    rng = np.random.default_rng(zlib.crc32(name.encode()) + seed)
+    return W.uplink_frame(rng, n, B, U, S, m, snr, channel=ch, rho_bs=0.5, rho_ue=0.2)
+
+
+@pytest.mark.parametrize("case", DETECT_CASES, ids=[c[0] for c in DETECT_CASES])
+@pytest.mark.parametrize("scalar", ["f32", "f64"])
+def test_detect_approx_parity(case, scalar):
+    name, n, B, U, S, m, K, snr, ch = case
+    f = _uplink(case)
+    out = api().detect_cg(dev(f.H), dev(f.Y), f.n0, f.es, K, m, "approx", scalar,
+                          xhat=True, mu=True, sinr=True)
+    torch.cuda.synchronize()
+    ref = O.detect_cg(f.H, f.Y, f.n0, f.es, K, m, "approx")
+    ex = rel_err_vec(host(out["xhat"]), ref["xhat"], axis=1)
+    el = llr_err(host(out["llr"]), ref["llr"])
+    emu = rel_err_scalar(host(out["mu"]), ref["mu"])
+    erho = rel_err_scalar(host(out["sinr"]), ref["rho"])
+    print(f"{name} {scalar}: eps_x={ex:.2e} eps_L={el:.2e} eps_mu={emu:.2e} eps_rho={erho:.2e}")
+    assert ex <= TOL_X and el <= TOL_L and emu <= TOL_X and erho <= 1e-5
+
+
+EXACT_CASES = [
+    ("small_32x8_K3", 16, 32, 8, 1, 4, 3, 10.0, "iid"),
+    ("small_32x8_KU", 16, 32, 8, 3, 4, 8, 10.0, "iid"),
+    ("u16_K4", 8, 64, 16, 14, 6, 4, 15.0, "iid"),
+    ("u20_S17", 5, 40, 20, 17, 2, 6, 8.0, "iid"),
+    ("u32_corr", 4, 128, 32, 3, 8, 6, 25.0, "kronecker"),
+    ("square_16x16_KU", 6, 16, 16, 3, 4, 16, 15.0, "iid"),
+]
+
+
+@pytest.mark.parametrize("case", EXACT_CASES, ids=[c[0] for c in EXACT_CASES])
+def test_detect_exact_parity(case):
+    name, n, B, U, S, m, K, snr, ch = case
+    f = _uplink(case, 1)
+    out = api().detect_cg(dev(f.H), dev(f.Y), f.n0, f.es, K, m, "exact", "f64",
+                          xhat=True, mu=True, sinr=True)
+    torch.cuda.synchronize()
+    ref = O.detect_cg(f.H, f.Y, f.n0, f.es, K, m, "exact")
+    ex = rel_err_vec(host(out["xhat"]), ref["xhat"], axis=1)
+    el = llr_err(host(out["llr"]), ref["llr"])
+    emu = rel_err_scalar(host(out["mu"]), ref["mu"])
+    erho = rel_err_scalar(host(out["sinr"]), ref["rho"])
+    print(f"{name}: eps_x={ex:.2e} eps_L={el:.2e} eps_mu={emu:.2e} eps_rho={erho:.2e}")
+    assert ex <= TOL_X and el <= TOL_L and emu <= TOL_X and erho <= 1e-3
+
+
+def test_exact_mode_at_K_equals_U_matches_cholesky_mmse():
+    f = W.uplink_frame(np.random.default_rng(77), 8, 32, 8, 2, 4, 12.0)
+    out = api().detect_cg(dev(f.H), dev(f.Y), f.n0, f.es, 8, 4, "exact", "f64",
+                          xhat=True, mu=True, sinr=True)
+    ex = O.mmse_exact(f.H, f.Y, f.n0, f.es)
+    assert rel_err_vec(host(out["xhat"]), ex["xhat"], axis=1) <= TOL_X
+    assert rel_err_scalar(host(out["mu"]), ex["mu"][:, :, None] * np.ones(2)) <= TOL_X
+    assert rel_err_scalar(host(out["sinr"]), ex["rho"][:, :, None] * np.ones(2)) <= 1e-3
+
+
+def test_detect_zero_receive_vectors():
+    f = W.uplink_frame(np.random.default_rng(5), 12, 32, 8, 6, 4, 10.0)
+    Y = f.Y.copy()
+    Y[3] = 0
+    Y[7, :, 2] = 0
+    for mode in ("approx", "exact"):
+        out = api().detect_cg(dev(f.H), dev(Y), f.n0, f.es, 3, 4, mode, "f32", xhat=True, mu=True,
+                              sinr=True)
+        ref = O.detect_cg(f.H, Y, f.n0, f.es, 3, 4, mode)
+        L = host(out["llr"])
+        assert np.all(np.isfinite(L))
+        assert np.all(host(out["xhat"])[3] == 0) and np.all(host(out["mu"])[3] == 0)
+        assert llr_err(L, ref["llr"]) <= TOL_L
+        assert rel_err_scalar(host(out["sinr"]), ref["rho"]) <= 1e-3
+
+
+def test_detect_is_deterministic():
+    f = _uplink(DETECT_CASES[4])
+    H, Y = dev(f.H), dev(f.Y)
+    a = host(api().detect_cg(H, Y, f.n0, f.es, 4, 6)["llr"])
+    b = host(api().detect_cg(H, Y, f.n0, f.es, 4, 6)["llr"])
+    assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------- precoding
+
+PRECODE_CASES = [
+    ("small_32x8", 64, 32, 8, 1, 3, 10.0),
+    ("plain_128x8", 48, 128, 8, 14, 3, 10.0),
+    ("mixed_128x16", 48, 128, 16, 14, 4, 15.0),
+    ("mixed_128x32", 24, 128, 32, 14, 4, 15.0),
+    ("corr_256x32", 16, 256, 32, 14, 6, 25.0),
+    ("ragged_30x5_S17", 37, 30, 5, 17, 5, 5.0),
+    ("zf_32x8_KU", 16, 32, 8, 3, 8, None),
+]
+
+
+@pytest.mark.parametrize("case", PRECODE_CASES, ids=[c[0] for c in PRECODE_CASES])
+@pytest.mark.parametrize("normalize", [False, True])
+def test_precode_parity(case, normalize):
+    name, n, B, U, S, K, snr = case
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    ch = "kronecker" if "corr" in name else "iid"
+    d = W.downlink_frame(rng, n, B, U, S, 6, snr, channel=ch, rho_bs=0.5, rho_ue=0.2)
+    Q, qn = api().precode_cg(dev(d.H), dev(d.T), d.beta, K, normalize,
+                             "f64" if "corr" in name else "f32")
+    ref = O.precode_cg(d.H, d.T, d.beta, K, normalize)
+    eq = rel_err_vec(host(Q), ref["Q"], axis=1)
+    en = rel_err_scalar(host(qn), ref["qnorm"])
+    print(f"{name} norm={normalize}: eps_q={eq:.2e} eps_qnorm={en:.2e}")
+    assert eq <= TOL_X and en <= TOL_X
+    if snr is None:     # zero forcing inverts the channel: H_d q = t
+        HdQ = np.conj(np.swapaxes(d.H, 1, 2)) @ host(Q).astype(np.complex128)
+        if normalize:
+            HdQ = HdQ * ref["qnorm"][:, None, :]
+        assert rel_err_vec(HdQ, d.T, axis=1) <= 1e-3
+
+
+# ---------------------------------------------------------------- Gram / MF
+
+@pytest.mark.parametrize("B,U,S,n", [(32, 8, 1, 64), (128, 16, 14, 37), (128, 32, 14, 9),
+                                     (30, 5, 17, 11), (6, 1, 3, 5), (256, 32, 33, 6)])
+def test_gram_mf_parity(B, U, S, n):
+    rng = np.random.default_rng(B * 1000 + U)
+    f = W.uplink_frame(rng, n, B, U, S, 4, 10.0)
+    A, b = api().gram_mf(dev(f.H), dev(f.Y), reg=0.37)
+    A0 = O.regularized_gram(f.H, 0.37)
+    b0 = O.matched_filter(f.H, f.Y)
+    Ag = host(A)
+    eA = np.max(np.linalg.norm(Ag - A0, axis=(1, 2)) / np.linalg.norm(A0, axis=(1, 2)))
+    eb = rel_err_vec(host(b), b0, axis=1)
+    assert eA <= 2e-6 and eb <= 2e-6, (eA, eb)
+    # Hermitian by construction: mirrored upper triangle, real diagonal
+    assert np.array_equal(Ag, np.conj(np.swapaxes(Ag, 1, 2)))
+    A2, b2 = api().gram_mf(dev(f.H), None, reg=0.0)
+    assert b2 is None
+    assert np.max(np.abs(host(A2) - O.gram(f.H))) <= 2e-6 * np.max(np.abs(A0))
+
+
+# ---------------------------------------------------------------- 16-bit ingest
+
+@pytest.mark.parametrize("dt", ["f16", "bf16"])
+def test_convert_is_bit_exact_rne(dt):
+    rng = np.random.default_rng(9)
+    X = (rng.standard_normal((7, 40, 13)) + 1j * rng.standard_normal((7, 40, 13))) * 0.3
+    X[0, 0, 0] = 1 + 2.0 ** -8 + 1j * (1 + 2.0 ** -11)      # ties
+    P = api().convert(dev(X), dt)
+    q = O.quantize_f16(X) if dt == "f16" else O.quantize_bf16(X)
+    assert np.array_equal(host(P.data), blocked16(q))
+
+
+@pytest.mark.parametrize("dt", ["f16", "bf16"])
+@pytest.mark.parametrize("case", [DETECT_CASES[0], DETECT_CASES[4], DETECT_CASES[5]],
+                         ids=["small_32x8", "mixed_128x16", "mixed_128x32"])
+def test_detect_16bit_matches_oracle_on_quantized_inputs(dt, case):
+    name, n, B, U, S, m, K, snr, ch = case
+    f = _uplink(case, 2)
+    A = api()
+    H16, Y16 = A.convert(dev(f.H), dt), A.convert(dev(f.Y), dt)
+    out = A.detect_cg(H16, Y16, f.n0, f.es, K, m, "approx", xhat=True)
+    deq = O.dequantize_f16 if dt == "f16" else O.dequantize_bf16
+    qz = O.quantize_f16 if dt == "f16" else O.quantize_bf16
+    Hq, Yq = deq(qz(f.H)), deq(qz(f.Y))
+    ref_q = O.detect_cg(Hq, Yq, f.n0, f.es, K, m, "approx")
+    ex = rel_err_vec(host(out["xhat"]), ref_q["xhat"], axis=1)
+    el = llr_err(host(out["llr"]), ref_q["llr"])
+    ref = O.detect_cg(f.H, f.Y, f.n0, f.es, K, m, "approx")
+    ex_tot = rel_err_vec(host(out["xhat"]), ref["xhat"], axis=1)
+    el_tot = llr_err(host(out["llr"]), ref["llr"])
+    print(f"{name} {dt}: vs quantized-input oracle eps_x={ex:.2e} eps_L={el:.2e}; "
+          f"vs full-precision oracle eps_x={ex_tot:.2e} eps_L={el_tot:.2e}")
+    assert ex <= TOL_X and el <= TOL_L
+    assert ex_tot <= (5e-3 if dt == "f16" else 3e-2)
+
+
+@pytest.mark.parametrize("dt", ["f16", "bf16"])
+def test_precode_16bit_matches_oracle_on_quantized_channel(dt):
+    rng = np.random.default_rng(41)
+    d = W.downlink_frame(rng, 24, 128, 16, 14, 6, 15.0)
+    A = api()
+    Q, qn = A.precode_cg(A.convert(dev(d.H), dt), dev(d.T), d.beta, 4, True)
+    deq = O.dequantize_f16 if dt == "f16" else O.dequantize_bf16
+    qz = O.quantize_f16 if dt == "f16" else O.quantize_bf16
+    ref = O.precode_cg(deq(qz(d.H)), d.T, d.beta, 4, True)
+    assert rel_err_vec(host(Q), ref["Q"], axis=1) <= TOL_X
+    assert rel_err_scalar(host(qn), ref["qnorm"]) <= TOL_X
+
+
+# ---------------------------------------------------------------- full size, sampled
+
+@pytest.mark.parametrize("wl,frames", [("mixed_128x16", 2), ("corr_256x32", 1)])
+def test_full_size_sampled(wl, frames):
+    """At the benchmark's full sizes and launch configuration: run whole
+    frames on the GPU, check a sample of subcarriers against the oracle."""
+    w = W.WORKLOADS[wl]
+    rng = W.rng_for(3 if wl.startswith("mixed") else 5, 0)
+    f = W.uplink_frame(rng, w.n_sc * frames, w.B, w.U, w.S, w.m, w.snr_db[0], channel=w.channel,
+                       rho_bs=w.rho_bs, rho_ue=w.rho_ue)
+    sc = "f64" if w.scalar_f64 else "f32"
+    out = api().detect_cg(dev(f.H), dev(f.Y), f.n0, f.es, w.K, w.m, "approx", sc, xhat=True)
+    idx = np.sort(np.random.default_rng(1).choice(f.H.shape[0], 24, replace=False))
+    idx[-1] = f.H.shape[0] - 1            # the last subcarrier of the batch
+    ref = O.detect_cg(f.H[idx], f.Y[idx], f.n0, f.es, w.K, w.m, "approx")
+    ex = rel_err_vec(host(out["xhat"])[idx], ref["xhat"], axis=1)
+    el = llr_err(host(out["llr"])[idx], ref["llr"])
+    print(f"{wl} full size sampled: eps_x={ex:.2e} eps_L={el:.2e}")
+    assert ex <= TOL_X and el <= TOL_L
+    assert np.all(np.isfinite(host(out["llr"])))
