@@ -54,6 +54,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 512 MiB device copy 3x (reference for HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -116,7 +118,25 @@ def main():
             f"precode {pre * 1e3:.3f} ms)")
         return wall, det, pre
 
+    def kernel_time(fn, reps=20):
+        """Average duration of back-to-back launches between two events on
+        the stream the kernels run on (torch's current stream)."""
+        fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps / 1e3
+
     wall, det_s, pre_s = timed(H, Y, "complex64")
+    det_s = kernel_time(lambda: api.detect_cg(H, Y, n0, es, K, m, "approx", scalar,
+                                              out={"llr": llr}))
+    pre_s = kernel_time(lambda: api.precode_cg(H, T, beta, K, normalize=True, scalar_prec=scalar,
+                                               qnorm=False, out=Q))
+    log(f"back-to-back: detect {det_s * 1e3:.3f} ms, precode {pre_s * 1e3:.3f} ms per launch")
     solves = 2 * n * wl.S                      # uplink + downlink CG solves per step
     llr_bits = n * wl.S * wl.U * wl.m
     det_bytes = detect_bytes_per_sc(wl.B, wl.U, wl.S, wl.m) * n
@@ -188,7 +208,22 @@ def main():
                                       "p99": float(np.percentile(lat, 99)),
                                       "what": "one frame, UL detect + DL precode, idle GPU"}
 
+    if args.copy_calibration:
+        nbytes = 512 << 20
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_calibration_bytes"] = nbytes
+        del src, dst
+
     if not args.no_cpu_baseline:
+        # the complex64 outputs (the variants above reused the buffers)
+        api.detect_cg(H, Y, n0, es, K, m, "approx", scalar, out={"llr": llr})
+        api.precode_cg(H, T, beta, K, normalize=True, scalar_prec=scalar, qnorm=False, out=Q)
+        torch.cuda.synchronize()
         result["cpu_baseline"] = cpu_baseline(up, dn, wl, llr, Q, args.cpu_seconds)
 
     print(json.dumps(result), flush=True)

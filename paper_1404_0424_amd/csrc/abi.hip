@@ -131,8 +131,9 @@ int mimo_detect_cg(const mimo_shape* shape, const void* H, const void* Y, int in
     return fail(MIMO_EWORKSPACE, "workspace needs %zu bytes", need);
   if (shape->n_sc == 0) return MIMO_OK;
   const int M = 1 << qam_bits;
+  const float scale = std::sqrt(es * 3.0f / (2.0f * (float)(M - 1)));
   mimo::DetectParams p{H, Y, shape->B, shape->U, shape->S, shape->K, shape->n_sc,
-                       n0 / es, n0, es, std::sqrt(es * 3.0f / (2.0f * (float)(M - 1))),
+                       n0 / es, n0, es, scale, 1.0f / scale,
                        llr, (float2*)xhat, mu, sinr};
   const int f64 = scalar_prec == MIMO_SCALAR_F64;
   hipError_t e = sinr_mode == MIMO_SINR_EXACT

@@ -3,15 +3,21 @@
 // Lane (c, g) = lane % 16, lane / 16 owns users u = 16 w + c (w < W) and
 // right-hand sides s = s0 + 4 g + j (j < 4): the 16 lanes of a DPP row hold
 // one right-hand side's vector, so inner products over users are a row sum
-// (four DPP steps) plus a sum over w inside the lane.  A is in the wave's
-// LDS region; the search direction p is exchanged through LDS for the
-// mat-vec e = A p.  Vectors are FP32; the scalar recurrences (||r||^2,
-// p^H e, alpha, beta) use ST (float or double).
+// (four DPP steps) plus a sum over w inside the lane.  Vectors are FP32; the
+// scalar recurrences (||r||^2, p^H e, alpha, beta) use ST (float or double).
+//
+// The mat-vec e = A p of all right-hand sides at once is the product
+// E = A P, computed on MFMA in transposed form E^T = P^T A^T (rows =
+// right-hand sides, columns = users) so that the result lands in the lane
+// layout above.  P is exchanged through LDS as P[user][rhs]; the A^T operand
+// (A[16 w + c][k] for the lane's k-group) stays in registers.
 #pragma once
 
 #include "common.hpp"
 
 namespace mimo {
+
+constexpr int kPST = 18;   // LDS row stride (complex) of P[user][rhs]
 
 template <int W, typename ST>
 struct CGState {
@@ -33,8 +39,44 @@ struct Tracker {
   }
 };
 
+// A^T operand of the mat-vec: a[wc][t] = A[16 wc + c][4 t + g].
+template <int W>
+struct AOperand {
+  float2 a[W][4 * W];
+  __device__ void load(const float2* __restrict__ As, int ast, int c, int g) {
+#pragma unroll
+    for (int wc = 0; wc < W; ++wc)
+#pragma unroll
+      for (int t = 0; t < 4 * W; ++t) a[wc][t] = As[(16 * wc + c) * ast + 4 * t + g];
+  }
+};
+
+// Scalar division of the recurrences.  FP32 uses the hardware reciprocal; it
+// is only reached for operands >= FLT_MIN (see live_floor), where the
+// reciprocal is finite and within 1 ulp.  FP64 divides exactly.
 template <typename ST>
-__device__ __forceinline__ ST to_st(float x) { return (ST)x; }
+__device__ __forceinline__ ST div_fast(ST a, ST b) { return a / b; }
+template <>
+__device__ __forceinline__ float div_fast<float>(float a, float b) {
+  return a * __builtin_amdgcn_rcpf(b);
+}
+
+// A right-hand side is live while ||r||^2 and p^H e are at least this value.
+// FP64: any positive value (freeze only on an exact zero, as Algorithm 1
+// leaves beta undefined there).  FP32: the smallest normal float -- past
+// convergence the recursive residual keeps shrinking geometrically into
+// denormals, where 1/x overflows; freezing there changes v by less than
+// FP32 round-off.
+template <typename ST>
+__device__ __forceinline__ bool live_floor(ST rr, ST pe);
+template <>
+__device__ __forceinline__ bool live_floor<double>(double rr, double pe) {
+  return rr > 0.0 && pe > 0.0;
+}
+template <>
+__device__ __forceinline__ bool live_floor<float>(float rr, float pe) {
+  return rr >= __FLT_MIN__ && pe >= __FLT_MIN__;
+}
 
 template <int W, typename ST>
 __device__ __forceinline__ void cg_init(CGState<W, ST>& st, const float2 (&b)[W][4]) {
@@ -52,53 +94,54 @@ __device__ __forceinline__ void cg_init(CGState<W, ST>& st, const float2 (&b)[W]
   }
 }
 
-// e[w][j] = (A x)_{16 w + c} for the 4 right-hand sides of this lane, with x
-// staged in Ps (row = rhs within the chunk, column = user).
+// Stage x (lane layout) to LDS as X[user][rhs].
 template <int W>
-__device__ __forceinline__ void matvec(const float2* __restrict__ As, const float2* __restrict__ Ps,
-                                       int ast, int c, int g, float2 (&e)[W][4]) {
-  constexpr int NU = 16 * W;
+__device__ __forceinline__ void stage_vec(float2* __restrict__ Ps, int c, int g,
+                                          const float2 (&x)[W][4]) {
 #pragma unroll
-  for (int w = 0; w < W; ++w)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) e[w][j] = make_float2(0.f, 0.f);
-#pragma unroll 2
-  for (int k = 0; k < NU; k += 2) {
-    float4 a[W], x[4];
-#pragma unroll
-    for (int w = 0; w < W; ++w) a[w] = *(const float4*)&As[(16 * w + c) * ast + k];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) x[j] = *(const float4*)&Ps[(4 * g + j) * ast + k];
-#pragma unroll
-    for (int w = 0; w < W; ++w)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        cfma(e[w][j], make_float2(a[w].x, a[w].y), make_float2(x[j].x, x[j].y));
-        cfma(e[w][j], make_float2(a[w].z, a[w].w), make_float2(x[j].z, x[j].w));
-      }
+  for (int w = 0; w < W; ++w) {
+    float4* d = (float4*)&Ps[(16 * w + c) * kPST + 4 * g];
+    d[0] = make_float4(x[w][0].x, x[w][0].y, x[w][1].x, x[w][1].y);
+    d[1] = make_float4(x[w][2].x, x[w][2].y, x[w][3].x, x[w][3].y);
   }
 }
 
+// e = A x for the staged X: E^T = X^T A^T on 16x16x4 MFMA, k over users.
 template <int W>
-__device__ __forceinline__ void stage_vec(float2* __restrict__ Ps, int ast, int c, int g,
-                                          const float2 (&x)[W][4]) {
+__device__ __forceinline__ void matvec_mfma(const AOperand<W>& at, const float2* __restrict__ Ps,
+                                            int c, int g, float2 (&e)[W][4]) {
+  f4 er[W], ei[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) { er[w] = zero4(); ei[w] = zero4(); }
+#pragma unroll
+  for (int t = 0; t < 4 * W; ++t) {
+    const float2 pk = Ps[(4 * t + g) * kPST + c];     // X[k = 4 t + g][rhs c]
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const float2 a = at.a[w][t];
+      er[w] = mfma4(pk.x, a.x, er[w]);
+      ei[w] = mfma4(pk.x, a.y, ei[w]);
+      er[w] = mfma4(-pk.y, a.y, er[w]);
+      ei[w] = mfma4(pk.y, a.x, ei[w]);
+    }
+  }
 #pragma unroll
   for (int w = 0; w < W; ++w)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) Ps[(4 * g + j) * ast + 16 * w + c] = x[w][j];
+    for (int j = 0; j < 4; ++j) e[w][j] = make_float2(er[w][j], ei[w][j]);
 }
 
 // One iteration of Algorithm 1 (loop body) for the lane's 4 right-hand
 // sides.  alpha/beta are returned for the trackers.  A right-hand side whose
 // residual norm is zero (converged or b = 0) freezes: alpha = beta = 0.
 template <int W, typename ST>
-__device__ __forceinline__ void cg_step(CGState<W, ST>& st, const float2* __restrict__ As,
-                                        float2* __restrict__ Ps, int ast, int c, int g,
-                                        ST (&alpha)[4], ST (&beta)[4]) {
-  stage_vec<W>(Ps, ast, c, g, st.p);
+__device__ __forceinline__ void cg_step(CGState<W, ST>& st, const AOperand<W>& at,
+                                        float2* __restrict__ Ps, int c, int g, ST (&alpha)[4],
+                                        ST (&beta)[4]) {
+  stage_vec<W>(Ps, c, g, st.p);
   wave_lds_sync();
   float2 e[W][4];
-  matvec<W>(As, Ps, ast, c, g, e);                 // e_{k-1} = A p_{k-1}
+  matvec_mfma<W>(at, Ps, c, g, e);                 // e_{k-1} = A p_{k-1}
   wave_lds_sync();
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -107,8 +150,8 @@ __device__ __forceinline__ void cg_step(CGState<W, ST>& st, const float2* __rest
     for (int w = 0; w < W; ++w)
       part += (ST)st.p[w][j].x * (ST)e[w][j].x + (ST)st.p[w][j].y * (ST)e[w][j].y;
     const ST pe = row_sum16(part);                 // Re(p^H e)
-    const bool live = st.rr[j] > ST(0) && pe > ST(0);
-    alpha[j] = live ? st.rr[j] / pe : ST(0);
+    const bool live = live_floor<ST>(st.rr[j], pe);
+    alpha[j] = live ? div_fast<ST>(st.rr[j], pe) : ST(0);
     const float af = (float)alpha[j];
     ST part2 = ST(0);
 #pragma unroll
@@ -120,7 +163,7 @@ __device__ __forceinline__ void cg_step(CGState<W, ST>& st, const float2* __rest
       part2 += (ST)st.r[w][j].x * (ST)st.r[w][j].x + (ST)st.r[w][j].y * (ST)st.r[w][j].y;
     }
     const ST rr_new = row_sum16(part2);
-    beta[j] = live ? rr_new / st.rr[j] : ST(0);
+    beta[j] = live ? div_fast<ST>(rr_new, st.rr[j]) : ST(0);
     const float bf = (float)beta[j];
 #pragma unroll
     for (int w = 0; w < W; ++w) {

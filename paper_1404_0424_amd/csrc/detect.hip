@@ -11,11 +11,12 @@ namespace mimo {
 template <int W, typename IN, typename ST, int M_BITS>
 __global__ __launch_bounds__(256, 2) void detect_approx_kernel(DetectParams prm) {
   constexpr int NU = 16 * W;
-  constexpr int AST = NU + 2;   // LDS row stride (complex), conflict-free b128 rows
+  constexpr int AST = NU + 2;   // LDS row stride (complex) of A
   __shared__ __align__(16) float2 A_s[kWavesPerBlock][NU * AST];
-  __shared__ __align__(16) float2 P_s[kWavesPerBlock][16 * AST];
+  __shared__ __align__(16) float2 P_s[kWavesPerBlock][NU * kPST];
   __shared__ float G_s[kWavesPerBlock][NU];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const int c = lane & 15, g = lane >> 4;
   float2* As = A_s[wv];
   float2* Ps = P_s[wv];
@@ -26,17 +27,22 @@ __global__ __launch_bounds__(256, 2) void detect_approx_kernel(DetectParams prm)
        n += (int64_t)gridDim.x * kWavesPerBlock) {
     const void* Hn = offset_sc(IN{}, prm.H, n, B, U);
     const void* Yn = offset_sc(IN{}, prm.Y, n, B, S);
+    AOperand<W> at;
+    float d[W];
     for (int s0 = 0; s0 < S; s0 += 16) {
       // ---- A = H^H H + (N0/E_s) I and b = H^H y (Algorithm 1, initialization)
       GramAcc<W> acc;
       acc.clear();
       if (s0 == 0) {
         gram_mf<W, true, true>(IN{}, Hn, Yn, B, U, S, s0, c, g, acc);
-        store_gram_lds<W>(acc, As, Gs, AST, prm.reg, c, g);
+        store_gram_lds<W>(acc, As, Gs, (float*)Ps, AST, prm.reg, c, g);
+        wave_lds_sync();
+        at.load(As, AST, c, g);
+#pragma unroll
+        for (int w = 0; w < W; ++w) d[w] = As[(16 * w + c) * AST + 16 * w + c].x;
       } else {
         gram_mf<W, false, true>(IN{}, Hn, Yn, B, U, S, s0, c, g, acc);
       }
-      wave_lds_sync();
 
       // ---- K iterations of Algorithm 1 with the tracker of eq. (13)
       float2 b[W][4];
@@ -48,12 +54,9 @@ __global__ __launch_bounds__(256, 2) void detect_approx_kernel(DetectParams prm)
       cg_init<W, ST>(st, b);
       Tracker<W, ST> tk;
       tk.init();
-      float d[W];
-#pragma unroll
-      for (int w = 0; w < W; ++w) d[w] = As[(16 * w + c) * AST + 16 * w + c].x;
       for (int k = 0; k < prm.K; ++k) {
         ST al[4], be[4];
-        cg_step<W, ST>(st, As, Ps, AST, c, g, al, be);
+        cg_step<W, ST>(st, at, Ps, c, g, al, be);
         tracker_step<W, ST>(tk, d, al, be);
       }
 
@@ -70,9 +73,12 @@ __global__ __launch_bounds__(256, 2) void detect_approx_kernel(DetectParams prm)
           if (s >= S) continue;
           const float mu = (float)(tk.tv[w][j] * (ST)Guu);
           const float2 x = st.v[w][j];
-          const float2 z = (mu != 0.f) ? make_float2(x.x / mu, x.y / mu) : make_float2(0.f, 0.f);
+          // |mu| < FLT_MIN only when the right-hand side froze at (near) zero:
+          // z = 0 as for b = 0.
+          const float imu = fabsf(mu) >= __FLT_MIN__ ? __builtin_amdgcn_rcpf(mu) : 0.f;
+          const float2 z = make_float2(x.x * imu, x.y * imu);
           float out[M_BITS];
-          llr_maxlog<M_BITS>(z, rho, prm.scale, out);
+          llr_maxlog<M_BITS>(z, rho, prm.scale, prm.inv_scale, out);
           const size_t idx = ((size_t)n * U + u) * S + s;
           float* lp = prm.llr + idx * M_BITS;
 #pragma unroll

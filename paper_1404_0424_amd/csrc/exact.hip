@@ -40,7 +40,8 @@ __global__ __launch_bounds__(64) void detect_exact_kernel(DetectParams prm) {
       acc.clear();
       if (s0 == 0) {
         gram_mf<W, true, true>(IN{}, Hn, Yn, B, U, S, s0, c, g, acc);
-        store_gram_lds<W>(acc, As, Gs, AST, prm.reg, c, g);
+        store_gram_lds<W>(acc, As, Gs, (float*)Bs, AST, prm.reg, c, g);
+        wave_lds_sync();
       } else {
         gram_mf<W, false, true>(IN{}, Hn, Yn, B, U, S, s0, c, g, acc);
       }
@@ -140,7 +141,7 @@ __global__ __launch_bounds__(64) void detect_exact_kernel(DetectParams prm) {
             rho = Gs[i] / prm.n0;
           }
           float out[M_BITS];
-          llr_maxlog<M_BITS>(z, rho, prm.scale, out);
+          llr_maxlog<M_BITS>(z, rho, prm.scale, prm.inv_scale, out);
           const size_t o = ((size_t)n * U + i) * S + s;
           float* lp = prm.llr + o * M_BITS;
 #pragma unroll

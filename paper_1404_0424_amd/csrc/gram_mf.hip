@@ -12,7 +12,9 @@ __global__ __launch_bounds__(256) void gram_mf_kernel(GramParams prm) {
   constexpr int AST = NU + 2;
   __shared__ __align__(16) float2 A_s[kWavesPerBlock][NU * AST];
   __shared__ float G_s[kWavesPerBlock][NU];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __shared__ float X_s[kWavesPerBlock][gram_scratch_floats<W>()];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const int c = lane & 15, g = lane >> 4;
   float2* As = A_s[wv];
   const int B = prm.B, U = prm.U, S = prm.S;
@@ -27,7 +29,7 @@ __global__ __launch_bounds__(256) void gram_mf_kernel(GramParams prm) {
       acc.clear();
       if (ch == 0) {
         gram_mf<W, true, HAS_Y>(IN{}, Hn, Yn, B, U, S, s0, c, g, acc);
-        store_gram_lds<W>(acc, As, G_s[wv], AST, prm.reg, c, g);
+        store_gram_lds<W>(acc, As, G_s[wv], X_s[wv], AST, prm.reg, c, g);
         wave_lds_sync();
         float2* An = prm.A + (size_t)n * U * U;
         for (int idx = lane; idx < U * U; idx += kWave) An[idx] = As[(idx / U) * AST + idx % U];

@@ -2,14 +2,19 @@
 // initialization: A = H^H H + reg I, b = H^H y), one wavefront per
 // subcarrier.
 //
-// The complex products are split into real MFMA products.  With
-// Hr/Hi and Yr/Yi the real and imaginary parts,
-//   Re G = Hr^T Hr + Hi^T Hi,      Im G = Hr^T Hi - Hi^T Hr,
-//   Re b = Hr^T Yr + Hi^T Yi,      Im b = Hr^T Yi - Hi^T Yr,
-// and the contraction index k of each MFMA runs over BS antennas.  Lane
-// l = 16 g + c loads user column c (Gram) / right-hand side c (matched
-// filter) of the antennas of k-group g, so A- and B-operands of the Gram
-// come from the same registers.
+// With Hr/Hi and Yr/Yi the real and imaginary parts, over BS antennas k:
+//   Re G = Hr^T Hr + Hi^T Hi,          Im G = M - M^T with M = Hr^T Hi
+//   Re b = P1 + P2,  Im b = P3 - P1 + P2  with P1 = Yr^T Hr, P2 = Yi^T Hi,
+//                                        P3 = (Yr + Yi)^T (Hr - Hi)
+// (three real products per complex product; diagonal Gram tiles need only
+// M, whose transpose is taken through LDS).  The 16-bit path keeps four
+// products for b, because Yr + Yi would round in 16-bit storage.
+//
+// Lane l = 16 g + c loads user column c (Gram) / right-hand side c (matched
+// filter) of the antennas of k-group g, so A- and B-operands of the Gram come
+// from the same registers.  Loads are buffer loads whose descriptor covers
+// exactly one subcarrier's array: rows past B and masked lanes (users >= U,
+// rhs >= S) read zero from the hardware range check, with no branches.
 //
 // Output layout (MFMA D layout): lane (c, g) holds, in element j,
 //   Gram tile (wr, wc):   G[16 wr + 4 g + j][16 wc + c]
@@ -21,16 +26,31 @@
 
 namespace mimo {
 
+constexpr uint32_t kOOB = 0x80000000u;   // offset outside every descriptor's range
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
+                                           0x00020000);
+}
+__device__ __forceinline__ float2 bload2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ uint4 bload4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
 template <int W>
 struct GramAcc {
   static constexpr int NT = W * (W + 1) / 2;   // upper-triangular tiles
-  f4 gr[NT], gi[NT];                           // Re / Im of G tiles
-  f4 dr[W], di[W];                             // Re / Im of b tiles
+  f4 gr[NT];          // Re G
+  f4 gi[NT];          // diagonal tiles: M = Hr^T Hi; off-diagonal tiles: Im G
+  f4 dr[W], di[W];    // complex64: P1, P2; 16-bit: Re b, Im b
+  f4 p3[W];           // complex64: P3
   __device__ void clear() {
 #pragma unroll
     for (int t = 0; t < NT; ++t) { gr[t] = zero4(); gi[t] = zero4(); }
 #pragma unroll
-    for (int w = 0; w < W; ++w) { dr[w] = zero4(); di[w] = zero4(); }
+    for (int w = 0; w < W; ++w) { dr[w] = zero4(); di[w] = zero4(); p3[w] = zero4(); }
   }
 };
 
@@ -44,23 +64,28 @@ __host__ __device__ constexpr int tile_index(int wr, int wc, int W) {
 // one contiguous antenna row of H and of Y.
 template <int W, bool DO_GRAM, bool DO_MF>
 __device__ __forceinline__ void gram_mf_c32(const float2* __restrict__ Hn,
-                                            const float2* __restrict__ Yn, int B,
-                                            int U, int S, int s0, int c, int g,
-                                            GramAcc<W>& acc) {
+                                            const float2* __restrict__ Yn, int B, int U, int S,
+                                            int s0, int c, int g, GramAcc<W>& acc) {
   constexpr int UNR = 8;
+  const __amdgpu_buffer_rsrc_t rh = make_rsrc(Hn, (uint32_t)B * U * 8u);
+  const __amdgpu_buffer_rsrc_t ry = make_rsrc(Yn, DO_MF ? (uint32_t)B * S * 8u : 0u);
+  uint32_t oh[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const int u = 16 * w + c;
+    oh[w] = u < U ? (uint32_t)(g * U + u) * 8u : kOOB;
+  }
   const int s = s0 + c;
+  const uint32_t oy = s < S ? (uint32_t)(g * S + s) * 8u : kOOB;
   for (int b0 = 0; b0 < B; b0 += 4 * UNR) {
     float2 h[UNR][W];
     float2 y[UNR];
 #pragma unroll
     for (int t = 0; t < UNR; ++t) {
-      const int b = b0 + 4 * t + g;
+      const int b = b0 + 4 * t;
 #pragma unroll
-      for (int w = 0; w < W; ++w) {
-        const int u = 16 * w + c;
-        h[t][w] = (b < B && u < U) ? Hn[(size_t)b * U + u] : make_float2(0.f, 0.f);
-      }
-      if (DO_MF) y[t] = (b < B && s < S) ? Yn[(size_t)b * S + s] : make_float2(0.f, 0.f);
+      for (int w = 0; w < W; ++w) h[t][w] = bload2(rh, oh[w], (uint32_t)b * U * 8u);
+      if (DO_MF) y[t] = bload2(ry, oy, (uint32_t)b * S * 8u);
     }
 #pragma unroll
     for (int t = 0; t < UNR; ++t) {
@@ -73,18 +98,26 @@ __device__ __forceinline__ void gram_mf_c32(const float2* __restrict__ Hn,
             acc.gr[ti] = mfma4(h[t][wr].x, h[t][wc].x, acc.gr[ti]);
             acc.gr[ti] = mfma4(h[t][wr].y, h[t][wc].y, acc.gr[ti]);
             acc.gi[ti] = mfma4(h[t][wr].x, h[t][wc].y, acc.gi[ti]);
-            acc.gi[ti] = mfma4(-h[t][wr].y, h[t][wc].x, acc.gi[ti]);
+            if (wr != wc) acc.gi[ti] = mfma4(-h[t][wr].y, h[t][wc].x, acc.gi[ti]);
           }
       }
       if (DO_MF) {
+        const float ys = y[t].x + y[t].y;
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-          acc.dr[w] = mfma4(y[t].x, h[t][w].x, acc.dr[w]);
-          acc.dr[w] = mfma4(y[t].y, h[t][w].y, acc.dr[w]);
-          acc.di[w] = mfma4(y[t].y, h[t][w].x, acc.di[w]);
-          acc.di[w] = mfma4(-y[t].x, h[t][w].y, acc.di[w]);
+          acc.dr[w] = mfma4(y[t].x, h[t][w].x, acc.dr[w]);                 // P1
+          acc.di[w] = mfma4(y[t].y, h[t][w].y, acc.di[w]);                 // P2
+          acc.p3[w] = mfma4(ys, h[t][w].x - h[t][w].y, acc.p3[w]);         // P3
         }
       }
+    }
+  }
+  if (DO_MF) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const f4 p1 = acc.dr[w], p2 = acc.di[w];
+      acc.dr[w] = p1 + p2;
+      acc.di[w] = acc.p3[w] - p1 + p2;
     }
   }
 }
@@ -103,31 +136,33 @@ __device__ __forceinline__ V8 neg8(V8 x) {
 
 template <int W, bool DO_GRAM, bool DO_MF, typename V8>
 __device__ __forceinline__ void gram_mf_16(const uint16_t* __restrict__ Hn,
-                                           const uint16_t* __restrict__ Yn, int B,
-                                           int U, int S, int s0, int c, int g,
-                                           GramAcc<W>& acc) {
+                                           const uint16_t* __restrict__ Yn, int B, int U, int S,
+                                           int s0, int c, int g, GramAcc<W>& acc) {
   constexpr int UNR = 2;
   const int nblk = B >> 3;
+  const __amdgpu_buffer_rsrc_t rh = make_rsrc(Hn, (uint32_t)B * U * 4u);
+  const __amdgpu_buffer_rsrc_t ry = make_rsrc(Yn, DO_MF ? (uint32_t)B * S * 4u : 0u);
+  uint32_t oh[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const int u = 16 * w + c;
+    oh[w] = u < U ? (uint32_t)(2 * g * U + u) * 16u : kOOB;      // block g, part 0
+  }
   const int s = s0 + c;
-  const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+  const uint32_t oy = s < S ? (uint32_t)(2 * g * S + s) * 16u : kOOB;
   for (int k0 = 0; k0 < nblk; k0 += 4 * UNR) {
     V8 hr[UNR][W], hi[UNR][W], yr[UNR], yi[UNR];
 #pragma unroll
     for (int t = 0; t < UNR; ++t) {
-      const int kb = k0 + 4 * t + g;
+      const uint32_t kb = (uint32_t)(k0 + 4 * t);          // first block of this step
 #pragma unroll
       for (int w = 0; w < W; ++w) {
-        const int u = 16 * w + c;
-        const bool ok = kb < nblk && u < U;
-        const uint16_t* p = Hn + ((size_t)(2 * kb) * U + u) * 8;
-        hr[t][w] = __builtin_bit_cast(V8, ok ? *(const uint4*)p : z);
-        hi[t][w] = __builtin_bit_cast(V8, ok ? *(const uint4*)(p + (size_t)U * 8) : z);
+        hr[t][w] = __builtin_bit_cast(V8, bload4(rh, oh[w], kb * 2u * U * 16u));
+        hi[t][w] = __builtin_bit_cast(V8, bload4(rh, oh[w], (kb * 2u + 1u) * U * 16u));
       }
       if (DO_MF) {
-        const bool ok = kb < nblk && s < S;
-        const uint16_t* p = Yn + ((size_t)(2 * kb) * S + s) * 8;
-        yr[t] = __builtin_bit_cast(V8, ok ? *(const uint4*)p : z);
-        yi[t] = __builtin_bit_cast(V8, ok ? *(const uint4*)(p + (size_t)S * 8) : z);
+        yr[t] = __builtin_bit_cast(V8, bload4(ry, oy, kb * 2u * S * 16u));
+        yi[t] = __builtin_bit_cast(V8, bload4(ry, oy, (kb * 2u + 1u) * S * 16u));
       }
     }
 #pragma unroll
@@ -141,7 +176,7 @@ __device__ __forceinline__ void gram_mf_16(const uint16_t* __restrict__ Hn,
             acc.gr[ti] = mfma32(hr[t][wr], hr[t][wc], acc.gr[ti]);
             acc.gr[ti] = mfma32(hi[t][wr], hi[t][wc], acc.gr[ti]);
             acc.gi[ti] = mfma32(hr[t][wr], hi[t][wc], acc.gi[ti]);
-            acc.gi[ti] = mfma32(neg8(hi[t][wr]), hr[t][wc], acc.gi[ti]);
+            if (wr != wc) acc.gi[ti] = mfma32(neg8(hi[t][wr]), hr[t][wc], acc.gi[ti]);
           }
       }
       if (DO_MF) {
@@ -180,17 +215,6 @@ __device__ __forceinline__ void gram_mf(InBF16, const void* Hn, const void* Yn, 
                                      g, acc);
 }
 
-// Elements per subcarrier of an [R][C] complex array in each storage type,
-// counted in units of the pointer type used above (float2 or uint16_t).
-template <typename IN>
-__host__ __device__ constexpr size_t elems_per(IN, size_t R, size_t C);
-template <>
-__host__ __device__ constexpr size_t elems_per(InC32, size_t R, size_t C) { return R * C; }
-template <>
-__host__ __device__ constexpr size_t elems_per(InF16, size_t R, size_t C) { return 2 * R * C; }
-template <>
-__host__ __device__ constexpr size_t elems_per(InBF16, size_t R, size_t C) { return 2 * R * C; }
-
 template <typename IN>
 __device__ __forceinline__ const void* offset_sc(IN tag, const void* base, int64_t n, int R, int C);
 template <>
@@ -206,13 +230,25 @@ __device__ __forceinline__ const void* offset_sc(InBF16, const void* base, int64
   return (const uint16_t*)base + (size_t)n * R * C * 2;
 }
 
+// Bytes of LDS scratch store_gram_lds needs (M tiles for the transpose).
+template <int W>
+__host__ __device__ constexpr int gram_scratch_floats() { return W * 16 * 17; }
+
 // Write the upper triangle (and its conjugate mirror) of the Gram tiles to
 // the wave's LDS copy of A with reg added to the real diagonal; the raw
-// diagonal G_ii goes to Gd.  Padding users (>= U) have zero columns, so
-// their rows of A are reg * e_u and decouple from the real system.
+// diagonal G_ii goes to Gd.  Diagonal tiles first park M in `scratch` so
+// that Im G = M - M^T can be formed.  Padding users (>= U) have zero
+// columns, so their rows of A are reg * e_u and decouple from the system.
 template <int W>
 __device__ __forceinline__ void store_gram_lds(const GramAcc<W>& acc, float2* As, float* Gd,
-                                               int ast, float reg, int c, int g) {
+                                               float* scratch, int ast, float reg, int c, int g) {
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const int ti = tile_index(w, w, W);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) scratch[w * 272 + (4 * g + j) * 17 + c] = acc.gi[ti][j];
+  }
+  wave_lds_sync();
 #pragma unroll
   for (int wr = 0; wr < W; ++wr)
 #pragma unroll
@@ -220,9 +256,12 @@ __device__ __forceinline__ void store_gram_lds(const GramAcc<W>& acc, float2* As
       const int ti = tile_index(wr, wc, W);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int r = 16 * wr + 4 * g + j;
+        const int rl = 4 * g + j;
+        const int r = 16 * wr + rl;
         const int cc = 16 * wc + c;
-        const float re = acc.gr[ti][j], im = acc.gi[ti][j];
+        const float re = acc.gr[ti][j];
+        const float im = (wr == wc) ? acc.gi[ti][j] - scratch[wr * 272 + c * 17 + rl]
+                                    : acc.gi[ti][j];
         if (r < cc) {
           As[r * ast + cc] = make_float2(re, im);
           As[cc * ast + r] = make_float2(re, -im);

@@ -16,6 +16,7 @@ struct DetectParams {
   float n0;             // N0
   float es;             // E_s
   float scale;          // constellation level unit sqrt(3 E_s / (2 (M - 1)))
+  float inv_scale;      // 1 / scale
   float* llr;           // [n_sc][U][S][m]
   float2* xhat;         // [n_sc][U][S] or null
   float* mu;            // [n_sc][U][S] or null

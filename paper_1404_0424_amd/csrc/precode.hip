@@ -28,15 +28,39 @@ __device__ __forceinline__ float2 load_h(InBF16, const void* Hn, int b, int u, i
   return make_float2(bf16_to_f32(p[0]), bf16_to_f32(p[(size_t)U * 8]));
 }
 
+// A-operand rows of the output contraction: H[b][u] for u = 16 w + 4 g + t.
+// Row b0 + c of H (users 16 w + 4 g + t); rows past B read zero.
+template <int W>
+__device__ __forceinline__ void load_h_row(InC32, const void* Hn, int B, int U, int b0, int c,
+                                           int w, int g, float2 (&hv)[4]) {
+  const __amdgpu_buffer_rsrc_t rh = make_rsrc(Hn, (uint32_t)B * U * 8u);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int u = 16 * w + 4 * g + t;
+    hv[t] = bload2(rh, u < U ? (uint32_t)(c * U + u) * 8u : kOOB, (uint32_t)b0 * U * 8u);
+  }
+}
+template <int W, typename IN>
+__device__ __forceinline__ void load_h_row(IN tag, const void* Hn, int B, int U, int b0, int c,
+                                           int w, int g, float2 (&hv)[4]) {
+  const int brow = b0 + c;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int u = 16 * w + 4 * g + t;
+    hv[t] = (brow < B && u < U) ? load_h(tag, Hn, brow, u, U) : make_float2(0.f, 0.f);
+  }
+}
+
 template <int W, typename IN, typename ST>
 __global__ __launch_bounds__(256, 2) void precode_kernel(PrecodeParams prm) {
   constexpr int NU = 16 * W;
   constexpr int AST = NU + 2;
   __shared__ __align__(16) float2 A_s[kWavesPerBlock][NU * AST];
-  __shared__ __align__(16) float2 P_s[kWavesPerBlock][16 * AST];
+  __shared__ __align__(16) float2 P_s[kWavesPerBlock][NU * kPST];
   __shared__ float G_s[kWavesPerBlock][NU];
   __shared__ float N_s[kWavesPerBlock][16];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const int c = lane & 15, g = lane >> 4;
   float2* As = A_s[wv];
   float2* Ps = P_s[wv];
@@ -48,13 +72,16 @@ __global__ __launch_bounds__(256, 2) void precode_kernel(PrecodeParams prm) {
   for (int64_t n = (int64_t)blockIdx.x * kWavesPerBlock + wv; n < prm.n_sc;
        n += (int64_t)gridDim.x * kWavesPerBlock) {
     const void* Hn = offset_sc(IN{}, prm.H, n, B, U);
+    AOperand<W> at;
     for (int s0 = 0; s0 < S; s0 += 16) {
       // ---- A = H_d H_d^H + beta I = G + beta I (Algorithm 1, initialization)
       if (s0 == 0) {
         GramAcc<W> acc;
         acc.clear();
         gram_mf<W, true, false>(IN{}, Hn, nullptr, B, U, S, 0, c, g, acc);
-        store_gram_lds<W>(acc, As, Gs, AST, beta, c, g);
+        store_gram_lds<W>(acc, As, Gs, (float*)Ps, AST, beta, c, g);
+        wave_lds_sync();
+        at.load(As, AST, c, g);
       }
       // b = t
       float2 b[W][4];
@@ -65,20 +92,19 @@ __global__ __launch_bounds__(256, 2) void precode_kernel(PrecodeParams prm) {
           const int u = 16 * w + c, s = s0 + 4 * g + j;
           b[w][j] = (u < U && s < S) ? prm.T[((size_t)n * U + u) * S + s] : make_float2(0.f, 0.f);
         }
-      wave_lds_sync();
 
       CGState<W, ST> st;
       cg_init<W, ST>(st, b);
       for (int k = 0; k < prm.K; ++k) {
         ST al[4], be[4];
-        cg_step<W, ST>(st, As, Ps, AST, c, g, al, be);
+        cg_step<W, ST>(st, at, Ps, c, g, al, be);
       }
 
-      // ---- ||q||^2 = v^H G v ; V staged in Ps for the output contraction
-      stage_vec<W>(Ps, AST, c, g, st.v);
+      // ---- ||q||^2 = v^H G v ; V stays staged in Ps for the output contraction
+      stage_vec<W>(Ps, c, g, st.v);
       wave_lds_sync();
       float2 e[W][4];
-      matvec<W>(As, Ps, AST, c, g, e);
+      matvec_mfma<W>(at, Ps, c, g, e);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         ST part = ST(0);
@@ -98,25 +124,33 @@ __global__ __launch_bounds__(256, 2) void precode_kernel(PrecodeParams prm) {
       // 16 w + 4 g + t, t = 0..3, so a lane reads 4 adjacent users of a row).
       const int s = s0 + c;
       const float nrm2 = Ns[c];
-      const float scl = prm.normalize ? (nrm2 > 0.f ? 1.0f / sqrtf(nrm2) : 0.f) : 1.0f;
+      const float scl = prm.normalize ? (nrm2 > 0.f ? __builtin_amdgcn_rsqf(nrm2) : 0.f) : 1.0f;
+      float2 vv[W][4];
+#pragma unroll
+      for (int w = 0; w < W; ++w)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) vv[w][t] = Ps[(16 * w + 4 * g + t) * kPST + c];
+      float2 hn[W][4];                                 // next row tile, loaded ahead
+#pragma unroll
+      for (int w = 0; w < W; ++w) load_h_row<W>(IN{}, Hn, B, U, 0, c, w, g, hn[w]);
       for (int b0 = 0; b0 < B; b0 += 16) {
         f4 qr = zero4(), qi = zero4();
-        const int brow = b0 + c;
+        float2 hc[W][4];
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) hc[w][t] = hn[w][t];
+#pragma unroll
+        for (int w = 0; w < W; ++w) load_h_row<W>(IN{}, Hn, B, U, b0 + 16, c, w, g, hn[w]);
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-          float2 hv[4], vv[4];
+          const float2(&hv)[4] = hc[w];
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
-            const int u = 16 * w + 4 * g + t;
-            hv[t] = (brow < B && u < U) ? load_h(IN{}, Hn, brow, u, U) : make_float2(0.f, 0.f);
-            vv[t] = Ps[c * AST + u];
-          }
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            qr = mfma4(hv[t].x, vv[t].x, qr);
-            qr = mfma4(-hv[t].y, vv[t].y, qr);
-            qi = mfma4(hv[t].x, vv[t].y, qi);
-            qi = mfma4(hv[t].y, vv[t].x, qi);
+            qr = mfma4(hv[t].x, vv[w][t].x, qr);
+            qi = mfma4(hv[t].x, vv[w][t].y, qi);
+            qr = mfma4(-hv[t].y, vv[w][t].y, qr);
+            qi = mfma4(hv[t].y, vv[w][t].x, qi);
           }
         }
         if (s < S) {
