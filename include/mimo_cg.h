@@ -149,6 +149,27 @@ int mimo_precode_cg(const mimo_shape* shape, const void* H, const void* T,
 int mimo_convert(const void* src, void* dst, int dst_dtype, int64_t n,
                  int32_t R, int32_t C, void* stream);
 
+/*
+ * Kernel schedules (not part of the paper's method: how the same arithmetic
+ * is mapped onto the GPU).  Each operation has kernel variants and a grid
+ * size; the pair used for (op, user class, storage type) comes from a
+ * process-wide table that an autotuner fills by timing the variants.
+ *   user_class    0: U <= 16, 1: 16 < U <= 32
+ *   variant       0 .. mimo_tune_variant_count(op) - 1 (detection: 0 generic,
+ *                 1 stream = next subcarrier's loads in flight during CG,
+ *                 2 stream with half-size load blocks; variant 1/2 apply for
+ *                 S <= 16, larger S always uses 0)
+ *   blocks_per_cu 0: one wavefront per subcarrier; k in [1, 64]: persistent
+ *                 grid of k four-wavefront blocks per compute unit
+ * Results do not depend on the schedule (every variant performs the same
+ * operations in the same order per system).  mimo_tune_set is not
+ * synchronized with launches already enqueued; it affects later calls.
+ */
+int mimo_tune_set(int op, int user_class, int in_dtype, int variant, int blocks_per_cu);
+int mimo_tune_get(int op, int user_class, int in_dtype, int* variant, int* blocks_per_cu);
+int mimo_tune_variant_count(int op);
+const char* mimo_tune_variant_name(int op, int variant);   /* NULL if out of range */
+
 /* Device workspace (bytes) that an operation needs; 0 means none. */
 size_t mimo_workspace_bytes(const mimo_shape* shape, int op, int sinr_mode);
 

@@ -47,6 +47,10 @@ _SIGNATURES = {
     "mimo_status_string": (ctypes.c_char_p, [_i]),
     "mimo_last_error": (ctypes.c_char_p, []),
     "mimo_version": (ctypes.c_char_p, []),
+    "mimo_tune_set": (_i, [_i, _i, _i, _i, _i]),
+    "mimo_tune_get": (_i, [_i, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
+    "mimo_tune_variant_count": (_i, [_i]),
+    "mimo_tune_variant_name": (ctypes.c_char_p, [_i, _i]),
 }
 
 

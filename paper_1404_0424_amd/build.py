@@ -27,6 +27,9 @@ FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 VALU forms are kept out of generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # contract a*b+c only within one source expression, so every kernel
+    # variant rounds a given formula the same way
+    "-ffp-contract=on",
     "-I", os.path.join(ROOT, "include"),
 ]
 

@@ -2,6 +2,7 @@
 // selection and launch.  No device memory is allocated here.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -57,6 +58,46 @@ int check_ptr(const void* p, const char* name, bool required) {
   return MIMO_OK;
 }
 
+// ---------------------------------------------------------------- schedules
+// Process-wide table of kernel schedules, indexed by operation, user class
+// (U <= 16, U <= 32) and storage type; written by mimo_tune_set (the
+// autotuner), read at every launch.  Each entry packs variant | blocks << 8.
+constexpr int kOps = 3, kUClasses = 2, kDtypes = 3;
+std::atomic<int> g_sched[kOps][kUClasses][kDtypes];
+std::atomic<bool> g_sched_init{false};
+
+int pack(int variant, int blocks) { return (variant & 0xff) | (blocks << 8); }
+
+void sched_defaults() {
+  bool expect = false;
+  if (!g_sched_init.compare_exchange_strong(expect, true)) return;
+  for (int o = 0; o < kOps; ++o)
+    for (int u = 0; u < kUClasses; ++u)
+      for (int d = 0; d < kDtypes; ++d) g_sched[o][u][d].store(pack(0, 0));
+  // measured defaults on MI355X (128x16 and 256x32 workloads); the
+  // autotuner overrides them per process
+  for (int u = 0; u < kUClasses; ++u)
+    for (int d = 0; d < kDtypes; ++d) {
+      g_sched[MIMO_OP_DETECT][u][d].store(pack(mimo::kDetectStream, 0));
+      g_sched[MIMO_OP_PRECODE][u][d].store(pack(mimo::kPrecodeGeneric, 4));
+    }
+}
+
+mimo::Schedule get_sched(int op, int U, int dt) {
+  sched_defaults();
+  const int v = g_sched[op][U <= 16 ? 0 : 1][dt].load(std::memory_order_relaxed);
+  return mimo::Schedule{v & 0xff, v >> 8};
+}
+
+int variant_count(int op) {
+  switch (op) {
+    case MIMO_OP_DETECT: return mimo::kDetectVariants;
+    case MIMO_OP_PRECODE: return mimo::kPrecodeVariants;
+    case MIMO_OP_GRAM_MF: return 1;
+  }
+  return 0;
+}
+
 #define CHECK(x)              \
   do {                        \
     const int st_ = (x);      \
@@ -65,7 +106,65 @@ int check_ptr(const void* p, const char* name, bool required) {
 
 }  // namespace
 
+namespace mimo {
+int num_compute_units() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  int v = cache[dev].load(std::memory_order_relaxed);
+  if (v <= 0) {
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        v <= 0)
+      v = 256;
+    cache[dev].store(v, std::memory_order_relaxed);
+  }
+  return v;
+}
+}  // namespace mimo
+
 extern "C" {
+
+int mimo_tune_variant_count(int op) { return variant_count(op); }
+
+const char* mimo_tune_variant_name(int op, int variant) {
+  if (op == MIMO_OP_DETECT) {
+    switch (variant) {
+      case mimo::kDetectGeneric: return "generic";
+      case mimo::kDetectStream: return "stream";
+      case mimo::kDetectStreamSmall: return "stream-small";
+    }
+  } else if (variant == 0 && (op == MIMO_OP_PRECODE || op == MIMO_OP_GRAM_MF)) {
+    return "generic";
+  }
+  return nullptr;
+}
+
+int mimo_tune_set(int op, int user_class, int in_dtype, int variant, int blocks_per_cu) {
+  g_last_error[0] = 0;
+  if (op < 0 || op >= kOps) return fail(MIMO_EINVAL, "op=%d unknown", op);
+  if (user_class < 0 || user_class >= kUClasses)
+    return fail(MIMO_EINVAL, "user_class=%d outside [0, %d)", user_class, kUClasses);
+  if (in_dtype < 0 || in_dtype >= kDtypes) return fail(MIMO_EINVAL, "in_dtype=%d unknown", in_dtype);
+  if (variant < 0 || variant >= variant_count(op))
+    return fail(MIMO_EINVAL, "variant=%d outside [0, %d)", variant, variant_count(op));
+  if (blocks_per_cu < 0 || blocks_per_cu > 64)
+    return fail(MIMO_EINVAL, "blocks_per_cu=%d outside [0, 64]", blocks_per_cu);
+  sched_defaults();
+  g_sched[op][user_class][in_dtype].store(pack(variant, blocks_per_cu));
+  return MIMO_OK;
+}
+
+int mimo_tune_get(int op, int user_class, int in_dtype, int* variant, int* blocks_per_cu) {
+  g_last_error[0] = 0;
+  if (op < 0 || op >= kOps || user_class < 0 || user_class >= kUClasses || in_dtype < 0 ||
+      in_dtype >= kDtypes || !variant || !blocks_per_cu)
+    return fail(MIMO_EINVAL, "bad tune_get arguments");
+  const mimo::Schedule s = get_sched(op, user_class == 0 ? 16 : 32, in_dtype);
+  *variant = s.variant;
+  *blocks_per_cu = s.blocks_per_cu;
+  return MIMO_OK;
+}
+
 
 const char* mimo_version(void) { return "mimo_cg 0.1 gfx950"; }
 
@@ -138,7 +237,9 @@ int mimo_detect_cg(const mimo_shape* shape, const void* H, const void* Y, int in
   const int f64 = scalar_prec == MIMO_SCALAR_F64;
   hipError_t e = sinr_mode == MIMO_SINR_EXACT
                      ? mimo::launch_detect_exact(p, in_dtype, f64, qam_bits, (hipStream_t)stream)
-                     : mimo::launch_detect_approx(p, in_dtype, f64, qam_bits, (hipStream_t)stream);
+                     : mimo::launch_detect_approx(p, in_dtype, f64, qam_bits,
+                                                  get_sched(MIMO_OP_DETECT, shape->U, in_dtype),
+                                                  (hipStream_t)stream);
   return hip_status(e, "detect_cg launch");
 }
 
@@ -162,6 +263,7 @@ int mimo_precode_cg(const mimo_shape* shape, const void* H, const void* T, int i
   mimo::PrecodeParams p{H, (const float2*)T, shape->B, shape->U, shape->S, shape->K,
                         shape->n_sc, beta, normalize ? 1 : 0, (float2*)Q, qnorm};
   return hip_status(mimo::launch_precode(p, in_dtype, scalar_prec == MIMO_SCALAR_F64,
+                                         get_sched(MIMO_OP_PRECODE, shape->U, in_dtype),
                                          (hipStream_t)stream),
                     "precode_cg launch");
 }

@@ -80,18 +80,23 @@ __device__ __forceinline__ bool live_floor<float>(float rr, float pe) {
 
 template <int W, typename ST>
 __device__ __forceinline__ void cg_init(CGState<W, ST>& st, const float2 (&b)[W][4]) {
+  ST part[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    ST part = ST(0);
+    part[j] = (ST)b[0][j].x * (ST)b[0][j].x + (ST)b[0][j].y * (ST)b[0][j].y;
+#pragma unroll
+    for (int w = 1; w < W; ++w)
+      part[j] += (ST)b[w][j].x * (ST)b[w][j].x + (ST)b[w][j].y * (ST)b[w][j].y;
 #pragma unroll
     for (int w = 0; w < W; ++w) {
       st.v[w][j] = make_float2(0.f, 0.f);
       st.r[w][j] = b[w][j];
       st.p[w][j] = b[w][j];
-      part += (ST)b[w][j].x * (ST)b[w][j].x + (ST)b[w][j].y * (ST)b[w][j].y;
     }
-    st.rr[j] = row_sum16(part);
   }
+  row_sum16_x4(part);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) st.rr[j] = part[j];
 }
 
 // Stage x (lane layout) to LDS as X[user][rhs].
@@ -134,6 +139,8 @@ __device__ __forceinline__ void matvec_mfma(const AOperand<W>& at, const float2*
 // One iteration of Algorithm 1 (loop body) for the lane's 4 right-hand
 // sides.  alpha/beta are returned for the trackers.  A right-hand side whose
 // residual norm is zero (converged or b = 0) freezes: alpha = beta = 0.
+// Branch-free (selects), with the four right-hand sides' reductions
+// interleaved.
 template <int W, typename ST>
 __device__ __forceinline__ void cg_step(CGState<W, ST>& st, const AOperand<W>& at,
                                         float2* __restrict__ Ps, int c, int g, ST (&alpha)[4],
@@ -143,36 +150,47 @@ __device__ __forceinline__ void cg_step(CGState<W, ST>& st, const AOperand<W>& a
   float2 e[W][4];
   matvec_mfma<W>(at, Ps, c, g, e);                 // e_{k-1} = A p_{k-1}
   wave_lds_sync();
+  ST pe[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    ST part = ST(0);
+    pe[j] = (ST)st.p[0][j].x * (ST)e[0][j].x + (ST)st.p[0][j].y * (ST)e[0][j].y;
 #pragma unroll
-    for (int w = 0; w < W; ++w)
-      part += (ST)st.p[w][j].x * (ST)e[w][j].x + (ST)st.p[w][j].y * (ST)e[w][j].y;
-    const ST pe = row_sum16(part);                 // Re(p^H e)
-    const bool live = live_floor<ST>(st.rr[j], pe);
-    alpha[j] = live ? div_fast<ST>(st.rr[j], pe) : ST(0);
+    for (int w = 1; w < W; ++w)
+      pe[j] += (ST)st.p[w][j].x * (ST)e[w][j].x + (ST)st.p[w][j].y * (ST)e[w][j].y;
+  }
+  row_sum16_x4(pe);                                // Re(p^H e)
+  bool live[4];
+  ST rr_new[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    live[j] = live_floor<ST>(st.rr[j], pe[j]);
+    alpha[j] = live[j] ? div_fast<ST>(st.rr[j], pe[j]) : ST(0);
     const float af = (float)alpha[j];
-    ST part2 = ST(0);
 #pragma unroll
     for (int w = 0; w < W; ++w) {
       st.v[w][j].x = __builtin_fmaf(af, st.p[w][j].x, st.v[w][j].x);
       st.v[w][j].y = __builtin_fmaf(af, st.p[w][j].y, st.v[w][j].y);
       st.r[w][j].x = __builtin_fmaf(-af, e[w][j].x, st.r[w][j].x);
       st.r[w][j].y = __builtin_fmaf(-af, e[w][j].y, st.r[w][j].y);
-      part2 += (ST)st.r[w][j].x * (ST)st.r[w][j].x + (ST)st.r[w][j].y * (ST)st.r[w][j].y;
     }
-    const ST rr_new = row_sum16(part2);
-    beta[j] = live ? div_fast<ST>(rr_new, st.rr[j]) : ST(0);
+    rr_new[j] = (ST)st.r[0][j].x * (ST)st.r[0][j].x + (ST)st.r[0][j].y * (ST)st.r[0][j].y;
+#pragma unroll
+    for (int w = 1; w < W; ++w)
+      rr_new[j] += (ST)st.r[w][j].x * (ST)st.r[w][j].x + (ST)st.r[w][j].y * (ST)st.r[w][j].y;
+  }
+  row_sum16_x4(rr_new);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    beta[j] = live[j] ? div_fast<ST>(rr_new[j], st.rr[j]) : ST(0);
     const float bf = (float)beta[j];
 #pragma unroll
     for (int w = 0; w < W; ++w) {
-      if (live) {
-        st.p[w][j].x = __builtin_fmaf(bf, st.p[w][j].x, st.r[w][j].x);
-        st.p[w][j].y = __builtin_fmaf(bf, st.p[w][j].y, st.r[w][j].y);
-      }
+      const float px = __builtin_fmaf(bf, st.p[w][j].x, st.r[w][j].x);
+      const float py = __builtin_fmaf(bf, st.p[w][j].y, st.r[w][j].y);
+      st.p[w][j].x = live[j] ? px : st.p[w][j].x;
+      st.p[w][j].y = live[j] ? py : st.p[w][j].y;
     }
-    if (live) st.rr[j] = rr_new;
+    st.rr[j] = live[j] ? rr_new[j] : st.rr[j];
   }
 }
 

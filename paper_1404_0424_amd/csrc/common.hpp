@@ -59,6 +59,20 @@ __device__ __forceinline__ T row_sum16(T x) {
   return x;
 }
 
+// Four independent row sums, advanced step by step so the DPP latencies of
+// the four chains overlap.
+template <typename T>
+__device__ __forceinline__ void row_sum16_x4(T (&x)[4]) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) x[j] += dpp<kQuadSwap1>(x[j]);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) x[j] += dpp<kQuadSwap2>(x[j]);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) x[j] += dpp<kRowHalfMirror>(x[j]);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) x[j] += dpp<kRowMirror>(x[j]);
+}
+
 // Full-wave sum (64 lanes) via cross-lane shuffles; result in every lane.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T x) {

@@ -1,6 +1,8 @@
 // Fused CG-D kernel: Gram + matched filter (MFMA) -> K CG iterations with the
 // approximate in-loop SINR tracker -> max-log LLR epilogue, one wavefront per
 // subcarrier (Sec. III-B, III-C-2, Algorithm 1, eqs. (4), (13)-(15)).
+#include <type_traits>
+
 #include "cg_core.hpp"
 #include "gram_phase.hpp"
 #include "kernels.hpp"
@@ -8,6 +10,137 @@
 
 namespace mimo {
 
+// K iterations of Algorithm 1 with the tracker of eq. (13), then mu (eq. (14)),
+// rho (eq. (15)), z = xhat / mu and the LLRs (eq. (4)) of right-hand sides
+// s0 + 4 g + j of subcarrier n.  A^T, d and G_ii come from the Gram phase.
+template <int W, typename ST, int M_BITS>
+__device__ __forceinline__ void cg_llr_epilogue(const DetectParams& prm, int64_t n, int s0,
+                                                const GramAcc<W>& acc, const AOperand<W>& at,
+                                                const float (&d)[W], const float* Gs,
+                                                float2* Ps, int c, int g) {
+  const int U = prm.U, S = prm.S;
+  float2 b[W][4];
+#pragma unroll
+  for (int w = 0; w < W; ++w)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[w][j] = make_float2(acc.dr[w][j], acc.di[w][j]);
+  CGState<W, ST> st;
+  cg_init<W, ST>(st, b);
+  Tracker<W, ST> tk;
+  tk.init();
+  for (int k = 0; k < prm.K; ++k) {
+    ST al[4], be[4];
+    cg_step<W, ST>(st, at, Ps, c, g, al, be);
+    tracker_step<W, ST>(tk, d, al, be);
+  }
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const int u = 16 * w + c;
+    const float Guu = Gs[u < U ? u : 0];
+    const float rho = Guu / prm.n0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int s = s0 + 4 * g + j;
+      const float mu = (float)(tk.tv[w][j] * (ST)Guu);
+      const float2 x = st.v[w][j];
+      // |mu| < FLT_MIN only when the right-hand side froze at (near) zero:
+      // z = 0 as for b = 0.
+      const float imu = fabsf(mu) >= __FLT_MIN__ ? __builtin_amdgcn_rcpf(mu) : 0.f;
+      const float2 z = make_float2(x.x * imu, x.y * imu);
+      float out[M_BITS];
+      llr_maxlog<M_BITS>(z, rho, prm.scale, prm.inv_scale, out);
+      if (u < U && s < S) {
+        const size_t idx = ((size_t)n * U + u) * S + s;
+        float* lp = prm.llr + idx * M_BITS;
+#pragma unroll
+        for (int q = 0; q < M_BITS; ++q) lp[q] = out[q];
+        if (prm.xhat) prm.xhat[idx] = x;
+        if (prm.mu) prm.mu[idx] = mu;
+        if (prm.sinr) prm.sinr[idx] = rho;
+      }
+    }
+  }
+}
+
+// Gram tiles -> LDS A, A^T operand and diagonal d = A_ii.
+template <int W>
+__device__ __forceinline__ void gram_to_operands(const GramAcc<W>& acc, float2* As, float* Gs,
+                                                 float2* Ps, int ast, float reg, int c, int g,
+                                                 AOperand<W>& at, float (&d)[W]) {
+  store_gram_lds<W>(acc, As, Gs, (float*)Ps, ast, reg, c, g);
+  wave_lds_sync();
+  at.load(As, ast, c, g);
+#pragma unroll
+  for (int w = 0; w < W; ++w) d[w] = As[(16 * w + c) * ast + 16 * w + c].x;
+}
+
+// Streaming kernel for S <= 16 (one right-hand-side chunk).  Each wavefront
+// keeps the next block of H / Y loads in flight while the MFMAs of the
+// current block run, and issues the first block of its next subcarrier
+// before the CG / LLR phase of the current one, so HBM latency overlaps
+// compute within the wave as well as across waves.
+template <int W, typename IN, typename ST, int M_BITS, bool SMALL>
+__global__ __launch_bounds__(256, 2) void detect_stream_kernel(DetectParams prm) {
+  constexpr int NU = 16 * W;
+  constexpr int AST = NU + 2;   // LDS row stride (complex) of A
+  using Sub = typename Storage<IN, W>::Sub;
+  using Blk = typename std::conditional<SMALL, typename Storage<IN, W>::SmallBlock,
+                                        typename Storage<IN, W>::Block>::type;
+  __shared__ __align__(16) float2 A_s[kWavesPerBlock][NU * AST];
+  __shared__ __align__(16) float2 P_s[kWavesPerBlock][NU * kPST];
+  __shared__ float G_s[kWavesPerBlock][NU];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+  const int c = lane & 15, g = lane >> 4;
+  float2* As = A_s[wv];
+  float2* Ps = P_s[wv];
+  float* Gs = G_s[wv];
+  const int B = prm.B, U = prm.U, S = prm.S;
+  const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
+
+  int64_t n = (int64_t)blockIdx.x * kWavesPerBlock + wv;
+  Sub cur;
+  Blk blk;
+  if (n < prm.n_sc) {
+    cur.init(offset_sc(IN{}, prm.H, n, B, U), offset_sc(IN{}, prm.Y, n, B, S), B, U, S, 0, c, g);
+    blk.template load<true>(cur, 0);
+  }
+  while (n < prm.n_sc) {
+    const int64_t nn = n + stride;
+    const int64_t nc = nn < prm.n_sc ? nn : n;        // descriptors only used if nn < n_sc
+    Sub nxt;
+    nxt.init(offset_sc(IN{}, prm.H, nc, B, U), offset_sc(IN{}, prm.Y, nc, B, S), B, U, S, 0, c, g);
+    // ---- A = H^H H + (N0/E_s) I and b = H^H y (Algorithm 1, initialization)
+    GramAcc<W> acc;
+    acc.clear();
+    // ping-pong between two block buffers: blk holds the block at b0, alt
+    // receives the next one (or the next subcarrier's first block)
+    Blk alt;
+    for (int b0 = 0;; b0 += 2 * Blk::ANT) {
+      if (b0 + Blk::ANT < B) alt.template load<true>(cur, b0 + Blk::ANT);
+      else if (nn < prm.n_sc) alt.template load<true>(nxt, 0);
+      blk.template mma<true, true>(acc);
+      if (b0 + Blk::ANT >= B) {                    // odd block count: hand over
+        blk = alt;
+        break;
+      }
+      if (b0 + 2 * Blk::ANT < B) blk.template load<true>(cur, b0 + 2 * Blk::ANT);
+      else if (nn < prm.n_sc) blk.template load<true>(nxt, 0);
+      alt.template mma<true, true>(acc);
+      if (b0 + 2 * Blk::ANT >= B) break;           // even block count: blk holds the next
+    }
+    finish_mf(IN{}, acc);
+    AOperand<W> at;
+    float d[W];
+    gram_to_operands<W>(acc, As, Gs, Ps, AST, prm.reg, c, g, at, d);
+    cg_llr_epilogue<W, ST, M_BITS>(prm, n, 0, acc, at, d, Gs, Ps, c, g);
+    n = nn;
+    cur = nxt;
+  }
+}
+
+// Generic kernel (any S): right-hand sides in chunks of 16, the Gram computed
+// with the first chunk and kept in LDS.
 template <int W, typename IN, typename ST, int M_BITS>
 __global__ __launch_bounds__(256, 2) void detect_approx_kernel(DetectParams prm) {
   constexpr int NU = 16 * W;
@@ -30,101 +163,65 @@ __global__ __launch_bounds__(256, 2) void detect_approx_kernel(DetectParams prm)
     AOperand<W> at;
     float d[W];
     for (int s0 = 0; s0 < S; s0 += 16) {
-      // ---- A = H^H H + (N0/E_s) I and b = H^H y (Algorithm 1, initialization)
       GramAcc<W> acc;
       acc.clear();
       if (s0 == 0) {
         gram_mf<W, true, true>(IN{}, Hn, Yn, B, U, S, s0, c, g, acc);
-        store_gram_lds<W>(acc, As, Gs, (float*)Ps, AST, prm.reg, c, g);
-        wave_lds_sync();
-        at.load(As, AST, c, g);
-#pragma unroll
-        for (int w = 0; w < W; ++w) d[w] = As[(16 * w + c) * AST + 16 * w + c].x;
+        gram_to_operands<W>(acc, As, Gs, Ps, AST, prm.reg, c, g, at, d);
       } else {
         gram_mf<W, false, true>(IN{}, Hn, Yn, B, U, S, s0, c, g, acc);
       }
-
-      // ---- K iterations of Algorithm 1 with the tracker of eq. (13)
-      float2 b[W][4];
-#pragma unroll
-      for (int w = 0; w < W; ++w)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) b[w][j] = make_float2(acc.dr[w][j], acc.di[w][j]);
-      CGState<W, ST> st;
-      cg_init<W, ST>(st, b);
-      Tracker<W, ST> tk;
-      tk.init();
-      for (int k = 0; k < prm.K; ++k) {
-        ST al[4], be[4];
-        cg_step<W, ST>(st, at, Ps, c, g, al, be);
-        tracker_step<W, ST>(tk, d, al, be);
-      }
-
-      // ---- mu (eq. (14)), rho (eq. (15)), z = xhat / mu, LLRs (eq. (4))
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        const int u = 16 * w + c;
-        if (u >= U) continue;
-        const float Guu = Gs[u];
-        const float rho = Guu / prm.n0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int s = s0 + 4 * g + j;
-          if (s >= S) continue;
-          const float mu = (float)(tk.tv[w][j] * (ST)Guu);
-          const float2 x = st.v[w][j];
-          // |mu| < FLT_MIN only when the right-hand side froze at (near) zero:
-          // z = 0 as for b = 0.
-          const float imu = fabsf(mu) >= __FLT_MIN__ ? __builtin_amdgcn_rcpf(mu) : 0.f;
-          const float2 z = make_float2(x.x * imu, x.y * imu);
-          float out[M_BITS];
-          llr_maxlog<M_BITS>(z, rho, prm.scale, prm.inv_scale, out);
-          const size_t idx = ((size_t)n * U + u) * S + s;
-          float* lp = prm.llr + idx * M_BITS;
-#pragma unroll
-          for (int q = 0; q < M_BITS; ++q) lp[q] = out[q];
-          if (prm.xhat) prm.xhat[idx] = x;
-          if (prm.mu) prm.mu[idx] = mu;
-          if (prm.sinr) prm.sinr[idx] = rho;
-        }
-      }
+      cg_llr_epilogue<W, ST, M_BITS>(prm, n, s0, acc, at, d, Gs, Ps, c, g);
     }
   }
 }
 
+template <int W, typename IN, typename ST, int M>
+static void launch_one(const DetectParams& p, const Schedule& sch, hipStream_t stream) {
+  const dim3 grid(sched_grid(p.n_sc, sch)), block(kWave * kWavesPerBlock);
+  if (p.S > 16 || sch.variant == kDetectGeneric)
+    hipLaunchKernelGGL((detect_approx_kernel<W, IN, ST, M>), grid, block, 0, stream, p);
+  else if (sch.variant == kDetectStreamSmall)
+    hipLaunchKernelGGL((detect_stream_kernel<W, IN, ST, M, true>), grid, block, 0, stream, p);
+  else
+    hipLaunchKernelGGL((detect_stream_kernel<W, IN, ST, M, false>), grid, block, 0, stream, p);
+}
+
 template <int W, typename IN, typename ST>
-static hipError_t launch_m(const DetectParams& p, int m_bits, hipStream_t stream) {
-  const dim3 grid(wave_grid(p.n_sc)), block(kWave * kWavesPerBlock);
+static hipError_t launch_m(const DetectParams& p, int m_bits, const Schedule& sch,
+                           hipStream_t stream) {
   switch (m_bits) {
-    case 2: hipLaunchKernelGGL((detect_approx_kernel<W, IN, ST, 2>), grid, block, 0, stream, p); break;
-    case 4: hipLaunchKernelGGL((detect_approx_kernel<W, IN, ST, 4>), grid, block, 0, stream, p); break;
-    case 6: hipLaunchKernelGGL((detect_approx_kernel<W, IN, ST, 6>), grid, block, 0, stream, p); break;
-    case 8: hipLaunchKernelGGL((detect_approx_kernel<W, IN, ST, 8>), grid, block, 0, stream, p); break;
+    case 2: launch_one<W, IN, ST, 2>(p, sch, stream); break;
+    case 4: launch_one<W, IN, ST, 4>(p, sch, stream); break;
+    case 6: launch_one<W, IN, ST, 6>(p, sch, stream); break;
+    case 8: launch_one<W, IN, ST, 8>(p, sch, stream); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 template <int W, typename IN>
-static hipError_t launch_st(const DetectParams& p, int f64, int m_bits, hipStream_t stream) {
-  return f64 ? launch_m<W, IN, double>(p, m_bits, stream) : launch_m<W, IN, float>(p, m_bits, stream);
+static hipError_t launch_st(const DetectParams& p, int f64, int m_bits, const Schedule& sch,
+                            hipStream_t stream) {
+  return f64 ? launch_m<W, IN, double>(p, m_bits, sch, stream)
+             : launch_m<W, IN, float>(p, m_bits, sch, stream);
 }
 
 template <int W>
 static hipError_t launch_in(const DetectParams& p, int in_dtype, int f64, int m_bits,
-                            hipStream_t stream) {
+                            const Schedule& sch, hipStream_t stream) {
   switch (in_dtype) {
-    case 0: return launch_st<W, InC32>(p, f64, m_bits, stream);
-    case 1: return launch_st<W, InF16>(p, f64, m_bits, stream);
-    case 2: return launch_st<W, InBF16>(p, f64, m_bits, stream);
+    case 0: return launch_st<W, InC32>(p, f64, m_bits, sch, stream);
+    case 1: return launch_st<W, InF16>(p, f64, m_bits, sch, stream);
+    case 2: return launch_st<W, InBF16>(p, f64, m_bits, sch, stream);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_detect_approx(const DetectParams& p, int in_dtype, int scalar_f64, int m_bits,
-                                hipStream_t stream) {
-  if (p.U <= 16) return launch_in<1>(p, in_dtype, scalar_f64, m_bits, stream);
-  return launch_in<2>(p, in_dtype, scalar_f64, m_bits, stream);
+                                const Schedule& sch, hipStream_t stream) {
+  if (p.U <= 16) return launch_in<1>(p, in_dtype, scalar_f64, m_bits, sch, stream);
+  return launch_in<2>(p, in_dtype, scalar_f64, m_bits, sch, stream);
 }
 
 }  // namespace mimo

@@ -58,35 +58,53 @@ __host__ __device__ constexpr int tile_index(int wr, int wc, int W) {
   return wr * W - (wr * (wr - 1)) / 2 + (wc - wr);
 }
 
+// Input storage tags
+struct InC32 {};
+struct InF16 {};
+struct InBF16 {};
+
 // ----------------------------------------------------------------- complex64
 // H: [B][U] complex64 of one subcarrier, Y: [B][S].  Each MFMA step covers 4
 // antennas (k-group g -> antenna 4 t + g), so the 16 lanes of a k-group read
-// one contiguous antenna row of H and of Y.
-template <int W, bool DO_GRAM, bool DO_MF>
-__device__ __forceinline__ void gram_mf_c32(const float2* __restrict__ Hn,
-                                            const float2* __restrict__ Yn, int B, int U, int S,
-                                            int s0, int c, int g, GramAcc<W>& acc) {
-  constexpr int UNR = 8;
-  const __amdgpu_buffer_rsrc_t rh = make_rsrc(Hn, (uint32_t)B * U * 8u);
-  const __amdgpu_buffer_rsrc_t ry = make_rsrc(Yn, DO_MF ? (uint32_t)B * S * 8u : 0u);
-  uint32_t oh[W];
+// one contiguous antenna row of H and of Y.  A block is UNR steps.
+template <int W>
+struct SubC32 {                       // per-subcarrier buffer descriptors and lane offsets
+  __amdgpu_buffer_rsrc_t rh, ry;
+  uint32_t oh[W], oy;
+  int U, S;
+  __device__ void init(const void* Hn, const void* Yn, int B, int U_, int S_, int s0, int c,
+                       int g) {
+    U = U_;
+    S = S_;
+    rh = make_rsrc(Hn, (uint32_t)B * U * 8u);
+    ry = make_rsrc(Yn ? Yn : Hn, Yn ? (uint32_t)B * S * 8u : 0u);
 #pragma unroll
-  for (int w = 0; w < W; ++w) {
-    const int u = 16 * w + c;
-    oh[w] = u < U ? (uint32_t)(g * U + u) * 8u : kOOB;
+    for (int w = 0; w < W; ++w) {
+      const int u = 16 * w + c;
+      oh[w] = u < U ? (uint32_t)(g * U + u) * 8u : kOOB;
+    }
+    const int s = s0 + c;
+    oy = s < S ? (uint32_t)(g * S + s) * 8u : kOOB;
   }
-  const int s = s0 + c;
-  const uint32_t oy = s < S ? (uint32_t)(g * S + s) * 8u : kOOB;
-  for (int b0 = 0; b0 < B; b0 += 4 * UNR) {
-    float2 h[UNR][W];
-    float2 y[UNR];
+};
+
+template <int W, int UNR = 8>
+struct BlockC32 {
+  static constexpr int ANT = 4 * UNR;  // antennas per block
+  float2 h[UNR][W];
+  float2 y[UNR];
+  template <bool DO_MF>
+  __device__ __forceinline__ void load(const SubC32<W>& sb, int b0) {
 #pragma unroll
     for (int t = 0; t < UNR; ++t) {
       const int b = b0 + 4 * t;
 #pragma unroll
-      for (int w = 0; w < W; ++w) h[t][w] = bload2(rh, oh[w], (uint32_t)b * U * 8u);
-      if (DO_MF) y[t] = bload2(ry, oy, (uint32_t)b * S * 8u);
+      for (int w = 0; w < W; ++w) h[t][w] = bload2(sb.rh, sb.oh[w], (uint32_t)b * sb.U * 8u);
+      if (DO_MF) y[t] = bload2(sb.ry, sb.oy, (uint32_t)b * sb.S * 8u);
     }
+  }
+  template <bool DO_GRAM, bool DO_MF>
+  __device__ __forceinline__ void mma(GramAcc<W>& acc) const {
 #pragma unroll
     for (int t = 0; t < UNR; ++t) {
       if (DO_GRAM) {
@@ -112,13 +130,16 @@ __device__ __forceinline__ void gram_mf_c32(const float2* __restrict__ Hn,
       }
     }
   }
-  if (DO_MF) {
+};
+
+// Re b = P1 + P2, Im b = P3 - P1 + P2 (complex64 matched filter)
+template <int W>
+__device__ __forceinline__ void finish_mf(InC32, GramAcc<W>& acc) {
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-      const f4 p1 = acc.dr[w], p2 = acc.di[w];
-      acc.dr[w] = p1 + p2;
-      acc.di[w] = acc.p3[w] - p1 + p2;
-    }
+  for (int w = 0; w < W; ++w) {
+    const f4 p1 = acc.dr[w], p2 = acc.di[w];
+    acc.dr[w] = p1 + p2;
+    acc.di[w] = acc.p3[w] - p1 + p2;
   }
 }
 
@@ -126,7 +147,7 @@ __device__ __forceinline__ void gram_mf_c32(const float2* __restrict__ Hn,
 // Blocked storage [B/8][2][C][8] (part 0 = Re, 1 = Im) of one subcarrier:
 // the 8 antennas of a block are contiguous for each column, so one 16-byte
 // load gives a lane the 8 k-values of a 16x16x32 MFMA operand.  Each MFMA
-// step covers 4 blocks (32 antennas), k-group g taking block 4 t + g.
+// step covers 4 blocks of 8 (32 antennas), k-group g taking block 4 t + g.
 template <typename V8>
 __device__ __forceinline__ V8 neg8(V8 x) {
   uint4 u = __builtin_bit_cast(uint4, x);
@@ -134,37 +155,49 @@ __device__ __forceinline__ V8 neg8(V8 x) {
   return __builtin_bit_cast(V8, u);
 }
 
-template <int W, bool DO_GRAM, bool DO_MF, typename V8>
-__device__ __forceinline__ void gram_mf_16(const uint16_t* __restrict__ Hn,
-                                           const uint16_t* __restrict__ Yn, int B, int U, int S,
-                                           int s0, int c, int g, GramAcc<W>& acc) {
-  constexpr int UNR = 2;
-  const int nblk = B >> 3;
-  const __amdgpu_buffer_rsrc_t rh = make_rsrc(Hn, (uint32_t)B * U * 4u);
-  const __amdgpu_buffer_rsrc_t ry = make_rsrc(Yn, DO_MF ? (uint32_t)B * S * 4u : 0u);
-  uint32_t oh[W];
+template <int W>
+struct Sub16 {
+  __amdgpu_buffer_rsrc_t rh, ry;
+  uint32_t oh[W], oy;
+  int U, S;
+  __device__ void init(const void* Hn, const void* Yn, int B, int U_, int S_, int s0, int c,
+                       int g) {
+    U = U_;
+    S = S_;
+    rh = make_rsrc(Hn, (uint32_t)B * U * 4u);
+    ry = make_rsrc(Yn ? Yn : Hn, Yn ? (uint32_t)B * S * 4u : 0u);
 #pragma unroll
-  for (int w = 0; w < W; ++w) {
-    const int u = 16 * w + c;
-    oh[w] = u < U ? (uint32_t)(2 * g * U + u) * 16u : kOOB;      // block g, part 0
+    for (int w = 0; w < W; ++w) {
+      const int u = 16 * w + c;
+      oh[w] = u < U ? (uint32_t)(2 * g * U + u) * 16u : kOOB;      // block g, part 0
+    }
+    const int s = s0 + c;
+    oy = s < S ? (uint32_t)(2 * g * S + s) * 16u : kOOB;
   }
-  const int s = s0 + c;
-  const uint32_t oy = s < S ? (uint32_t)(2 * g * S + s) * 16u : kOOB;
-  for (int k0 = 0; k0 < nblk; k0 += 4 * UNR) {
-    V8 hr[UNR][W], hi[UNR][W], yr[UNR], yi[UNR];
+};
+
+template <int W, typename V8, int UNR = 2>
+struct Block16 {
+  static constexpr int ANT = 32 * UNR;
+  V8 hr[UNR][W], hi[UNR][W], yr[UNR], yi[UNR];
+  template <bool DO_MF>
+  __device__ __forceinline__ void load(const Sub16<W>& sb, int b0) {
 #pragma unroll
     for (int t = 0; t < UNR; ++t) {
-      const uint32_t kb = (uint32_t)(k0 + 4 * t);          // first block of this step
+      const uint32_t kb = (uint32_t)((b0 >> 3) + 4 * t);     // first 8-antenna block of the step
 #pragma unroll
       for (int w = 0; w < W; ++w) {
-        hr[t][w] = __builtin_bit_cast(V8, bload4(rh, oh[w], kb * 2u * U * 16u));
-        hi[t][w] = __builtin_bit_cast(V8, bload4(rh, oh[w], (kb * 2u + 1u) * U * 16u));
+        hr[t][w] = __builtin_bit_cast(V8, bload4(sb.rh, sb.oh[w], kb * 2u * sb.U * 16u));
+        hi[t][w] = __builtin_bit_cast(V8, bload4(sb.rh, sb.oh[w], (kb * 2u + 1u) * sb.U * 16u));
       }
       if (DO_MF) {
-        yr[t] = __builtin_bit_cast(V8, bload4(ry, oy, kb * 2u * S * 16u));
-        yi[t] = __builtin_bit_cast(V8, bload4(ry, oy, (kb * 2u + 1u) * S * 16u));
+        yr[t] = __builtin_bit_cast(V8, bload4(sb.ry, sb.oy, kb * 2u * sb.S * 16u));
+        yi[t] = __builtin_bit_cast(V8, bload4(sb.ry, sb.oy, (kb * 2u + 1u) * sb.S * 16u));
       }
     }
+  }
+  template <bool DO_GRAM, bool DO_MF>
+  __device__ __forceinline__ void mma(GramAcc<W>& acc) const {
 #pragma unroll
     for (int t = 0; t < UNR; ++t) {
       if (DO_GRAM) {
@@ -190,29 +223,49 @@ __device__ __forceinline__ void gram_mf_16(const uint16_t* __restrict__ Hn,
       }
     }
   }
-}
+};
 
-// Input storage tags
-struct InC32 {};
-struct InF16 {};
-struct InBF16 {};
+template <int W>
+__device__ __forceinline__ void finish_mf(InF16, GramAcc<W>&) {}
+template <int W>
+__device__ __forceinline__ void finish_mf(InBF16, GramAcc<W>&) {}
 
-template <int W, bool DO_GRAM, bool DO_MF>
-__device__ __forceinline__ void gram_mf(InC32, const void* Hn, const void* Yn, int B, int U,
+// Storage traits: per-subcarrier descriptor and block types.
+template <typename IN, int W>
+struct Storage;
+template <int W>
+struct Storage<InC32, W> {
+  using Sub = SubC32<W>;
+  using Block = BlockC32<W, W == 1 ? 8 : 4>;
+  using SmallBlock = BlockC32<W, W == 1 ? 4 : 2>;
+};
+template <int W>
+struct Storage<InF16, W> {
+  using Sub = Sub16<W>;
+  using Block = Block16<W, h8, W == 1 ? 2 : 1>;
+  using SmallBlock = Block16<W, h8, 1>;
+};
+template <int W>
+struct Storage<InBF16, W> {
+  using Sub = Sub16<W>;
+  using Block = Block16<W, bf8, W == 1 ? 2 : 1>;
+  using SmallBlock = Block16<W, bf8, 1>;
+};
+
+// Whole Gram / matched filter of one subcarrier without cross-subcarrier
+// prefetch (used by the generic kernels).
+template <int W, bool DO_GRAM, bool DO_MF, typename IN>
+__device__ __forceinline__ void gram_mf(IN tag, const void* Hn, const void* Yn, int B, int U,
                                         int S, int s0, int c, int g, GramAcc<W>& acc) {
-  gram_mf_c32<W, DO_GRAM, DO_MF>((const float2*)Hn, (const float2*)Yn, B, U, S, s0, c, g, acc);
-}
-template <int W, bool DO_GRAM, bool DO_MF>
-__device__ __forceinline__ void gram_mf(InF16, const void* Hn, const void* Yn, int B, int U,
-                                        int S, int s0, int c, int g, GramAcc<W>& acc) {
-  gram_mf_16<W, DO_GRAM, DO_MF, h8>((const uint16_t*)Hn, (const uint16_t*)Yn, B, U, S, s0, c,
-                                    g, acc);
-}
-template <int W, bool DO_GRAM, bool DO_MF>
-__device__ __forceinline__ void gram_mf(InBF16, const void* Hn, const void* Yn, int B, int U,
-                                        int S, int s0, int c, int g, GramAcc<W>& acc) {
-  gram_mf_16<W, DO_GRAM, DO_MF, bf8>((const uint16_t*)Hn, (const uint16_t*)Yn, B, U, S, s0, c,
-                                     g, acc);
+  typename Storage<IN, W>::Sub sb;
+  sb.init(Hn, DO_MF ? Yn : nullptr, B, U, S, s0, c, g);
+  using Blk = typename Storage<IN, W>::Block;
+  for (int b0 = 0; b0 < B; b0 += Blk::ANT) {
+    Blk blk;
+    blk.template load<DO_MF>(sb, b0);
+    blk.template mma<DO_GRAM, DO_MF>(acc);
+  }
+  if (DO_MF) finish_mf(tag, acc);
 }
 
 template <typename IN>

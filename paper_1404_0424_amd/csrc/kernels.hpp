@@ -44,12 +44,36 @@ struct GramParams {
   float2* b;            // [n_sc][U][S] or null
 };
 
+// A kernel schedule: the kernel form of an operation and its grid.
+// blocks_per_cu = 0 launches one wavefront per subcarrier; k > 0 launches a
+// persistent grid of k blocks (4 wavefronts each) per compute unit that
+// loops over subcarriers.
+struct Schedule {
+  int variant;
+  int blocks_per_cu;
+};
+enum { kDetectGeneric = 0, kDetectStream = 1, kDetectStreamSmall = 2, kDetectVariants = 3 };
+enum { kPrecodeGeneric = 0, kPrecodeVariants = 1 };
+
+int num_compute_units();   // of the current device (cached per device)
+
+inline unsigned int sched_grid(int64_t n_sc, const Schedule& s) {
+  int64_t blocks = (n_sc + 3) / 4;
+  if (s.blocks_per_cu > 0) {
+    const int64_t cap = (int64_t)num_compute_units() * s.blocks_per_cu;
+    if (blocks > cap) blocks = cap;
+  }
+  if (blocks > (1 << 20)) blocks = 1 << 20;
+  if (blocks < 1) blocks = 1;
+  return (unsigned int)blocks;
+}
+
 hipError_t launch_detect_approx(const DetectParams& p, int in_dtype, int scalar_f64, int m_bits,
-                                hipStream_t stream);
+                                const Schedule& sch, hipStream_t stream);
 hipError_t launch_detect_exact(const DetectParams& p, int in_dtype, int scalar_f64, int m_bits,
                                hipStream_t stream);
 hipError_t launch_precode(const PrecodeParams& p, int in_dtype, int scalar_f64,
-                          hipStream_t stream);
+                          const Schedule& sch, hipStream_t stream);
 hipError_t launch_gram_mf(const GramParams& p, int in_dtype, hipStream_t stream);
 hipError_t launch_convert(const float2* src, uint16_t* dst, int dst_dtype, int64_t n, int R,
                           int C, hipStream_t stream);

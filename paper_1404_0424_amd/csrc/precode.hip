@@ -133,8 +133,15 @@ __global__ __launch_bounds__(256, 2) void precode_kernel(PrecodeParams prm) {
       float2 hn[W][4];                                 // next row tile, loaded ahead
 #pragma unroll
       for (int w = 0; w < W; ++w) load_h_row<W>(IN{}, Hn, B, U, 0, c, w, g, hn[w]);
+      // three real products per complex one: P1 = Hr Vr, P2 = Hi Vi,
+      // P3 = (Hr + Hi)(Vr + Vi); Re q = P1 - P2, Im q = P3 - P1 - P2
+      float vs[W][4];
+#pragma unroll
+      for (int w = 0; w < W; ++w)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) vs[w][t] = vv[w][t].x + vv[w][t].y;
       for (int b0 = 0; b0 < B; b0 += 16) {
-        f4 qr = zero4(), qi = zero4();
+        f4 p1 = zero4(), p2 = zero4(), p3 = zero4();
         float2 hc[W][4];
 #pragma unroll
         for (int w = 0; w < W; ++w)
@@ -147,12 +154,13 @@ __global__ __launch_bounds__(256, 2) void precode_kernel(PrecodeParams prm) {
           const float2(&hv)[4] = hc[w];
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
-            qr = mfma4(hv[t].x, vv[w][t].x, qr);
-            qi = mfma4(hv[t].x, vv[w][t].y, qi);
-            qr = mfma4(-hv[t].y, vv[w][t].y, qr);
-            qi = mfma4(hv[t].y, vv[w][t].x, qi);
+            p1 = mfma4(hv[t].x, vv[w][t].x, p1);
+            p2 = mfma4(hv[t].y, vv[w][t].y, p2);
+            p3 = mfma4(hv[t].x + hv[t].y, vs[w][t], p3);
           }
         }
+        const f4 qr = p1 - p2;
+        const f4 qi = p3 - p1 - p2;
         if (s < S) {
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
@@ -174,8 +182,9 @@ __global__ __launch_bounds__(256, 2) void precode_kernel(PrecodeParams prm) {
 }
 
 template <int W, typename IN>
-static hipError_t launch_st(const PrecodeParams& p, int f64, hipStream_t stream) {
-  const dim3 grid(wave_grid(p.n_sc)), block(kWave * kWavesPerBlock);
+static hipError_t launch_st(const PrecodeParams& p, int f64, const Schedule& sch,
+                            hipStream_t stream) {
+  const dim3 grid(sched_grid(p.n_sc, sch)), block(kWave * kWavesPerBlock);
   if (f64)
     hipLaunchKernelGGL((precode_kernel<W, IN, double>), grid, block, 0, stream, p);
   else
@@ -184,19 +193,20 @@ static hipError_t launch_st(const PrecodeParams& p, int f64, hipStream_t stream)
 }
 
 template <int W>
-static hipError_t launch_in(const PrecodeParams& p, int in_dtype, int f64, hipStream_t stream) {
+static hipError_t launch_in(const PrecodeParams& p, int in_dtype, int f64, const Schedule& sch,
+                            hipStream_t stream) {
   switch (in_dtype) {
-    case 0: return launch_st<W, InC32>(p, f64, stream);
-    case 1: return launch_st<W, InF16>(p, f64, stream);
-    case 2: return launch_st<W, InBF16>(p, f64, stream);
+    case 0: return launch_st<W, InC32>(p, f64, sch, stream);
+    case 1: return launch_st<W, InF16>(p, f64, sch, stream);
+    case 2: return launch_st<W, InBF16>(p, f64, sch, stream);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_precode(const PrecodeParams& p, int in_dtype, int scalar_f64,
-                          hipStream_t stream) {
-  if (p.U <= 16) return launch_in<1>(p, in_dtype, scalar_f64, stream);
-  return launch_in<2>(p, in_dtype, scalar_f64, stream);
+                          const Schedule& sch, hipStream_t stream) {
+  if (p.U <= 16) return launch_in<1>(p, in_dtype, scalar_f64, sch, stream);
+  return launch_in<2>(p, in_dtype, scalar_f64, sch, stream);
 }
 
 }  // namespace mimo

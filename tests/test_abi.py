@@ -115,3 +115,37 @@ def test_status_strings():
         assert lib.mimo_status_string(st)
     assert b"unknown" in lib.mimo_status_string(99)
     assert lib.mimo_version().startswith(b"mimo_cg")
+
+
+def test_schedule_table_validation_and_roundtrip():
+    import ctypes as C
+    lib = L.lib()
+    assert lib.mimo_tune_variant_count(L.MIMO_OP_DETECT) >= 1
+    names = [lib.mimo_tune_variant_name(L.MIMO_OP_DETECT, v)
+             for v in range(lib.mimo_tune_variant_count(L.MIMO_OP_DETECT))]
+    assert all(names) and names[0] == b"generic"
+    assert lib.mimo_tune_variant_name(L.MIMO_OP_DETECT, 99) is None
+    assert lib.mimo_tune_set(7, 0, 0, 0, 0) == L.MIMO_EINVAL
+    assert lib.mimo_tune_set(L.MIMO_OP_DETECT, 2, 0, 0, 0) == L.MIMO_EINVAL
+    assert lib.mimo_tune_set(L.MIMO_OP_DETECT, 0, 3, 0, 0) == L.MIMO_EINVAL
+    assert lib.mimo_tune_set(L.MIMO_OP_DETECT, 0, 0, 99, 0) == L.MIMO_EINVAL
+    assert lib.mimo_tune_set(L.MIMO_OP_DETECT, 0, 0, 0, 65) == L.MIMO_EINVAL
+    v0, b0 = C.c_int(), C.c_int()
+    assert lib.mimo_tune_get(L.MIMO_OP_DETECT, 1, 2, C.byref(v0), C.byref(b0)) == L.MIMO_OK
+    assert lib.mimo_tune_set(L.MIMO_OP_DETECT, 1, 2, 1, 3) == L.MIMO_OK
+    v, b = C.c_int(), C.c_int()
+    assert lib.mimo_tune_get(L.MIMO_OP_DETECT, 1, 2, C.byref(v), C.byref(b)) == L.MIMO_OK
+    assert (v.value, b.value) == (1, 3)
+    assert lib.mimo_tune_set(L.MIMO_OP_DETECT, 1, 2, v0.value, b0.value) == L.MIMO_OK
+
+
+def test_autotune_table_save_load(tmp_path):
+    from paper_1404_0424_amd import autotune
+    entries = [{"op": "detect", "user_class": 0, "dtype": 1,
+                "best": {"variant": 2, "blocks_per_cu": 4, "seconds": 1e-4}}]
+    p = tmp_path / "t.json"
+    before = autotune.get_schedule("detect", 8, 1)
+    autotune.save(entries, str(p))
+    assert autotune.load(str(p)) == 1
+    assert autotune.get_schedule("detect", 8, 1) == (2, 4)
+    autotune.set_schedule("detect", 8, 1, *before)

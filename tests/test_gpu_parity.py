@@ -260,3 +260,31 @@ def test_full_size_sampled(wl, frames):
     print(f"{wl} full size sampled: eps_x={ex:.2e} eps_L={el:.2e}")
     assert ex <= TOL_X and el <= TOL_L
     assert np.all(np.isfinite(host(out["llr"])))
+
+
+@pytest.mark.parametrize("case", [DETECT_CASES[4], DETECT_CASES[5], DETECT_CASES[7]],
+                         ids=["mixed_128x16", "mixed_128x32", "ragged_30x5_S17"])
+def test_schedules_give_identical_results(case):
+    """Every kernel variant and grid size computes the same per-system
+    arithmetic in the same order: outputs are bitwise equal."""
+    from paper_1404_0424_amd import autotune
+    name, n, B, U, S, m, K, snr, ch = case
+    f = _uplink(case)
+    d = W.downlink_frame(np.random.default_rng(3), n, B, U, S, m, snr, H=f.H)
+    H, Y, T = dev(f.H), dev(f.Y), dev(d.T)
+    saved = [autotune.get_schedule(op, U, 0) for op in ("detect", "precode")]
+    outs = []
+    try:
+        for v in range(len(autotune.variants("detect"))):
+            for bpc in (0, 1, 3):
+                autotune.set_schedule("detect", U, 0, v, bpc)
+                autotune.set_schedule("precode", U, 0, 0, bpc)
+                o = api().detect_cg(H, Y, f.n0, f.es, K, m, xhat=True)
+                q, _ = api().precode_cg(H, T, d.beta, K, True)
+                outs.append((host(o["llr"]), host(o["xhat"]), host(q)))
+    finally:
+        for op, (v, b) in zip(("detect", "precode"), saved):
+            autotune.set_schedule(op, U, 0, v, b)
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
