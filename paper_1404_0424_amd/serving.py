@@ -1,0 +1,354 @@
+"""Continuous-batching serving loop for uplink detection / downlink precoding.
+
+Requests (one OFDM frame each: all subcarriers x S symbols of one channel)
+arrive at any time through :meth:`Server.submit`.  A scheduler thread admits
+them in arrival order whenever a stream slot is free and the HBM budget has
+room for the request's buffers, and launches each admitted request on its
+own HIP stream, so requests that arrive while others are running overlap on
+the device.  Channel state (H, and its 16-bit copy when requested) stays on
+the device across frames, keyed by channel id; uplink and downlink share it
+by reciprocity (the precoder uses H_d = H_u^H).
+
+Latency is arrival to completion of the request's last kernel: completion
+times come from HIP events measured against a reference event whose host
+time was taken when the server started.
+
+The scheduling logic is independent of the GPU: an *executor* object does
+the device work (``GpuExecutor`` here), so the admission and ordering rules
+can be exercised with any executor that implements the same methods.
+"""
+from __future__ import annotations
+
+import collections
+import concurrent.futures as cf
+import dataclasses
+import threading
+import time
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class UplinkRequest:
+    ch_id: object
+    Y: object                 # device complex64 tensor (n_sc, B, S) or numpy array
+    n0: float
+    es: float
+    qam_bits: int
+    K: int
+    sinr_mode: str = "approx"
+    scalar_prec: str = "f32"
+    want_xhat: bool = False
+
+
+@dataclasses.dataclass
+class DownlinkRequest:
+    ch_id: object
+    T: object                 # device complex64 tensor (n_sc, U, S) or numpy array
+    beta: float
+    K: int
+    normalize: bool = True
+    scalar_prec: str = "f32"
+
+
+@dataclasses.dataclass
+class Result:
+    outputs: dict             # device tensors (llr / xhat or Q / qnorm)
+    t_submit: float
+    t_admit: float
+    t_done: float
+    solves: int
+    llr_bits: int
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_submit
+
+
+class AdmissionError(RuntimeError):
+    """A request can never fit the HBM budget."""
+
+
+@dataclasses.dataclass
+class _Pending:
+    req: object
+    fut: cf.Future
+    t_submit: float
+    need: int
+    ready: object = None
+
+
+class Server:
+    """FIFO continuous batching over ``n_slots`` concurrent streams within
+    ``hbm_budget`` bytes (channel cache included)."""
+
+    def __init__(self, executor, hbm_budget: int = 16 << 30, n_slots: int = 4,
+                 poll_interval: float = 20e-6):
+        self.ex = executor
+        self.budget = int(hbm_budget)
+        self.n_slots = n_slots
+        self.poll_interval = poll_interval
+        self._lock = threading.Condition()
+        self._queue: collections.deque[_Pending] = collections.deque()
+        self._inflight: list = []          # (pending, handle, slot)
+        self._free_slots = list(range(n_slots))
+        self._reserved = 0                 # bytes of admitted requests
+        self._channels: dict = {}          # ch_id -> bytes
+        self._done: list[Result] = []
+        self._running = True
+        self._t_first = None
+        self.peak_bytes = 0                # largest reserved + cached bytes seen
+        self.admit_order: list = []        # ids of requests in admission order
+        self._thread = threading.Thread(target=self._loop, name="mimo-serving", daemon=True)
+        self._thread.start()
+
+    # ------------------------------------------------------------ channels
+    def register_channel(self, ch_id, H, dtype: str = "c32") -> None:
+        """Keep H (n_sc, B, U) on the device for later requests."""
+        with self._lock:
+            need = self.ex.channel_bytes(H, dtype)
+            old = self._channels.get(ch_id, 0)
+            if self._cache_bytes() - old + need + self._reserved > self.budget:
+                raise AdmissionError(f"channel {ch_id!r} ({need} B) exceeds the HBM budget")
+            self.ex.register_channel(ch_id, H, dtype)
+            self._channels[ch_id] = need
+
+    def unregister_channel(self, ch_id) -> None:
+        with self._lock:
+            self.ex.unregister_channel(ch_id)
+            self._channels.pop(ch_id, None)
+            self._lock.notify_all()
+
+    def _cache_bytes(self) -> int:
+        return sum(self._channels.values())
+
+    # ------------------------------------------------------------ requests
+    def submit(self, req) -> cf.Future:
+        fut: cf.Future = cf.Future()
+        t = self.ex.now()
+        with self._lock:
+            if req.ch_id not in self._channels:
+                fut.set_exception(KeyError(f"channel {req.ch_id!r} is not registered"))
+                return fut
+            need = self.ex.request_bytes(req)
+            if need + self._cache_bytes() > self.budget:
+                fut.set_exception(AdmissionError(
+                    f"request needs {need} B, budget {self.budget} B minus cache "
+                    f"{self._cache_bytes()} B"))
+                return fut
+            if self._t_first is None:
+                self._t_first = t
+            ready = self.ex.on_submit(req) if hasattr(self.ex, "on_submit") else None
+            self._queue.append(_Pending(req, fut, t, need, ready))
+            self._lock.notify_all()
+        return fut
+
+    def drain(self, timeout: float | None = None) -> None:
+        """Wait until every submitted request has completed."""
+        deadline = None if timeout is None else time.perf_counter() + timeout
+        with self._lock:
+            while self._queue or self._inflight:
+                left = None if deadline is None else deadline - time.perf_counter()
+                if left is not None and left <= 0:
+                    raise TimeoutError("serving queue did not drain")
+                self._lock.wait(timeout=0.001 if left is None else min(left, 0.001))
+
+    def close(self) -> None:
+        self.drain()
+        with self._lock:
+            self._running = False
+            self._lock.notify_all()
+        self._thread.join()
+
+    # ------------------------------------------------------------ stats
+    def stats(self, reset: bool = False) -> dict:
+        with self._lock:
+            done = list(self._done)
+            if reset:
+                self._done.clear()
+                self._t_first = None
+        if not done:
+            return {"frames": 0}
+        lat = np.array([r.latency for r in done])
+        t0 = min(r.t_submit for r in done)
+        t1 = max(r.t_done for r in done)
+        span = max(t1 - t0, 1e-12)
+        return {"frames": len(done),
+                "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                "mean_ms": float(lat.mean() * 1e3),
+                "frames_per_s": len(done) / span,
+                "solves_per_s": sum(r.solves for r in done) / span,
+                "llr_gbit_s": sum(r.llr_bits for r in done) / span / 1e9}
+
+    # ------------------------------------------------------------ scheduler
+    def _loop(self) -> None:
+        while True:
+            with self._lock:
+                if not self._running:
+                    return
+                self._admit_locked()
+                busy = bool(self._inflight)
+                if not busy and not self._queue:
+                    self._lock.wait(timeout=0.01)
+                    continue
+            self._poll()
+            time.sleep(self.poll_interval)
+
+    def _admit_locked(self) -> None:
+        # strict arrival order: the head waits until it fits (no overtaking)
+        while self._queue and self._free_slots:
+            head = self._queue[0]
+            if self._reserved + head.need + self._cache_bytes() > self.budget:
+                return
+            self._queue.popleft()
+            slot = self._free_slots.pop(0)
+            self._reserved += head.need
+            self.peak_bytes = max(getattr(self, "peak_bytes", 0), self._reserved + self._cache_bytes())
+            self.admit_order.append(id(head.req))
+            t_admit = self.ex.now()
+            try:
+                handle = self.ex.launch(head.req, slot, head.ready)
+            except Exception as e:          # noqa: BLE001 - reported through the future
+                self._reserved -= head.need
+                self._free_slots.append(slot)
+                head.fut.set_exception(e)
+                continue
+            self._inflight.append((head, handle, slot, t_admit))
+
+    def _poll(self) -> None:
+        finished = []
+        with self._lock:
+            for item in list(self._inflight):
+                pend, handle, slot, t_admit = item
+                if self.ex.done(handle):
+                    self._inflight.remove(item)
+                    self._reserved -= pend.need
+                    self._free_slots.append(slot)
+                    finished.append(item)
+            if finished:
+                self._lock.notify_all()
+        for pend, handle, slot, t_admit in finished:
+            try:
+                outputs, t_done, solves, bits = self.ex.finish(handle)
+                res = Result(outputs, pend.t_submit, t_admit, t_done, solves, bits)
+                with self._lock:
+                    self._done.append(res)
+                pend.fut.set_result(res)
+            except Exception as e:          # noqa: BLE001
+                pend.fut.set_exception(e)
+
+
+class GpuExecutor:
+    """Device work for :class:`Server` through the C ABI, one HIP stream per
+    slot (all at default priority)."""
+
+    def __init__(self, n_slots: int = 4, device: int = 0):
+        import torch
+
+        from . import api
+        self.torch = torch
+        self.api = api
+        self.dev = torch.device("cuda", device)
+        self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(n_slots)]
+        self.channels: dict = {}
+        # host/device clock alignment: a reference event whose host time is
+        # bracketed as tightly as possible (best of several round trips)
+        best = None
+        for _ in range(20):
+            ev = torch.cuda.Event(enable_timing=True)
+            ta = time.perf_counter()
+            ev.record()
+            ev.synchronize()
+            tb = time.perf_counter()
+            if best is None or tb - ta < best[2] - best[1]:
+                best = (ev, ta, tb)
+        self._ref, ta, tb = best
+        self._t_ref = 0.5 * (ta + tb)
+
+    def now(self) -> float:
+        return time.perf_counter()
+
+    def _dev_c64(self, x):
+        t = self.torch
+        if isinstance(x, np.ndarray):
+            return t.from_numpy(np.ascontiguousarray(x.astype(np.complex64))).to(self.dev)
+        return x
+
+    def channel_bytes(self, H, dtype: str) -> int:
+        n = int(np.prod(H.shape))
+        return n * (8 if dtype == "c32" else 4)
+
+    def register_channel(self, ch_id, H, dtype: str) -> None:
+        Hd = self._dev_c64(H)
+        if dtype == "c32":
+            self.channels[ch_id] = (Hd, dtype)
+        else:
+            self.channels[ch_id] = (self.api.convert(Hd, dtype), dtype)
+        self.torch.cuda.synchronize(self.dev)
+
+    def unregister_channel(self, ch_id) -> None:
+        self.channels.pop(ch_id, None)
+
+    def _shape(self, ch_id):
+        H, dtype = self.channels[ch_id]
+        if dtype == "c32":
+            return tuple(H.shape), dtype
+        return (H.n, H.R, H.C), dtype
+
+    def request_bytes(self, req) -> int:
+        (n, B, U), dtype = self._shape(req.ch_id)
+        if isinstance(req, UplinkRequest):
+            S = req.Y.shape[2]
+            b = 4 * n * U * S * req.qam_bits + (8 * n * U * S if req.want_xhat else 0)
+            if isinstance(req.Y, np.ndarray):
+                b += 8 * n * B * S
+            if dtype != "c32":
+                b += 4 * n * B * S
+            return b
+        S = req.T.shape[2]
+        b = 8 * n * B * S + 4 * n * S
+        if isinstance(req.T, np.ndarray):
+            b += 8 * n * U * S
+        return b
+
+    def on_submit(self, req):
+        """Called at submission: device inputs written on the caller's stream
+        must be complete before the slot stream reads them."""
+        ev = self.torch.cuda.Event()
+        ev.record()
+        return ev
+
+    def launch(self, req, slot: int, ready=None):
+        t = self.torch
+        H, dtype = self.channels[req.ch_id]
+        st = self.streams[slot]
+        if ready is not None:
+            st.wait_event(ready)
+        with t.cuda.stream(st):
+            if isinstance(req, UplinkRequest):
+                Y = self._dev_c64(req.Y)
+                if dtype != "c32":
+                    Y = self.api.convert(Y, dtype, stream=st)
+                out = self.api.detect_cg(H, Y, req.n0, req.es, req.K, req.qam_bits,
+                                         req.sinr_mode, req.scalar_prec, xhat=req.want_xhat,
+                                         stream=st)
+                n, U, S, m = out["llr"].shape
+                work = (n * S, n * S * U * m)
+            else:
+                T = self._dev_c64(req.T)
+                Q, qn = self.api.precode_cg(H, T, req.beta, req.K, req.normalize,
+                                            req.scalar_prec, stream=st)
+                out = {"Q": Q, "qnorm": qn}
+                work = (T.shape[0] * T.shape[2], 0)
+            ev = t.cuda.Event(enable_timing=True)
+            ev.record(st)
+        return (ev, out, work, (req,))        # request kept alive until completion
+
+    def done(self, handle) -> bool:
+        return handle[0].query()
+
+    def finish(self, handle):
+        ev, out, work, _ = handle
+        t_done = self._t_ref + self._ref.elapsed_time(ev) / 1e3
+        return out, t_done, work[0], work[1]

@@ -221,3 +221,46 @@ WORKLOADS = {
                             channel="kronecker", rho_bs=0.5, rho_ue=0.2,
                             scalar_f64=True),
 }
+
+
+# --------------------------------------------------------------------------
+# serving stream: Poisson arrivals of mixed-shape uplink/downlink frames
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class StreamChannel:
+    ch_id: int
+    B: int
+    U: int
+    n_sc: int
+    H: np.ndarray           # (n_sc, B, U)
+
+
+@dataclasses.dataclass
+class StreamFrame:
+    t_arrival: float        # seconds from stream start
+    ch_id: int
+    uplink: bool
+    m: int                  # bits per symbol
+    snr_db: float
+
+
+def serving_stream(rng: np.random.Generator, n_channels: int, n_frames: int, rate: float,
+                   B_set=(64, 128, 256), U_set=(8, 16, 32), n_sc_range=(300, 1200),
+                   m_set=(4, 6, 8), snr_range=(5.0, 25.0), uplink_share: float = 0.5):
+    """Channels with B, U drawn from the sets and n_sc uniform in the range;
+    frames with exponential inter-arrival times at `rate` frames/s (rate <= 0:
+    all arrive at t = 0), a channel uniformly at random, QAM and SNR drawn
+    per frame, uplink with probability `uplink_share`."""
+    chans = []
+    for c in range(n_channels):
+        B = int(rng.choice(B_set))
+        U = int(rng.choice(U_set))
+        n_sc = int(rng.integers(n_sc_range[0], n_sc_range[1] + 1))
+        chans.append(StreamChannel(c, B, U, n_sc, iid_channel(rng, n_sc, B, U)))
+    gaps = (rng.exponential(1.0 / rate, n_frames) if rate > 0 else np.zeros(n_frames))
+    t = np.cumsum(gaps) - (gaps[0] if n_frames else 0.0)
+    frames = [StreamFrame(float(t[i]), int(rng.integers(n_channels)),
+                          bool(rng.random() < uplink_share), int(rng.choice(m_set)),
+                          float(rng.uniform(*snr_range))) for i in range(n_frames)]
+    return chans, frames

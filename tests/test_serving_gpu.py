@@ -1,0 +1,102 @@
+"""Serving loop on the GPU: each result is the same alone and in a mix of
+concurrent mixed-shape requests (bitwise: per-system arithmetic does not
+depend on what else runs), matches the oracle, and a small HBM budget makes
+requests wait without ever exceeding it."""
+import numpy as np
+import pytest
+
+from oracle import mimo_oracle as O
+from paper_1404_0424_amd import workload as W
+
+from _parity import TOL_L, TOL_X, dev, host, llr_err, rel_err_vec
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+SHAPES = [(64, 8, 48), (128, 16, 64), (256, 32, 24), (128, 8, 80), (64, 16, 40), (256, 16, 32)]
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1404_0424_amd import serving as SV
+    rng = np.random.default_rng(2024)
+    chans = {i: W.iid_channel(rng, n, B, U) for i, (B, U, n) in enumerate(SHAPES)}
+    return SV, rng, chans
+
+
+def _uplink(SV, rng, H, ch, m=6, snr=12.0, S=14):
+    n, B, U = H.shape
+    bits = W.random_bits(rng, (n, U, S), m)
+    n0 = W.n0_from_snr_db(snr, U, B)
+    Y = H @ W.qam_map(bits, m) + W.awgn(rng, (n, B, S), n0)
+    return SV.UplinkRequest(ch, dev(Y), n0, 1.0, m, 3), Y
+
+
+def _downlink(SV, rng, H, ch, S=14):
+    n, B, U = H.shape
+    T = W.qam_map(W.random_bits(rng, (n, U, S), 4), 4)
+    return SV.DownlinkRequest(ch, dev(T), 0.3, 3, True), T
+
+
+def test_alone_vs_mix_and_oracle(setup):
+    SV, rng, chans = setup
+    ex = SV.GpuExecutor(n_slots=4)
+    srv = SV.Server(ex, hbm_budget=8 << 30, n_slots=4)
+    for i, H in chans.items():
+        srv.register_channel(i, H, "c32")
+    up, Y = _uplink(SV, rng, chans[1], 1)
+    dn, T = _downlink(SV, rng, chans[2], 2)
+    alone_up = host(srv.submit(up).result(timeout=60).outputs["llr"])
+    alone_dn = host(srv.submit(dn).result(timeout=60).outputs["Q"])
+    futs = []
+    for k in range(24):
+        ch = int(rng.integers(len(chans)))
+        r = _uplink(SV, rng, chans[ch], ch)[0] if k % 2 else _downlink(SV, rng, chans[ch], ch)[0]
+        futs.append(srv.submit(r))
+        if k == 9:
+            f_up = srv.submit(up)
+        if k == 15:
+            f_dn = srv.submit(dn)
+    mix_up = host(f_up.result(timeout=60).outputs["llr"])
+    mix_dn = host(f_dn.result(timeout=60).outputs["Q"])
+    for f in futs:
+        res = f.result(timeout=60)
+        for v in res.outputs.values():
+            if v is not None:
+                assert torch.isfinite(v).all()
+    srv.close()
+    assert np.array_equal(alone_up, mix_up)
+    assert np.array_equal(alone_dn, mix_dn)
+    ref = O.detect_cg(chans[1], Y, up.n0, 1.0, 3, 6)
+    assert llr_err(alone_up, ref["llr"]) <= TOL_L
+    pref = O.precode_cg(chans[2], T, 0.3, 3, normalize=True)
+    assert rel_err_vec(alone_dn, pref["Q"], axis=1) <= TOL_X
+    st = srv.stats()
+    assert st["frames"] == 28 and st["p99_ms"] >= st["p50_ms"] > 0
+
+
+def test_small_budget_waits_and_16bit_channels(setup):
+    SV, rng, chans = setup
+    ex = SV.GpuExecutor(n_slots=4)
+    H = chans[1]
+    cache = ex.channel_bytes(H, "f16")
+    req, Y = _uplink(SV, rng, H, "h16")
+    srv = SV.Server(ex, hbm_budget=10 ** 9, n_slots=4)
+    srv.register_channel("h16", H, "f16")
+    need = ex.request_bytes(req)
+    srv.close()
+    srv = SV.Server(ex, hbm_budget=cache + 2 * need, n_slots=4)   # two requests at a time
+    srv.register_channel("h16", H, "f16")
+    futs = [srv.submit(_uplink(SV, rng, H, "h16")[0]) for _ in range(8)]
+    f0 = srv.submit(req)
+    for f in futs:
+        f.result(timeout=60)
+    out = host(f0.result(timeout=60).outputs["llr"])
+    srv.close()
+    assert srv.peak_bytes <= cache + 2 * need
+    deq = O.dequantize_f16(O.quantize_f16(H))
+    Yq = O.dequantize_f16(O.quantize_f16(Y))
+    ref = O.detect_cg(deq, Yq, req.n0, 1.0, 3, 6)
+    assert llr_err(out, ref["llr"]) <= TOL_L
