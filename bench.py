@@ -299,17 +299,20 @@ def serving_leg(n_frames):
         t0 = time.perf_counter()
         for f, r in zip(frames, reqs):
             target = t0 + f.t_arrival
-            while True:
+            while True:                      # wait for the arrival time, yielding the GIL
                 d = target - time.perf_counter()
                 if d <= 0:
                     break
-                if d > 3e-4:
-                    time.sleep(d - 2e-4)
+                time.sleep(d - 1e-4 if d > 2e-4 else 0)
             srv.submit(r)
         srv.drain(timeout=120)
         st = srv.stats()
+        st["mean_batch"] = float(np.mean(srv.batch_sizes[-len(frames):])) if srv.batch_sizes else 0
         srv.close()
         return st
+
+    old_switch = sys.getswitchinterval()
+    sys.setswitchinterval(2e-5)              # submitter and scheduler threads share the GIL
 
     sat = run(0.0, n_frames)
     log(f"serving saturation: {sat['frames_per_s']:.0f} frames/s, p50 {sat['p50_ms']:.3f} ms, "
@@ -323,6 +326,7 @@ def serving_leg(n_frames):
         log(f"serving load {load}: offered {load * sat['frames_per_s']:.0f}/s, achieved "
             f"{st['frames_per_s']:.0f}/s, p50 {st['p50_ms']:.3f} ms, p99 {st['p99_ms']:.3f} ms")
         out[f"load_{load}"] = st
+    sys.setswitchinterval(old_switch)
     return out
 
 

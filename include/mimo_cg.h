@@ -150,6 +150,41 @@ int mimo_convert(const void* src, void* dst, int dst_dtype, int64_t n,
                  int32_t R, int32_t C, void* stream);
 
 /*
+ * Batched calls: up to MIMO_MAX_BATCH frames of different shapes in one
+ * kernel launch (the serving loop's continuous batching).  Each frame is an
+ * independent problem exactly as in mimo_detect_cg / mimo_precode_cg; all
+ * frames of one call share in_dtype, qam_bits (detection) and scalar_prec.
+ * Detection uses the approximate SINR of eq. (13)-(15).  Every frame is
+ * validated before anything is enqueued; a frame with n_sc = 0 is skipped.
+ * The descriptor array is read during the call only.
+ *   detection:  H [n_sc][B][U], Y [n_sc][B][S] (storage in_dtype),
+ *               out = llr float [n_sc][U][S][qam_bits],
+ *               out2 = xhat complex64 [n_sc][U][S] or NULL; uses n0, es
+ *   precoding:  H [n_sc][B][U] (storage in_dtype), Y = T complex64
+ *               [n_sc][U][S], out = Q complex64 [n_sc][B][S],
+ *               out2 = qnorm float [n_sc][S] or NULL; uses beta, normalize
+ * Results are bitwise identical to the corresponding single-frame calls.
+ */
+#define MIMO_MAX_BATCH 32
+
+typedef struct mimo_frame {
+  int64_t n_sc;
+  int32_t B, U, S, K;
+  const void* H;
+  const void* Y;
+  void* out;
+  void* out2;
+  float n0, es;          /* detection */
+  float beta;            /* precoding */
+  int32_t normalize;     /* precoding */
+} mimo_frame;
+
+int mimo_detect_cg_batch(const mimo_frame* frames, int n_frames, int in_dtype, int qam_bits,
+                         int scalar_prec, void* stream);
+int mimo_precode_cg_batch(const mimo_frame* frames, int n_frames, int in_dtype,
+                          int scalar_prec, void* stream);
+
+/*
  * Kernel schedules (not part of the paper's method: how the same arithmetic
  * is mapped onto the GPU).  Each operation has kernel variants and a grid
  * size; the pair used for (op, user class, storage type) comes from a

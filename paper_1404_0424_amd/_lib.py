@@ -24,6 +24,17 @@ class MimoShape(ctypes.Structure):
                 ("K", ctypes.c_int32), ("n_sc", ctypes.c_int64)]
 
 
+MIMO_MAX_BATCH = 32
+
+
+class MimoFrame(ctypes.Structure):
+    _fields_ = [("n_sc", ctypes.c_int64), ("B", ctypes.c_int32), ("U", ctypes.c_int32),
+                ("S", ctypes.c_int32), ("K", ctypes.c_int32), ("H", ctypes.c_void_p),
+                ("Y", ctypes.c_void_p), ("out", ctypes.c_void_p), ("out2", ctypes.c_void_p),
+                ("n0", ctypes.c_float), ("es", ctypes.c_float), ("beta", ctypes.c_float),
+                ("normalize", ctypes.c_int32)]
+
+
 class MimoError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"[{status}] {message}")
@@ -47,6 +58,8 @@ _SIGNATURES = {
     "mimo_status_string": (ctypes.c_char_p, [_i]),
     "mimo_last_error": (ctypes.c_char_p, []),
     "mimo_version": (ctypes.c_char_p, []),
+    "mimo_detect_cg_batch": (_i, [ctypes.c_void_p, _i, _i, _i, _i, _vp]),
+    "mimo_precode_cg_batch": (_i, [ctypes.c_void_p, _i, _i, _i, _vp]),
     "mimo_tune_set": (_i, [_i, _i, _i, _i, _i]),
     "mimo_tune_get": (_i, [_i, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "mimo_tune_variant_count": (_i, [_i]),

@@ -159,3 +159,60 @@ def workspace_bytes(B, U, S, K, n_sc, op: str = "detect", sinr_mode: str = "appr
            "precode": L.MIMO_OP_PRECODE}[op]
     mode = {"approx": L.MIMO_SINR_APPROX, "exact": L.MIMO_SINR_EXACT}[sinr_mode]
     return int(L.lib().mimo_workspace_bytes(L.shape(B, U, S, K, n_sc), opc, mode))
+
+
+def detect_cg_batch(frames, K: int | list, qam_bits: int, scalar_prec: str = "f32",
+                    xhat: bool = False, stream=None) -> list[dict]:
+    """Detect up to MIMO_MAX_BATCH frames of different shapes in one launch.
+    ``frames`` is a list of (H, Y, n0, es) with the same storage type; K is
+    one value or one per frame.  Returns one output dict per frame."""
+    if not frames:
+        return []
+    Ks = K if isinstance(K, (list, tuple)) else [K] * len(frames)
+    arr = (L.MimoFrame * len(frames))()
+    outs, code0 = [], None
+    for i, ((H, Y, n0, es), k) in enumerate(zip(frames, Ks)):
+        hp, code, n, B, U = _channel(H)
+        if code0 is None:
+            code0 = code
+        elif code != code0:
+            raise ValueError("all frames of a batch need the same storage type")
+        yp, S = _rhs(Y, code, n, B)
+        dev = H.device
+        llr = torch.empty((n, U, S, qam_bits), dtype=torch.float32, device=dev)
+        xh = torch.empty((n, U, S), dtype=torch.complex64, device=dev) if xhat else None
+        arr[i] = L.MimoFrame(n, B, U, S, int(k), hp, yp, llr.data_ptr(), _ptr(xh),
+                             float(n0), float(es), 0.0, 0)
+        outs.append({"llr": llr, "xhat": xh} if xhat else {"llr": llr})
+    prec = {"f32": L.MIMO_SCALAR_F32, "f64": L.MIMO_SCALAR_F64}[scalar_prec]
+    L.check(L.lib().mimo_detect_cg_batch(ctypes.addressof(arr), len(frames), code0,
+                                         int(qam_bits), prec, _stream(stream)))
+    return outs
+
+
+def precode_cg_batch(frames, K: int | list, scalar_prec: str = "f32", qnorm: bool = False,
+                     stream=None) -> list[tuple]:
+    """Precode up to MIMO_MAX_BATCH frames in one launch.  ``frames`` is a
+    list of (H, T, beta, normalize).  Returns (Q, qnorm) per frame."""
+    if not frames:
+        return []
+    Ks = K if isinstance(K, (list, tuple)) else [K] * len(frames)
+    arr = (L.MimoFrame * len(frames))()
+    outs, code0 = [], None
+    for i, ((H, T, beta, normalize), k) in enumerate(zip(frames, Ks)):
+        hp, code, n, B, U = _channel(H)
+        if code0 is None:
+            code0 = code
+        elif code != code0:
+            raise ValueError("all frames of a batch need the same storage type")
+        _check_c64(T, "T")
+        S = T.shape[2]
+        Q = torch.empty((n, B, S), dtype=torch.complex64, device=T.device)
+        qn = torch.empty((n, S), dtype=torch.float32, device=T.device) if qnorm else None
+        arr[i] = L.MimoFrame(n, B, U, S, int(k), hp, T.data_ptr(), Q.data_ptr(), _ptr(qn),
+                             0.0, 0.0, float(beta), int(bool(normalize)))
+        outs.append((Q, qn))
+    prec = {"f32": L.MIMO_SCALAR_F32, "f64": L.MIMO_SCALAR_F64}[scalar_prec]
+    L.check(L.lib().mimo_precode_cg_batch(ctypes.addressof(arr), len(frames), code0, prec,
+                                          _stream(stream)))
+    return outs

@@ -98,6 +98,12 @@ int variant_count(int op) {
   return 0;
 }
 
+// Level unit of square 2^qam_bits-QAM with average energy es.
+float qam_scale(float es, int qam_bits) {
+  const int M = 1 << qam_bits;
+  return std::sqrt(es * 3.0f / (2.0f * (float)(M - 1)));
+}
+
 #define CHECK(x)              \
   do {                        \
     const int st_ = (x);      \
@@ -229,8 +235,7 @@ int mimo_detect_cg(const mimo_shape* shape, const void* H, const void* Y, int in
   if (need > 0 && (!workspace || workspace_bytes < need))
     return fail(MIMO_EWORKSPACE, "workspace needs %zu bytes", need);
   if (shape->n_sc == 0) return MIMO_OK;
-  const int M = 1 << qam_bits;
-  const float scale = std::sqrt(es * 3.0f / (2.0f * (float)(M - 1)));
+  const float scale = qam_scale(es, qam_bits);
   mimo::DetectParams p{H, Y, shape->B, shape->U, shape->S, shape->K, shape->n_sc,
                        n0 / es, n0, es, scale, 1.0f / scale,
                        llr, (float2*)xhat, mu, sinr};
@@ -266,6 +271,103 @@ int mimo_precode_cg(const mimo_shape* shape, const void* H, const void* T, int i
                                          get_sched(MIMO_OP_PRECODE, shape->U, in_dtype),
                                          (hipStream_t)stream),
                     "precode_cg launch");
+}
+
+// Prefix the message of a failed check with the frame index.
+static int frame_fail(int status, int i) {
+  char msg[sizeof(g_last_error)];
+  std::memcpy(msg, g_last_error, sizeof(msg));
+  return fail(status, "frame %d: %s", i, msg);
+}
+
+static int check_frame(const mimo_frame& f, int i, int in_dtype, bool detect) {
+  mimo_shape sh{f.B, f.U, f.S, f.K, f.n_sc};
+  int st = check_shape(&sh, true);
+  if (st == MIMO_OK) st = check_dtype(in_dtype, f.B);
+  if (st == MIMO_OK) st = check_ptr(f.H, "H", true);
+  if (st == MIMO_OK) st = check_ptr(f.Y, detect ? "Y" : "T", true);
+  if (st == MIMO_OK) st = check_ptr(f.out, detect ? "llr" : "Q", true);
+  if (st == MIMO_OK) st = check_ptr(f.out2, "out2", false);
+  if (st != MIMO_OK) return frame_fail(st, i);
+  if (detect) {
+    if (!(f.n0 > 0.f) || !std::isfinite(f.n0) || !(f.es > 0.f) || !std::isfinite(f.es))
+      return fail(MIMO_EINVAL, "frame %d: n0=%g es=%g must be > 0", i, f.n0, f.es);
+  } else if (!(f.beta >= 0.f) || !std::isfinite(f.beta)) {
+    return fail(MIMO_EINVAL, "frame %d: beta=%g must be >= 0", i, f.beta);
+  }
+  return MIMO_OK;
+}
+
+static int build_batch(const mimo_frame* frames, int n_frames, int in_dtype, bool detect,
+                       int qam_bits, mimo::BatchArgs& a, int& max_u) {
+  if (!frames && n_frames > 0) return fail(MIMO_EINVAL, "frames is NULL");
+  if (n_frames < 0 || n_frames > MIMO_MAX_BATCH)
+    return fail(MIMO_EINVAL, "n_frames=%d outside [0, %d]", n_frames, MIMO_MAX_BATCH);
+  std::memset(&a, 0, sizeof(a));
+  max_u = 1;
+  for (int i = 0; i < n_frames; ++i) {
+    const mimo_frame& f = frames[i];
+    CHECK(check_frame(f, i, in_dtype, detect));
+    if (f.n_sc == 0) continue;
+    mimo::FrameArgs& d = a.f[a.n++];
+    d.H = f.H;
+    d.Y = f.Y;
+    d.out = f.out;
+    d.out2 = f.out2;
+    d.sc_begin = a.total;
+    d.n_sc = f.n_sc;
+    d.B = f.B;
+    d.U = f.U;
+    d.S = f.S;
+    d.K = f.K;
+    if (detect) {
+      d.n0 = f.n0;
+      d.es = f.es;
+      d.reg = f.n0 / f.es;
+      d.scale = qam_scale(f.es, qam_bits);
+      d.inv_scale = 1.0f / d.scale;
+    } else {
+      d.beta = f.beta;
+      d.normalize = f.normalize ? 1 : 0;
+    }
+    a.total += f.n_sc;
+    if (f.U > max_u) max_u = f.U;
+  }
+  return MIMO_OK;
+}
+
+int mimo_detect_cg_batch(const mimo_frame* frames, int n_frames, int in_dtype, int qam_bits,
+                         int scalar_prec, void* stream) {
+  g_last_error[0] = 0;
+  if (qam_bits != 2 && qam_bits != 4 && qam_bits != 6 && qam_bits != 8)
+    return fail(MIMO_EUNSUPPORTED, "qam_bits=%d not in {2,4,6,8}", qam_bits);
+  if (scalar_prec != MIMO_SCALAR_F32 && scalar_prec != MIMO_SCALAR_F64)
+    return fail(MIMO_EINVAL, "scalar_prec=%d unknown", scalar_prec);
+  static thread_local mimo::BatchArgs a;
+  int max_u = 1;
+  CHECK(build_batch(frames, n_frames, in_dtype, true, qam_bits, a, max_u));
+  if (a.n == 0) return MIMO_OK;
+  return hip_status(mimo::launch_detect_batch(a, max_u, in_dtype,
+                                              scalar_prec == MIMO_SCALAR_F64, qam_bits,
+                                              get_sched(MIMO_OP_DETECT, max_u, in_dtype),
+                                              (hipStream_t)stream),
+                    "detect_cg_batch launch");
+}
+
+int mimo_precode_cg_batch(const mimo_frame* frames, int n_frames, int in_dtype,
+                          int scalar_prec, void* stream) {
+  g_last_error[0] = 0;
+  if (scalar_prec != MIMO_SCALAR_F32 && scalar_prec != MIMO_SCALAR_F64)
+    return fail(MIMO_EINVAL, "scalar_prec=%d unknown", scalar_prec);
+  static thread_local mimo::BatchArgs a;
+  int max_u = 1;
+  CHECK(build_batch(frames, n_frames, in_dtype, false, 0, a, max_u));
+  if (a.n == 0) return MIMO_OK;
+  return hip_status(mimo::launch_precode_batch(a, max_u, in_dtype,
+                                               scalar_prec == MIMO_SCALAR_F64,
+                                               get_sched(MIMO_OP_PRECODE, max_u, in_dtype),
+                                               (hipStream_t)stream),
+                    "precode_cg_batch launch");
 }
 
 int mimo_convert(const void* src, void* dst, int dst_dtype, int64_t n, int32_t R, int32_t C,

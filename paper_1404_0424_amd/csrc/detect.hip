@@ -139,8 +139,31 @@ __global__ __launch_bounds__(256, 2) void detect_stream_kernel(DetectParams prm)
   }
 }
 
-// Generic kernel (any S): right-hand sides in chunks of 16, the Gram computed
-// with the first chunk and kept in LDS.
+// All right-hand sides of subcarrier n, in chunks of 16; the Gram is
+// computed with the first chunk and kept in LDS.
+template <int W, typename IN, typename ST, int M_BITS>
+__device__ __forceinline__ void detect_one(const DetectParams& prm, int64_t n, float2* As,
+                                           float2* Ps, float* Gs, int c, int g) {
+  constexpr int AST = 16 * W + 2;
+  const int B = prm.B, U = prm.U, S = prm.S;
+  const void* Hn = offset_sc(IN{}, prm.H, n, B, U);
+  const void* Yn = offset_sc(IN{}, prm.Y, n, B, S);
+  AOperand<W> at;
+  float d[W];
+  for (int s0 = 0; s0 < S; s0 += 16) {
+    GramAcc<W> acc;
+    acc.clear();
+    if (s0 == 0) {
+      gram_mf<W, true, true>(IN{}, Hn, Yn, B, U, S, s0, c, g, acc);
+      gram_to_operands<W>(acc, As, Gs, Ps, AST, prm.reg, c, g, at, d);
+    } else {
+      gram_mf<W, false, true>(IN{}, Hn, Yn, B, U, S, s0, c, g, acc);
+    }
+    cg_llr_epilogue<W, ST, M_BITS>(prm, n, s0, acc, at, d, Gs, Ps, c, g);
+  }
+}
+
+// Generic kernel (any S).
 template <int W, typename IN, typename ST, int M_BITS>
 __global__ __launch_bounds__(256, 2) void detect_approx_kernel(DetectParams prm) {
   constexpr int NU = 16 * W;
@@ -151,28 +174,32 @@ __global__ __launch_bounds__(256, 2) void detect_approx_kernel(DetectParams prm)
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const int c = lane & 15, g = lane >> 4;
-  float2* As = A_s[wv];
-  float2* Ps = P_s[wv];
-  float* Gs = G_s[wv];
-  const int B = prm.B, U = prm.U, S = prm.S;
-
   for (int64_t n = (int64_t)blockIdx.x * kWavesPerBlock + wv; n < prm.n_sc;
-       n += (int64_t)gridDim.x * kWavesPerBlock) {
-    const void* Hn = offset_sc(IN{}, prm.H, n, B, U);
-    const void* Yn = offset_sc(IN{}, prm.Y, n, B, S);
-    AOperand<W> at;
-    float d[W];
-    for (int s0 = 0; s0 < S; s0 += 16) {
-      GramAcc<W> acc;
-      acc.clear();
-      if (s0 == 0) {
-        gram_mf<W, true, true>(IN{}, Hn, Yn, B, U, S, s0, c, g, acc);
-        gram_to_operands<W>(acc, As, Gs, Ps, AST, prm.reg, c, g, at, d);
-      } else {
-        gram_mf<W, false, true>(IN{}, Hn, Yn, B, U, S, s0, c, g, acc);
-      }
-      cg_llr_epilogue<W, ST, M_BITS>(prm, n, s0, acc, at, d, Gs, Ps, c, g);
-    }
+       n += (int64_t)gridDim.x * kWavesPerBlock)
+    detect_one<W, IN, ST, M_BITS>(prm, n, A_s[wv], P_s[wv], G_s[wv], c, g);
+}
+
+// Batched kernel: frames of different shapes (same user class, QAM order,
+// storage and scalar precision) in one launch.  Frame f covers global
+// subcarriers [sc_begin_f, sc_begin_f + n_sc_f); each wave finds its frame
+// by a binary search over the (wave-uniform) descriptor table.
+template <int W, typename IN, typename ST, int M_BITS>
+__global__ __launch_bounds__(256, 2) void detect_batch_kernel(BatchArgs args) {
+  constexpr int NU = 16 * W;
+  constexpr int AST = NU + 2;
+  __shared__ __align__(16) float2 A_s[kWavesPerBlock][NU * AST];
+  __shared__ __align__(16) float2 P_s[kWavesPerBlock][NU * kPST];
+  __shared__ float G_s[kWavesPerBlock][NU];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+  const int c = lane & 15, g = lane >> 4;
+  for (int64_t gsc = (int64_t)blockIdx.x * kWavesPerBlock + wv; gsc < args.total;
+       gsc += (int64_t)gridDim.x * kWavesPerBlock) {
+    const int f = find_frame(args, gsc);
+    const FrameArgs& F = args.f[f];
+    DetectParams prm{F.H, F.Y, F.B, F.U, F.S, F.K, F.n_sc, F.reg, F.n0, F.es, F.scale,
+                     F.inv_scale, (float*)F.out, (float2*)F.out2, nullptr, nullptr};
+    detect_one<W, IN, ST, M_BITS>(prm, gsc - F.sc_begin, A_s[wv], P_s[wv], G_s[wv], c, g);
   }
 }
 
@@ -216,6 +243,44 @@ static hipError_t launch_in(const DetectParams& p, int in_dtype, int f64, int m_
     case 2: return launch_st<W, InBF16>(p, f64, m_bits, sch, stream);
   }
   return hipErrorInvalidValue;
+}
+
+template <int W, typename IN, typename ST>
+static hipError_t launch_batch_m(const BatchArgs& a, int m_bits, const Schedule& sch,
+                                 hipStream_t stream) {
+  const dim3 grid(sched_grid(a.total, sch)), block(kWave * kWavesPerBlock);
+  switch (m_bits) {
+    case 2: hipLaunchKernelGGL((detect_batch_kernel<W, IN, ST, 2>), grid, block, 0, stream, a); break;
+    case 4: hipLaunchKernelGGL((detect_batch_kernel<W, IN, ST, 4>), grid, block, 0, stream, a); break;
+    case 6: hipLaunchKernelGGL((detect_batch_kernel<W, IN, ST, 6>), grid, block, 0, stream, a); break;
+    case 8: hipLaunchKernelGGL((detect_batch_kernel<W, IN, ST, 8>), grid, block, 0, stream, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int W, typename IN>
+static hipError_t launch_batch_st(const BatchArgs& a, int f64, int m_bits, const Schedule& sch,
+                                  hipStream_t stream) {
+  return f64 ? launch_batch_m<W, IN, double>(a, m_bits, sch, stream)
+             : launch_batch_m<W, IN, float>(a, m_bits, sch, stream);
+}
+
+template <int W>
+static hipError_t launch_batch_in(const BatchArgs& a, int in_dtype, int f64, int m_bits,
+                                  const Schedule& sch, hipStream_t stream) {
+  switch (in_dtype) {
+    case 0: return launch_batch_st<W, InC32>(a, f64, m_bits, sch, stream);
+    case 1: return launch_batch_st<W, InF16>(a, f64, m_bits, sch, stream);
+    case 2: return launch_batch_st<W, InBF16>(a, f64, m_bits, sch, stream);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_detect_batch(const BatchArgs& a, int max_u, int in_dtype, int scalar_f64,
+                               int m_bits, const Schedule& sch, hipStream_t stream) {
+  if (max_u <= 16) return launch_batch_in<1>(a, in_dtype, scalar_f64, m_bits, sch, stream);
+  return launch_batch_in<2>(a, in_dtype, scalar_f64, m_bits, sch, stream);
 }
 
 hipError_t launch_detect_approx(const DetectParams& p, int in_dtype, int scalar_f64, int m_bits,

@@ -44,6 +44,40 @@ struct GramParams {
   float2* b;            // [n_sc][U][S] or null
 };
 
+// Batched launches: up to kMaxBatch frames of different shapes in one
+// kernel, passed by value in the kernel arguments.
+constexpr int kMaxBatch = 32;
+struct FrameArgs {
+  const void* H;        // [n_sc][B][U]
+  const void* Y;        // detect: Y [n_sc][B][S]; precode: T complex64 [n_sc][U][S]
+  void* out;            // detect: llr; precode: Q
+  void* out2;           // detect: xhat or null; precode: qnorm or null
+  int64_t sc_begin;     // first global subcarrier of the frame
+  int64_t n_sc;
+  int B, U, S, K;
+  float reg, n0, es, scale, inv_scale;   // detection
+  float beta;                            // precoding
+  int normalize;
+  int pad;
+};
+struct BatchArgs {
+  int n;                // frames
+  int pad;
+  int64_t total;        // subcarriers over all frames
+  FrameArgs f[kMaxBatch];
+};
+
+// Frame of global subcarrier gsc: the last f with sc_begin <= gsc.
+__device__ __forceinline__ int find_frame(const BatchArgs& a, int64_t gsc) {
+  int lo = 0, hi = a.n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.f[mid].sc_begin <= gsc) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // A kernel schedule: the kernel form of an operation and its grid.
 // blocks_per_cu = 0 launches one wavefront per subcarrier; k > 0 launches a
 // persistent grid of k blocks (4 wavefronts each) per compute unit that
@@ -74,6 +108,10 @@ hipError_t launch_detect_exact(const DetectParams& p, int in_dtype, int scalar_f
                                hipStream_t stream);
 hipError_t launch_precode(const PrecodeParams& p, int in_dtype, int scalar_f64,
                           const Schedule& sch, hipStream_t stream);
+hipError_t launch_detect_batch(const BatchArgs& a, int max_u, int in_dtype, int scalar_f64,
+                               int m_bits, const Schedule& sch, hipStream_t stream);
+hipError_t launch_precode_batch(const BatchArgs& a, int max_u, int in_dtype, int scalar_f64,
+                                const Schedule& sch, hipStream_t stream);
 hipError_t launch_gram_mf(const GramParams& p, int in_dtype, hipStream_t stream);
 hipError_t launch_convert(const float2* src, uint16_t* dst, int dst_dtype, int64_t n, int R,
                           int C, hipStream_t stream);

@@ -83,14 +83,18 @@ class Server:
     ``hbm_budget`` bytes (channel cache included)."""
 
     def __init__(self, executor, hbm_budget: int = 16 << 30, n_slots: int = 4,
-                 poll_interval: float = 20e-6):
+                 poll_interval: float = 20e-6, max_batch: int = 32, lookahead: int = 128):
         self.ex = executor
+        self.max_batch = max_batch
+        self.lookahead = lookahead
+        self.batch_sizes: list = []        # frames per launch
+        self.admit_groups: list = []       # request ids of each launch
         self.budget = int(hbm_budget)
         self.n_slots = n_slots
         self.poll_interval = poll_interval
         self._lock = threading.Condition()
         self._queue: collections.deque[_Pending] = collections.deque()
-        self._inflight: list = []          # (pending, handle, slot)
+        self._inflight: list = []          # (group, bytes, handle, slot, t_admit)
         self._free_slots = list(range(n_slots))
         self._reserved = 0                 # bytes of admitted requests
         self._channels: dict = {}          # ch_id -> bytes
@@ -196,47 +200,67 @@ class Server:
             time.sleep(self.poll_interval)
 
     def _admit_locked(self) -> None:
-        # strict arrival order: the head waits until it fits (no overtaking)
+        """Admit the queue head when it fits, together with later queued
+        requests of the same kernel class (one batched launch, up to
+        max_batch frames, within the budget).  The head never waits behind a
+        later request."""
         while self._queue and self._free_slots:
             head = self._queue[0]
-            if self._reserved + head.need + self._cache_bytes() > self.budget:
+            cache = self._cache_bytes()
+            if self._reserved + head.need + cache > self.budget:
                 return
-            self._queue.popleft()
+            key = self.ex.batch_key(head.req)
+            group, total = [head], head.need
+            for p in list(self._queue)[1:self.lookahead]:
+                if len(group) >= self.max_batch:
+                    break
+                if (self.ex.batch_key(p.req) == key
+                        and self._reserved + total + p.need + cache <= self.budget):
+                    group.append(p)
+                    total += p.need
+            for p in group:
+                self._queue.remove(p)
             slot = self._free_slots.pop(0)
-            self._reserved += head.need
-            self.peak_bytes = max(getattr(self, "peak_bytes", 0), self._reserved + self._cache_bytes())
-            self.admit_order.append(id(head.req))
+            self._reserved += total
+            self.peak_bytes = max(self.peak_bytes, self._reserved + cache)
+            self.admit_order.extend(id(p.req) for p in group)
+            self.admit_groups.append([id(p.req) for p in group])
+            self.batch_sizes.append(len(group))
             t_admit = self.ex.now()
             try:
-                handle = self.ex.launch(head.req, slot, head.ready)
-            except Exception as e:          # noqa: BLE001 - reported through the future
-                self._reserved -= head.need
+                handle = self.ex.launch([p.req for p in group], slot, [p.ready for p in group])
+            except Exception as e:          # noqa: BLE001 - reported through the futures
+                self._reserved -= total
                 self._free_slots.append(slot)
-                head.fut.set_exception(e)
+                for p in group:
+                    p.fut.set_exception(e)
                 continue
-            self._inflight.append((head, handle, slot, t_admit))
+            self._inflight.append((group, total, handle, slot, t_admit))
 
     def _poll(self) -> None:
         finished = []
         with self._lock:
             for item in list(self._inflight):
-                pend, handle, slot, t_admit = item
+                group, total, handle, slot, t_admit = item
                 if self.ex.done(handle):
                     self._inflight.remove(item)
-                    self._reserved -= pend.need
+                    self._reserved -= total
                     self._free_slots.append(slot)
                     finished.append(item)
             if finished:
                 self._lock.notify_all()
-        for pend, handle, slot, t_admit in finished:
+        for group, total, handle, slot, t_admit in finished:
             try:
-                outputs, t_done, solves, bits = self.ex.finish(handle)
-                res = Result(outputs, pend.t_submit, t_admit, t_done, solves, bits)
+                per = self.ex.finish(handle)
+                results = [Result(o, p.t_submit, t_admit, t_done, solves, bits)
+                           for p, (o, t_done, solves, bits) in zip(group, per)]
                 with self._lock:
-                    self._done.append(res)
-                pend.fut.set_result(res)
+                    self._done.extend(results)
+                for p, r in zip(group, results):
+                    p.fut.set_result(r)
             except Exception as e:          # noqa: BLE001
-                pend.fut.set_exception(e)
+                for p in group:
+                    p.fut.set_exception(e)
 
 
 class GpuExecutor:
@@ -319,36 +343,64 @@ class GpuExecutor:
         ev.record()
         return ev
 
-    def launch(self, req, slot: int, ready=None):
+    def batch_key(self, req):
+        """Requests with equal keys can share one batched launch."""
+        (n, B, U), dtype = self._shape(req.ch_id)
+        if isinstance(req, UplinkRequest):
+            if req.sinr_mode != "approx":
+                return ("up-exact", id(req))          # never batched
+            return ("up", U <= 16, dtype, req.qam_bits, req.scalar_prec, req.want_xhat)
+        return ("dn", U <= 16, dtype, req.scalar_prec)
+
+    def launch(self, reqs, slot: int, readies=()):
         t = self.torch
-        H, dtype = self.channels[req.ch_id]
         st = self.streams[slot]
-        if ready is not None:
-            st.wait_event(ready)
+        for ev in readies:
+            if ev is not None:
+                st.wait_event(ev)
+        outs, work = [], []
         with t.cuda.stream(st):
-            if isinstance(req, UplinkRequest):
-                Y = self._dev_c64(req.Y)
+            first = reqs[0]
+            if isinstance(first, UplinkRequest) and first.sinr_mode != "approx":
+                H, dtype = self.channels[first.ch_id]
+                Y = self._dev_c64(first.Y)
                 if dtype != "c32":
                     Y = self.api.convert(Y, dtype, stream=st)
-                out = self.api.detect_cg(H, Y, req.n0, req.es, req.K, req.qam_bits,
-                                         req.sinr_mode, req.scalar_prec, xhat=req.want_xhat,
-                                         stream=st)
-                n, U, S, m = out["llr"].shape
-                work = (n * S, n * S * U * m)
+                o = self.api.detect_cg(H, Y, first.n0, first.es, first.K, first.qam_bits,
+                                       first.sinr_mode, first.scalar_prec, xhat=first.want_xhat,
+                                       stream=st)
+                outs.append(o)
+            elif isinstance(first, UplinkRequest):
+                frames = []
+                for r in reqs:
+                    H, dtype = self.channels[r.ch_id]
+                    Y = self._dev_c64(r.Y)
+                    if dtype != "c32":
+                        Y = self.api.convert(Y, dtype, stream=st)
+                    frames.append((H, Y, r.n0, r.es))
+                outs = self.api.detect_cg_batch(frames, [r.K for r in reqs], first.qam_bits,
+                                                first.scalar_prec, xhat=first.want_xhat,
+                                                stream=st)
             else:
-                T = self._dev_c64(req.T)
-                Q, qn = self.api.precode_cg(H, T, req.beta, req.K, req.normalize,
-                                            req.scalar_prec, stream=st)
-                out = {"Q": Q, "qnorm": qn}
-                work = (T.shape[0] * T.shape[2], 0)
+                frames = [(self.channels[r.ch_id][0], self._dev_c64(r.T), r.beta, r.normalize)
+                          for r in reqs]
+                res = self.api.precode_cg_batch(frames, [r.K for r in reqs], first.scalar_prec,
+                                                qnorm=True, stream=st)
+                outs = [{"Q": q, "qnorm": qn} for q, qn in res]
+            for r, o in zip(reqs, outs):
+                if isinstance(r, UplinkRequest):
+                    n, U, S, m = o["llr"].shape
+                    work.append((n * S, n * S * U * m))
+                else:
+                    work.append((r.T.shape[0] * r.T.shape[2], 0))
             ev = t.cuda.Event(enable_timing=True)
             ev.record(st)
-        return (ev, out, work, (req,))        # request kept alive until completion
+        return (ev, outs, work, reqs)         # requests kept alive until completion
 
     def done(self, handle) -> bool:
         return handle[0].query()
 
     def finish(self, handle):
-        ev, out, work, _ = handle
+        ev, outs, work, _ = handle
         t_done = self._t_ref + self._ref.elapsed_time(ev) / 1e3
-        return out, t_done, work[0], work[1]
+        return [(o, t_done, w[0], w[1]) for o, w in zip(outs, work)]

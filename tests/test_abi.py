@@ -149,3 +149,22 @@ def test_autotune_table_save_load(tmp_path):
     assert autotune.load(str(p)) == 1
     assert autotune.get_schedule("detect", 8, 1) == (2, 4)
     autotune.set_schedule("detect", 8, 1, *before)
+
+
+def test_batch_validation():
+    lib = L.lib()
+    fr = (L.MimoFrame * 2)()
+    fr[0] = L.MimoFrame(4, 32, 8, 2, 3, P, P, P2, None, 0.5, 1.0, 0.0, 0)
+    fr[1] = L.MimoFrame(4, 32, 8, 2, 3, P, P, P2, None, -0.5, 1.0, 0.0, 0)   # bad n0
+    st = lib.mimo_detect_cg_batch(ctypes.addressof(fr), 2, 0, 4, 0, None)
+    assert st == L.MIMO_EINVAL and b"frame 1" in lib.mimo_last_error()
+    fr[1] = L.MimoFrame(4, 64, 40, 2, 3, P, P, P2, None, 0.5, 1.0, 0.0, 0)   # U too large
+    assert lib.mimo_detect_cg_batch(ctypes.addressof(fr), 2, 0, 4, 0, None) == L.MIMO_EUNSUPPORTED
+    assert lib.mimo_detect_cg_batch(ctypes.addressof(fr), 33, 0, 4, 0, None) == L.MIMO_EINVAL
+    assert lib.mimo_detect_cg_batch(None, 1, 0, 4, 0, None) == L.MIMO_EINVAL
+    assert lib.mimo_detect_cg_batch(ctypes.addressof(fr), 1, 0, 5, 0, None) == L.MIMO_EUNSUPPORTED
+    fr[0] = L.MimoFrame(0, 32, 8, 2, 3, P, P, P2, None, 0.5, 1.0, 0.0, 0)    # empty frame
+    assert lib.mimo_detect_cg_batch(ctypes.addressof(fr), 1, 0, 4, 0, None) == L.MIMO_OK
+    assert lib.mimo_detect_cg_batch(ctypes.addressof(fr), 0, 0, 4, 0, None) == L.MIMO_OK
+    fr[0] = L.MimoFrame(4, 32, 8, 2, 3, P, P, P2, None, 0.0, 0.0, -1.0, 1)   # bad beta
+    assert lib.mimo_precode_cg_batch(ctypes.addressof(fr), 1, 0, 0, None) == L.MIMO_EINVAL

@@ -288,3 +288,33 @@ def test_schedules_give_identical_results(case):
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
             assert np.array_equal(a, b)
+
+
+def test_batched_calls_equal_single_calls():
+    """Frames of different shapes in one batched launch give bitwise the
+    same outputs as separate single-frame calls (and match the oracle)."""
+    rng = np.random.default_rng(99)
+    shapes = [(64, 8, 30, 14, 4), (128, 16, 21, 14, 3), (32, 5, 17, 3, 2), (256, 32, 9, 14, 5),
+              (128, 12, 13, 20, 4)]
+    ups, dns = [], []
+    for B, U, n, S, K in shapes:
+        f = W.uplink_frame(rng, n, B, U, S, 6, 12.0)
+        d = W.downlink_frame(rng, n, B, U, S, 6, 12.0, H=f.H)
+        ups.append((f, K))
+        dns.append((d, K))
+    A = api()
+    outs = A.detect_cg_batch([(dev(f.H), dev(f.Y), f.n0, f.es) for f, K in ups],
+                             [K for _, K in ups], 6, xhat=True)
+    qs = A.precode_cg_batch([(dev(d.H), dev(d.T), d.beta, True) for d, K in dns],
+                            [K for _, K in dns], qnorm=True)
+    for (f, K), o in zip(ups, outs):
+        single = A.detect_cg(dev(f.H), dev(f.Y), f.n0, f.es, K, 6, xhat=True)
+        assert np.array_equal(host(o["llr"]), host(single["llr"]))
+        assert np.array_equal(host(o["xhat"]), host(single["xhat"]))
+        ref = O.detect_cg(f.H, f.Y, f.n0, f.es, K, 6)
+        assert llr_err(host(o["llr"]), ref["llr"]) <= TOL_L
+    for (d, K), (Q, qn) in zip(dns, qs):
+        Q1, qn1 = A.precode_cg(dev(d.H), dev(d.T), d.beta, K, True)
+        assert np.array_equal(host(Q), host(Q1)) and np.array_equal(host(qn), host(qn1))
+        ref = O.precode_cg(d.H, d.T, d.beta, K, True)
+        assert rel_err_vec(host(Q), ref["Q"], axis=1) <= TOL_X

@@ -14,8 +14,9 @@ from paper_1404_0424_amd import serving as SV
 class FakeExecutor:
     """Completes each launch after `delay` seconds; records concurrency."""
 
-    def __init__(self, delay=0.002):
+    def __init__(self, delay=0.002, batching=False):
         self.delay = delay
+        self.batching = batching
         self.channels = {}
         self.lock = threading.Lock()
         self.running = 0
@@ -39,21 +40,24 @@ class FakeExecutor:
             return 4 * n * U * req.Y.shape[2] * req.qam_bits
         return 8 * n * B * req.T.shape[2]
 
-    def launch(self, req, slot, ready=None):
+    def batch_key(self, req):
+        return (type(req).__name__, req.ch_id) if self.batching else id(req)
+
+    def launch(self, reqs, slot, readies=()):
         with self.lock:
-            self.running += 1
+            self.running += len(reqs)
             self.max_running = max(self.max_running, self.running)
-        return {"t_end": time.perf_counter() + self.delay, "req": req, "closed": False}
+        return {"t_end": time.perf_counter() + self.delay, "reqs": reqs, "closed": False}
 
     def done(self, h):
         if not h["closed"] and time.perf_counter() >= h["t_end"]:
             with self.lock:
-                self.running -= 1
+                self.running -= len(h["reqs"])
             h["closed"] = True
         return h["closed"]
 
     def finish(self, h):
-        return {"echo": h["req"]}, time.perf_counter(), 14, 0
+        return [({"echo": r}, time.perf_counter(), 14, 0) for r in h["reqs"]]
 
 
 def _up(ch, n=10, S=14, m=4):
@@ -115,3 +119,25 @@ def test_downlink_and_unregister():
     with pytest.raises(KeyError):
         srv.submit(SV.DownlinkRequest("c", np.zeros((4, 2, 3)), 0.1, 2)).result(timeout=5)
     srv.close()
+
+
+def test_batching_groups_same_class_and_keeps_head_first():
+    ex = FakeExecutor(0.004, batching=True)
+    srv = SV.Server(ex, hbm_budget=1 << 30, n_slots=1, max_batch=4)
+    srv.register_channel("a", np.zeros((10, 8, 4)))
+    srv.register_channel("b", np.zeros((10, 8, 4)))
+    # the slot is busy with the first request while the rest queue up
+    reqs = [_up("a")] + [_up("a" if k % 2 else "b") for k in range(9)]
+    futs = [srv.submit(r) for r in reqs]
+    for f in futs:
+        f.result(timeout=10)
+    srv.close()
+    assert max(srv.batch_sizes) > 1 and max(srv.batch_sizes) <= 4
+    assert sum(srv.batch_sizes) == 10
+    # every launch starts with the oldest request still waiting
+    arrival = {id(r): k for k, r in enumerate(reqs)}
+    admitted = set()
+    for grp in srv.admit_groups:
+        waiting = [k for k in range(len(reqs)) if k not in admitted]
+        assert arrival[grp[0]] == min(waiting)
+        admitted.update(arrival[i] for i in grp)
