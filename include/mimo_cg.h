@@ -193,7 +193,9 @@ int mimo_precode_cg_batch(const mimo_frame* frames, int n_frames, int in_dtype,
  *   variant       0 .. mimo_tune_variant_count(op) - 1 (detection: 0 generic,
  *                 1 stream = next subcarrier's loads in flight during CG,
  *                 2 stream with half-size load blocks; variant 1/2 apply for
- *                 S <= 16, larger S always uses 0)
+ *                 S <= 16, larger S always uses 0; 3 plain = the baseline
+ *                 mapping with VALU Gram/CG and one right-hand side at a time,
+ *                 complex64 storage only, other storage uses 0)
  *   blocks_per_cu 0: one wavefront per subcarrier; k in [1, 64]: persistent
  *                 grid of k four-wavefront blocks per compute unit
  * Results do not depend on the schedule (every variant performs the same

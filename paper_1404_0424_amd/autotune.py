@@ -22,6 +22,7 @@ import sys
 from . import _lib as L
 
 BLOCKS_PER_CU = (0, 1, 2, 3, 4, 5, 6, 8)
+BASELINE_VARIANTS = {"plain"}      # reference mappings, never chosen
 OPS = {"detect": L.MIMO_OP_DETECT, "precode": L.MIMO_OP_PRECODE}
 
 
@@ -66,7 +67,9 @@ def tune(op: str, U: int, dtype_code: int, fn, reps: int = 5, log=None) -> dict:
     """Time ``fn`` (which launches ``op`` on fixed inputs) under every
     candidate schedule, install the fastest, return the measurements."""
     results = []
-    for v in range(len(variants(op))):
+    for v, name in enumerate(variants(op)):
+        if name in BASELINE_VARIANTS:
+            continue
         for b in BLOCKS_PER_CU:
             set_schedule(op, U, dtype_code, v, b)
             t = time_call(fn, reps)

@@ -138,6 +138,7 @@ const char* mimo_tune_variant_name(int op, int variant) {
       case mimo::kDetectGeneric: return "generic";
       case mimo::kDetectStream: return "stream";
       case mimo::kDetectStreamSmall: return "stream-small";
+      case mimo::kDetectPlain: return "plain";
     }
   } else if (variant == 0 && (op == MIMO_OP_PRECODE || op == MIMO_OP_GRAM_MF)) {
     return "generic";

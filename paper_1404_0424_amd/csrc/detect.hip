@@ -206,7 +206,7 @@ __global__ __launch_bounds__(256, 2) void detect_batch_kernel(BatchArgs args) {
 template <int W, typename IN, typename ST, int M>
 static void launch_one(const DetectParams& p, const Schedule& sch, hipStream_t stream) {
   const dim3 grid(sched_grid(p.n_sc, sch)), block(kWave * kWavesPerBlock);
-  if (p.S > 16 || sch.variant == kDetectGeneric)
+  if (p.S > 16 || sch.variant == kDetectGeneric || sch.variant == kDetectPlain)
     hipLaunchKernelGGL((detect_approx_kernel<W, IN, ST, M>), grid, block, 0, stream, p);
   else if (sch.variant == kDetectStreamSmall)
     hipLaunchKernelGGL((detect_stream_kernel<W, IN, ST, M, true>), grid, block, 0, stream, p);
@@ -285,6 +285,8 @@ hipError_t launch_detect_batch(const BatchArgs& a, int max_u, int in_dtype, int 
 
 hipError_t launch_detect_approx(const DetectParams& p, int in_dtype, int scalar_f64, int m_bits,
                                 const Schedule& sch, hipStream_t stream) {
+  if (sch.variant == kDetectPlain && in_dtype == 0)
+    return launch_detect_plain(p, scalar_f64, m_bits, sch, stream);
   if (p.U <= 16) return launch_in<1>(p, in_dtype, scalar_f64, m_bits, sch, stream);
   return launch_in<2>(p, in_dtype, scalar_f64, m_bits, sch, stream);
 }

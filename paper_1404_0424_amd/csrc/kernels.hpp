@@ -86,7 +86,8 @@ struct Schedule {
   int variant;
   int blocks_per_cu;
 };
-enum { kDetectGeneric = 0, kDetectStream = 1, kDetectStreamSmall = 2, kDetectVariants = 3 };
+enum { kDetectGeneric = 0, kDetectStream = 1, kDetectStreamSmall = 2, kDetectPlain = 3,
+       kDetectVariants = 4 };
 enum { kPrecodeGeneric = 0, kPrecodeVariants = 1 };
 
 int num_compute_units();   // of the current device (cached per device)
@@ -108,6 +109,8 @@ hipError_t launch_detect_exact(const DetectParams& p, int in_dtype, int scalar_f
                                hipStream_t stream);
 hipError_t launch_precode(const PrecodeParams& p, int in_dtype, int scalar_f64,
                           const Schedule& sch, hipStream_t stream);
+hipError_t launch_detect_plain(const DetectParams& p, int scalar_f64, int m_bits,
+                               const Schedule& sch, hipStream_t stream);
 hipError_t launch_detect_batch(const BatchArgs& a, int max_u, int in_dtype, int scalar_f64,
                                int m_bits, const Schedule& sch, hipStream_t stream);
 hipError_t launch_precode_batch(const BatchArgs& a, int max_u, int in_dtype, int scalar_f64,
