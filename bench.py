@@ -32,6 +32,41 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# kernel symbol that each detection schedule variant launches
+DETECT_KERNEL = {"generic": "detect_approx_kernel", "stream": "detect_stream_kernel",
+                 "stream-small": "detect_stream_kernel", "plain": "detect_plain_kernel"}
+# translation units the complex64 approximate-SINR detection kernels are built from
+DETECT_SOURCES = ["detect.hip", "cg_core.hpp", "gram_phase.hpp", "llr.hpp", "kernels.hpp",
+                  "common.hpp"]
+PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
+
+
+def recorded_traffic(kernel, workload, n_sc):
+    """HBM bytes per launch of ``kernel`` from the committed counter summary
+    profiles/<kernel>_<workload>_c32.md (FETCH_SIZE + WRITE_SIZE passes,
+    scaled by a plain copy of known size).  The summary records the source
+    digest of the kernel's files and the subcarriers per launch; a figure
+    taken from other sources or another launch size is not reported."""
+    path = os.path.join(PROFILES, f"{kernel}_{workload}_c32.md")
+    if not os.path.exists(path):
+        return None
+    from paper_1404_0424_amd.build import source_digest
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- `") and "` = " in line:
+                k, v = line[3:].split("` = ", 1)
+                rec[k] = v.strip().strip("`")
+    try:
+        if (rec.get("source_digest") != source_digest(DETECT_SOURCES)
+                or int(rec["subcarriers_per_launch"]) != n_sc):
+            return None
+        return {"bytes_per_launch": float(rec["hbm_bytes_per_launch"]),
+                "file": os.path.relpath(path, os.path.dirname(PROFILES))}
+    except (KeyError, ValueError):
+        return None
+
+
 def detect_bytes_per_sc(B, U, S, m, elem_bytes=8):
     """Algorithmic HBM bytes of detection per subcarrier: read H and Y once,
     write the LLRs (FP32)."""
@@ -55,6 +90,9 @@ def main():
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default schedules")
+    ap.add_argument("--schedules", help="load a schedule table saved by --save-schedules "
+                    "(or the autotuner) instead of tuning")
+    ap.add_argument("--save-schedules", help="write the tuned schedule table to this file")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-stream leg")
     ap.add_argument("--serving-frames", type=int, default=600)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -136,12 +174,21 @@ def main():
 
     from paper_1404_0424_amd import autotune
     tuned = {}
-    if not args.no_tune:
+    if args.schedules:
+        autotune.load(args.schedules)
+        for op in ("detect", "precode"):
+            v, b = autotune.get_schedule(op, wl.U, 0)
+            tuned[op] = {"variant": autotune.variants(op)[v], "blocks_per_cu": b,
+                         "from": os.path.basename(args.schedules)}
+        log(f"loaded schedules: {tuned}")
+    elif not args.no_tune:
         # schedules picked by the autotuner on these inputs (not timed)
         e1 = autotune.tune("detect", wl.U, 0, lambda: api.detect_cg(
             H, Y, n0, es, K, m, "approx", scalar, out={"llr": llr}))
         e2 = autotune.tune("precode", wl.U, 0, lambda: api.precode_cg(
             H, T, beta, K, normalize=True, scalar_prec=scalar, qnorm=False, out=Q))
+        if args.save_schedules:
+            autotune.save([e1, e2], args.save_schedules)
         for e in (e1, e2):
             b = e["best"]
             tuned[e["op"]] = {"variant": autotune.variants(e["op"])[b["variant"]],
@@ -192,6 +239,8 @@ def main():
     det_bytes = detect_bytes_per_sc(wl.B, wl.U, wl.S, wl.m) * n
     pre_bytes = precode_bytes_per_sc(wl.B, wl.U, wl.S) * n
     achieved = det_bytes / det_s / 1e9
+    det_kernel = DETECT_KERNEL[autotune.variants("detect")[autotune.get_schedule("detect", wl.U, 0)[0]]]
+    traffic = recorded_traffic(det_kernel, wl.name, n)
 
     result = {
         "metric": METRIC,
@@ -221,8 +270,10 @@ def main():
         "downlink": {"solves_per_s": n * wl.S / pre_s, "kernel_ms": pre_s * 1e3,
                      "hbm_gbs": pre_bytes / pre_s / 1e9},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "detect_approx_kernel",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic["bytes_per_launch"] if traffic else None,
+                     "traffic_source": traffic["file"] if traffic else None,
+                     "kernel": det_kernel,
                      "bytes_per_subcarrier": detect_bytes_per_sc(wl.B, wl.U, wl.S, wl.m),
                      "subcarriers_per_launch": n},
     }

@@ -42,6 +42,9 @@ __all__ = [
     "llr_maxlog_separable", "ml_maxlog_bruteforce", "detect_cg",
     "precode_cg", "cholesky", "cholesky_solve", "cholesky_inverse",
     "mmse_exact", "precode_mmse_exact", "quantize_f16", "quantize_bf16",
+    "linear_soft_output", "detect_cholesky", "precode_cholesky", "neumann_inverse",
+    "detect_neumann", "precode_neumann", "cgls", "CGLSTrace", "augment_uplink",
+    "augment_downlink", "detect_cgls", "precode_cgls",
 ]
 
 
@@ -504,6 +507,230 @@ def precode_mmse_exact(H, T, beta: float) -> np.ndarray:
     T = np.asarray(T, dtype=np.complex128)
     V = np.stack([cholesky_solve(A[t], T[t]) for t in range(H.shape[0])])
     return H @ V
+
+
+# --------------------------------------------------------------------------
+# Comparison methods built on an explicit (approximate) inverse (Sec. III-F)
+# --------------------------------------------------------------------------
+
+def linear_soft_output(Linv: np.ndarray, H, Y, n0: float, es: float, m: int,
+                       llr_form: str = "bruteforce") -> dict:
+    """Soft output of the linear detector W = Linv H^H (Sec. II-A with the
+    exact inverse of eq. (2) replaced by Linv, one (U, U) matrix per
+    subcarrier shared by all right-hand sides).
+
+    xhat = Linv H^H y (eq. (3)); mu_i = w_i^H h_i = (Linv G)_ii;
+    nu_i^2 = E_s sum_{j != i} |(Linv G)_ij|^2 + N0 (Linv G Linv^H)_ii;
+    rho_i = mu_i^2 / nu_i^2; the zero-mu rule and LLRs as in detect_cg.
+    """
+    H = np.asarray(H, dtype=np.complex128)
+    G = gram(H)
+    b = matched_filter(H, Y)
+    n, U, S = b.shape
+    xhat = Linv @ b
+    Ls = np.broadcast_to(Linv[:, None], (n, S, U, U))
+    mu, _, rho = exact_sinr(Ls, G, es, n0)
+    Gii = np.diagonal(G, axis1=-2, axis2=-1).real
+    rho_zero = np.broadcast_to((Gii / n0)[:, :, None], (n, U, S))
+    zero = mu == 0.0
+    rho = np.where(zero, rho_zero, rho)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        z = np.where(zero, 0.0, xhat / np.where(zero, 1.0, mu))
+    llr_fn = llr_maxlog_bruteforce if llr_form == "bruteforce" else llr_maxlog_separable
+    return dict(llr=llr_fn(z, rho, m, es), xhat=xhat, mu=mu, rho=rho, z=z, G=G, b=b,
+                Linv=Linv)
+
+
+def detect_cholesky(H, Y, n0: float, es: float, m: int, llr_form: str = "bruteforce") -> dict:
+    """Reference soft-output MMSE detector (Sec. III-F-1): A = H^H H +
+    (N0/E_s) I is factored as A = M M^H, A^{-1} follows by forward and
+    backward substitution, and the soft output is that of W = A^{-1} H^H."""
+    H = np.asarray(H, dtype=np.complex128)
+    A = regularized_gram(H, n0 / es)
+    Ainv = np.stack([cholesky_inverse(A[t]) for t in range(H.shape[0])])
+    return linear_soft_output(Ainv, H, Y, n0, es, m, llr_form)
+
+
+def precode_cholesky(H, T, beta: float, normalize: bool = False) -> dict:
+    """Exact MMSE (beta > 0) or ZF (beta = 0) precoding by Cholesky
+    (Sec. III-F-1): q = H_d^H (H_d H_d^H + beta I)^{-1} t (eq. (6))."""
+    H = np.asarray(H, dtype=np.complex128)
+    A = regularized_gram(H, beta)
+    T = np.asarray(T, dtype=np.complex128)
+    V = np.stack([cholesky_solve(A[t], T[t]) for t in range(H.shape[0])])
+    return _precode_output(H, V, normalize)
+
+
+def _precode_output(H, V, normalize):
+    Q = H @ V
+    qnorm = np.sqrt(np.sum(np.abs(Q) ** 2, axis=-2))
+    if normalize:
+        Q = np.where(qnorm[:, None, :] > 0, Q / np.where(qnorm > 0, qnorm, 1.0)[:, None, :], 0.0)
+    return dict(Q=Q, qnorm=qnorm, v=V)
+
+
+def neumann_inverse(A: np.ndarray, K: int) -> np.ndarray:
+    """Truncated K-term Neumann series (Sec. III-F-2): with A = D + E,
+    D = diag(A), A^{-1} ~ sum_{k=0}^{K-1} (-D^{-1} E)^k D^{-1}, summed term
+    by term (term_0 = D^{-1}, term_k = -D^{-1} E term_{k-1})."""
+    A = np.asarray(A, dtype=np.complex128)
+    U = A.shape[-1]
+    d = np.diagonal(A, axis1=-2, axis2=-1).real
+    E = A - d[..., :, None] * np.eye(U)
+    Dinv = (1.0 / d)[..., :, None] * np.eye(U)
+    term = Dinv
+    acc = term.copy()
+    for _ in range(1, K):
+        term = -(1.0 / d)[..., :, None] * (E @ term)
+        acc = acc + term
+    return acc
+
+
+def detect_neumann(H, Y, n0: float, es: float, K: int, m: int,
+                   llr_form: str = "bruteforce") -> dict:
+    """Soft-output detection with the K-term Neumann approximation of
+    A^{-1} (Sec. III-F-2) in place of the exact inverse of eq. (2)."""
+    H = np.asarray(H, dtype=np.complex128)
+    A = regularized_gram(H, n0 / es)
+    return linear_soft_output(neumann_inverse(A, K), H, Y, n0, es, m, llr_form)
+
+
+def precode_neumann(H, T, beta: float, K: int, normalize: bool = False) -> dict:
+    """q = H_d^H Ainv~ t with the K-term Neumann approximation of
+    (H_d H_d^H + beta I)^{-1} (Sec. III-F-2, eq. (6))."""
+    H = np.asarray(H, dtype=np.complex128)
+    A = regularized_gram(H, beta)
+    V = neumann_inverse(A, K) @ np.asarray(T, dtype=np.complex128)
+    return _precode_output(H, V, normalize)
+
+
+# --------------------------------------------------------------------------
+# CGLS on the augmented systems (Sec. III-E, eqs. (17), (18))
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class CGLSTrace:
+    x: np.ndarray          # (n, N, S) iterate after K steps
+    alpha: np.ndarray      # (K, n, S), as CGTrace
+    beta: np.ndarray       # (K, n, S)
+    iterates: list         # x_1 .. x_K
+
+
+def cgls(Hb: np.ndarray, yb: np.ndarray, K: int) -> CGLSTrace:
+    """K steps of CGLS (the conjugate-gradient least-squares method the paper
+    cites for eqs. (17)-(18)) on min ||yb - Hb x||_2 from x_0 = 0, for every
+    column of yb independently:
+
+        r_0 = yb, s_0 = Hb^H r_0, p_0 = s_0, gamma_0 = ||s_0||^2
+        q = Hb p;  alpha = gamma / ||q||^2;  x += alpha p;  r -= alpha q
+        s = Hb^H r;  gamma' = ||s||^2;  beta = gamma' / gamma;  p = s + beta p
+
+    The residual r of the augmented system is kept and s recomputed from it.
+    A column with gamma == 0 freezes (alpha = beta = 0), as in cg().
+    Hb: (n, R, N), yb: (n, R, S).
+    """
+    Hb = np.asarray(Hb, dtype=np.complex128)
+    yb = np.asarray(yb, dtype=np.complex128)
+    n, R, N = Hb.shape
+    S = yb.shape[-1]
+    HbH = np.conj(np.swapaxes(Hb, -1, -2))
+    x = np.zeros((n, N, S), dtype=np.complex128)
+    r = yb.copy()
+    s = HbH @ r
+    p = s.copy()
+    gamma = np.sum(np.abs(s) ** 2, axis=-2)
+    alphas = np.zeros((K, n, S))
+    betas = np.zeros((K, n, S))
+    its = []
+    for k in range(K):
+        q = Hb @ p
+        qq = np.sum(np.abs(q) ** 2, axis=-2)
+        live = (gamma > 0) & (qq > 0)
+        alpha = np.where(live, gamma / np.where(live, qq, 1.0), 0.0)
+        x = x + alpha[:, None, :] * p
+        r = r - alpha[:, None, :] * q
+        s = HbH @ r
+        gnew = np.sum(np.abs(s) ** 2, axis=-2)
+        beta = np.where(live, gnew / np.where(live, gamma, 1.0), 0.0)
+        p = np.where(live[:, None, :], s + beta[:, None, :] * p, p)
+        gamma = np.where(live, gnew, gamma)
+        alphas[k] = alpha
+        betas[k] = beta
+        its.append(x.copy())
+    return CGLSTrace(x=x, alpha=alphas, beta=betas, iterates=its)
+
+
+def augment_uplink(H, Y, reg: float):
+    """Eq. (17): Hbar_u = [H_u; sqrt(reg) I_U], ybar = [y; 0_U]."""
+    H = np.asarray(H, dtype=np.complex128)
+    Y = np.asarray(Y, dtype=np.complex128)
+    n, B, U = H.shape
+    S = Y.shape[-1]
+    Hb = np.concatenate([H, np.broadcast_to(math.sqrt(reg) * np.eye(U), (n, U, U))], axis=1)
+    yb = np.concatenate([Y, np.zeros((n, U, S))], axis=1)
+    return Hb, yb
+
+
+def augment_downlink(H, beta: float):
+    """Eq. (18): Hbar_d = [H_d, sqrt(beta) I_U] with H_d = H_u^H."""
+    H = np.asarray(H, dtype=np.complex128)
+    n, B, U = H.shape
+    Hd = np.conj(np.swapaxes(H, -1, -2))
+    return np.concatenate([Hd, np.broadcast_to(math.sqrt(beta) * np.eye(U), (n, U, U))],
+                          axis=2)
+
+
+def detect_cgls(H, Y, n0: float, es: float, K: int, m: int, sinr_mode: str = "approx",
+                llr_form: str = "bruteforce") -> dict:
+    """Soft-output detection by K CGLS steps on eq. (17), with the SINR
+    trackers of Sec. III-C run on the CGLS step sizes (the paper notes the
+    trackers carry over): approximate (eqs. (13)-(15), d_i = A_ii) or exact
+    (L_K from the matrix form of the recursion with the same alpha, beta)."""
+    H = np.asarray(H, dtype=np.complex128)
+    reg = n0 / es
+    Hb, yb = augment_uplink(H, Y, reg)
+    tr = cgls(Hb, yb, K)
+    G = gram(H)
+    U = G.shape[-1]
+    A = G + reg * np.eye(U)
+    xhat = tr.x
+    n, _, S = xhat.shape
+    Gii = np.diagonal(G, axis1=-2, axis2=-1).real
+    rho_approx = np.broadcast_to((Gii / n0)[:, :, None], (n, U, S)).copy()
+    if sinr_mode == "approx":
+        d = np.diagonal(A, axis1=-2, axis2=-1).real
+        mu = approx_tracker_shadow(d, tr.alpha, tr.beta) * Gii[:, :, None]
+        rho = rho_approx
+    elif sinr_mode == "exact":
+        L = exact_tracker_shadow(A, tr.alpha, tr.beta)
+        mu, _, rho = exact_sinr(L, G, es, n0)
+    else:
+        raise ValueError(sinr_mode)
+    zero = mu == 0.0
+    rho = np.where(zero, rho_approx, rho)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        z = np.where(zero, 0.0, xhat / np.where(zero, 1.0, mu))
+    llr_fn = llr_maxlog_bruteforce if llr_form == "bruteforce" else llr_maxlog_separable
+    return dict(llr=llr_fn(z, rho, m, es), xhat=xhat, mu=mu, rho=rho, z=z, trace=tr)
+
+
+def precode_cgls(H, T, beta: float, K: int, normalize: bool = False) -> dict:
+    """Precoding by K CGLS steps on eq. (18): qbar minimizes
+    ||t - Hbar_d qbar|| over the Krylov space; q = qbar[:B]."""
+    H = np.asarray(H, dtype=np.complex128)
+    B = H.shape[1]
+    tr = cgls(augment_downlink(H, beta), np.asarray(T, dtype=np.complex128), K)
+    out = _precode_output_q(tr.x[:, :B, :], normalize)
+    out["trace"] = tr
+    out["qbar"] = tr.x
+    return out
+
+
+def _precode_output_q(Q, normalize):
+    qnorm = np.sqrt(np.sum(np.abs(Q) ** 2, axis=-2))
+    if normalize:
+        Q = np.where(qnorm[:, None, :] > 0, Q / np.where(qnorm > 0, qnorm, 1.0)[:, None, :], 0.0)
+    return dict(Q=Q, qnorm=qnorm)
 
 
 # --------------------------------------------------------------------------

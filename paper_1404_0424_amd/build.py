@@ -9,6 +9,7 @@ never survive a source change).
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
 import os
 import shutil
 import subprocess
@@ -32,6 +33,19 @@ FLAGS = [
     "-ffp-contract=on",
     "-I", os.path.join(ROOT, "include"),
 ]
+
+
+def source_digest(names=None) -> str:
+    """SHA-256 over kernel sources (``names`` under csrc/, default all) and
+    the compiler flags: a hardware-counter figure recorded for a kernel stays
+    valid while the digest of the files it is built from is unchanged."""
+    h = hashlib.sha256(" ".join(FLAGS[:-2]).encode())
+    for name in sorted(names if names is not None else os.listdir(CSRC)):
+        path = os.path.join(CSRC, name)
+        h.update(name.encode())
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def _compile(src: str) -> str:
