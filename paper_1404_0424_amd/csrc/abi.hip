@@ -9,7 +9,7 @@
 #include <cstring>
 
 #include "../../include/mimo_cg.h"
-#include "kernels.hpp"
+#include "launch.hpp"
 
 namespace {
 

@@ -5,7 +5,7 @@
 
 #include "cg_core.hpp"
 #include "gram_phase.hpp"
-#include "kernels.hpp"
+#include "launch.hpp"
 #include "llr.hpp"
 
 namespace mimo {

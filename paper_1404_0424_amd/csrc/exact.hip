@@ -12,7 +12,7 @@
 // and walks its right-hand sides in turn, with the matrices in LDS.
 #include "cg_core.hpp"
 #include "gram_phase.hpp"
-#include "kernels.hpp"
+#include "launch.hpp"
 #include "llr.hpp"
 
 namespace mimo {

@@ -2,7 +2,7 @@
 // initialization), and the ingest kernel that rounds complex64 channel /
 // receive data to the blocked FP16 / BF16 storage the MFMA phase reads.
 #include "gram_phase.hpp"
-#include "kernels.hpp"
+#include "launch.hpp"
 
 namespace mimo {
 

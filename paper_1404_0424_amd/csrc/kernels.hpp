@@ -1,5 +1,6 @@
-// Kernel parameter blocks and host-side launchers (C++ linkage, internal to
-// the library; the public entry points are in abi.hip).
+// Kernel parameter blocks and launch geometry (C++ linkage, internal to the
+// library; the public entry points are in abi.hip, the host launchers are
+// declared in launch.hpp).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -99,32 +100,6 @@ inline unsigned int sched_grid(int64_t n_sc, const Schedule& s) {
     if (blocks > cap) blocks = cap;
   }
   if (blocks > (1 << 20)) blocks = 1 << 20;
-  if (blocks < 1) blocks = 1;
-  return (unsigned int)blocks;
-}
-
-hipError_t launch_detect_approx(const DetectParams& p, int in_dtype, int scalar_f64, int m_bits,
-                                const Schedule& sch, hipStream_t stream);
-hipError_t launch_detect_exact(const DetectParams& p, int in_dtype, int scalar_f64, int m_bits,
-                               hipStream_t stream);
-hipError_t launch_precode(const PrecodeParams& p, int in_dtype, int scalar_f64,
-                          const Schedule& sch, hipStream_t stream);
-hipError_t launch_detect_plain(const DetectParams& p, int scalar_f64, int m_bits,
-                               const Schedule& sch, hipStream_t stream);
-hipError_t launch_detect_batch(const BatchArgs& a, int max_u, int in_dtype, int scalar_f64,
-                               int m_bits, const Schedule& sch, hipStream_t stream);
-hipError_t launch_precode_batch(const BatchArgs& a, int max_u, int in_dtype, int scalar_f64,
-                                const Schedule& sch, hipStream_t stream);
-hipError_t launch_gram_mf(const GramParams& p, int in_dtype, hipStream_t stream);
-hipError_t launch_convert(const float2* src, uint16_t* dst, int dst_dtype, int64_t n, int R,
-                          int C, hipStream_t stream);
-
-// Grid for one-wavefront-per-subcarrier kernels (4 waves per block); the
-// kernels loop over subcarriers with a grid stride, so any n_sc is covered.
-inline unsigned int wave_grid(int64_t n_sc) {
-  int64_t blocks = (n_sc + 3) / 4;
-  const int64_t cap = 1 << 20;
-  if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
   return (unsigned int)blocks;
 }

@@ -1,0 +1,36 @@
+// Host-side launchers of the library's kernels (C++ linkage, internal; the
+// public entry points are in abi.hip).  Declarations only: each launcher
+// is defined next to its kernels.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace mimo {
+
+hipError_t launch_detect_approx(const DetectParams& p, int in_dtype, int scalar_f64, int m_bits,
+                                const Schedule& sch, hipStream_t stream);
+hipError_t launch_detect_exact(const DetectParams& p, int in_dtype, int scalar_f64, int m_bits,
+                               hipStream_t stream);
+hipError_t launch_precode(const PrecodeParams& p, int in_dtype, int scalar_f64,
+                          const Schedule& sch, hipStream_t stream);
+hipError_t launch_detect_plain(const DetectParams& p, int scalar_f64, int m_bits,
+                               const Schedule& sch, hipStream_t stream);
+hipError_t launch_detect_batch(const BatchArgs& a, int max_u, int in_dtype, int scalar_f64,
+                               int m_bits, const Schedule& sch, hipStream_t stream);
+hipError_t launch_precode_batch(const BatchArgs& a, int max_u, int in_dtype, int scalar_f64,
+                                const Schedule& sch, hipStream_t stream);
+hipError_t launch_gram_mf(const GramParams& p, int in_dtype, hipStream_t stream);
+hipError_t launch_convert(const float2* src, uint16_t* dst, int dst_dtype, int64_t n, int R,
+                          int C, hipStream_t stream);
+
+// Grid for one-wavefront-per-subcarrier kernels (4 waves per block); the
+// kernels loop over subcarriers with a grid stride, so any n_sc is covered.
+inline unsigned int wave_grid(int64_t n_sc) {
+  int64_t blocks = (n_sc + 3) / 4;
+  const int64_t cap = 1 << 20;
+  if (blocks > cap) blocks = cap;
+  if (blocks < 1) blocks = 1;
+  return (unsigned int)blocks;
+}
+
+}  // namespace mimo

@@ -6,7 +6,7 @@
 // outputs as detect.hip (Algorithm 1, eqs. (4), (13)-(15)).
 #include "cg_core.hpp"
 #include "gram_phase.hpp"
-#include "kernels.hpp"
+#include "launch.hpp"
 #include "llr.hpp"
 
 namespace mimo {
