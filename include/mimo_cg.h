@@ -185,6 +185,39 @@ int mimo_precode_cg_batch(const mimo_frame* frames, int n_frames, int in_dtype,
                           int scalar_prec, void* stream);
 
 /*
+ * Comparison methods (Sec. III-F), same layouts and conventions as
+ * mimo_detect_cg / mimo_precode_cg.  They form A = H^H H + reg I on MFMA and
+ * an explicit inverse X of A per subcarrier, shared by its S right-hand
+ * sides, in FP32:
+ *   *_cholesky  exact inverse: A = M M^H (Cholesky), X = M^{-H} M^{-1} by
+ *               forward substitution (Sec. III-F-1).  shape->K is ignored.
+ *               A must be positive definite (reg > 0, or full column rank
+ *               for zero-forcing precoding); otherwise outputs are not finite.
+ *   *_neumann   X = sum_{k=0}^{K-1} (-D^{-1} E)^k D^{-1}, A = D + E with
+ *               D = diag(A), K = shape->K terms (Sec. III-F-2).  Needs
+ *               A_ii > 0.
+ * Detection: xhat = X H^H y (eq. (3) with X for the inverse of eq. (2));
+ * mu_i = (X G)_ii, nu_i^2 = E_s sum_{j != i} |(X G)_ij|^2 + N0 (X G X^H)_ii,
+ * rho_i = mu_i^2 / nu_i^2 (Sec. II-A); for the exact inverse these reduce
+ * to mu_i = 1 - (N0/E_s)(A^{-1})_ii and rho_i = mu_i / (N0 (A^{-1})_ii),
+ * which is what the Cholesky detector evaluates.  mu and sinr are the same
+ * for all right-hand sides of a subcarrier.  LLRs and the mu = 0 rule as in
+ * mimo_detect_cg.  Precoding: v = X t, q = H_u v (eq. (5) with P of eq. (6)),
+ * normalization and qnorm as in mimo_precode_cg.
+ */
+int mimo_detect_cholesky(const mimo_shape* shape, const void* H, const void* Y,
+                         int in_dtype, float n0, float es, int qam_bits,
+                         float* llr, void* xhat, float* mu, float* sinr, void* stream);
+int mimo_detect_neumann(const mimo_shape* shape, const void* H, const void* Y,
+                        int in_dtype, float n0, float es, int qam_bits,
+                        float* llr, void* xhat, float* mu, float* sinr, void* stream);
+int mimo_precode_cholesky(const mimo_shape* shape, const void* H, const void* T,
+                          int in_dtype, float beta, int normalize, void* Q,
+                          float* qnorm, void* stream);
+int mimo_precode_neumann(const mimo_shape* shape, const void* H, const void* T,
+                         int in_dtype, float beta, int normalize, void* Q,
+                         float* qnorm, void* stream);
+/*
  * Kernel schedules (not part of the paper's method: how the same arithmetic
  * is mapped onto the GPU).  Each operation has kernel variants and a grid
  * size; the pair used for (op, user class, storage type) comes from a

@@ -98,15 +98,9 @@ def gram_mf(H, Y=None, reg: float = 0.0, stream=None):
     return A, b
 
 
-def detect_cg(H, Y, n0: float, es: float, K: int, qam_bits: int, sinr_mode: str = "approx",
-              scalar_prec: str = "f32", xhat: bool = False, mu: bool = False,
-              sinr: bool = False, out=None, stream=None) -> dict:
-    """CG soft-output MMSE detection.  Returns a dict with 'llr' and the
-    optional 'xhat', 'mu', 'sinr' tensors.  ``out`` may hold preallocated
-    tensors under the same keys."""
-    hp, code, n, B, U = _channel(H)
-    yp, S = _rhs(Y, code, n, B)
-    dev = H.device
+def _detect_outputs(dev, n, U, S, qam_bits, xhat, mu, sinr, out):
+    """Output tensors of a detection call: (dict, llr, xhat, mu, sinr); the
+    optional ones are None unless requested or supplied in ``out``."""
     out = {} if out is None else dict(out)
     res = {}
 
@@ -125,6 +119,32 @@ def detect_cg(H, Y, n0: float, es: float, K: int, qam_bits: int, sinr_mode: str 
     xh = get("xhat", (n, U, S), torch.complex64, xhat)
     mu_t = get("mu", (n, U, S), torch.float32, mu)
     sn = get("sinr", (n, U, S), torch.float32, sinr)
+    return res, llr, xh, mu_t, sn
+
+
+def _precode_outputs(H, T, out, qnorm):
+    hp, code, n, B, U = _channel(H)
+    _check_c64(T, "T")
+    if T.dim() != 3 or T.shape[0] != n or T.shape[1] != U:
+        raise ValueError("T must be (n_sc, U, S)")
+    S = T.shape[2]
+    dev = T.device
+    Q = torch.empty((n, B, S), dtype=torch.complex64, device=dev) if out is None else out
+    if tuple(Q.shape) != (n, B, S) or Q.dtype != torch.complex64:
+        raise ValueError("out must be complex64 (n_sc, B, S)")
+    qn = torch.empty((n, S), dtype=torch.float32, device=dev) if qnorm else None
+    return hp, code, n, B, U, S, Q, qn
+
+
+def detect_cg(H, Y, n0: float, es: float, K: int, qam_bits: int, sinr_mode: str = "approx",
+              scalar_prec: str = "f32", xhat: bool = False, mu: bool = False,
+              sinr: bool = False, out=None, stream=None) -> dict:
+    """CG soft-output MMSE detection.  Returns a dict with 'llr' and the
+    optional 'xhat', 'mu', 'sinr' tensors.  ``out`` may hold preallocated
+    tensors under the same keys."""
+    hp, code, n, B, U = _channel(H)
+    yp, S = _rhs(Y, code, n, B)
+    res, llr, xh, mu_t, sn = _detect_outputs(H.device, n, U, S, qam_bits, xhat, mu, sinr, out)
     mode = {"approx": L.MIMO_SINR_APPROX, "exact": L.MIMO_SINR_EXACT}[sinr_mode]
     prec = {"f32": L.MIMO_SCALAR_F32, "f64": L.MIMO_SCALAR_F64}[scalar_prec]
     shp = L.shape(B, U, S, K, n)
@@ -137,16 +157,7 @@ def detect_cg(H, Y, n0: float, es: float, K: int, qam_bits: int, sinr_mode: str 
 def precode_cg(H, T: torch.Tensor, beta: float, K: int, normalize: bool = False,
                scalar_prec: str = "f32", qnorm: bool = True, out=None, stream=None):
     """CG precoding q = H_u v with (G + beta I) v = t.  Returns (Q, qnorm)."""
-    hp, code, n, B, U = _channel(H)
-    _check_c64(T, "T")
-    if T.dim() != 3 or T.shape[0] != n or T.shape[1] != U:
-        raise ValueError("T must be (n_sc, U, S)")
-    S = T.shape[2]
-    dev = T.device
-    Q = torch.empty((n, B, S), dtype=torch.complex64, device=dev) if out is None else out
-    if tuple(Q.shape) != (n, B, S) or Q.dtype != torch.complex64:
-        raise ValueError("out must be complex64 (n_sc, B, S)")
-    qn = torch.empty((n, S), dtype=torch.float32, device=dev) if qnorm else None
+    hp, code, n, B, U, S, Q, qn = _precode_outputs(H, T, out, qnorm)
     prec = {"f32": L.MIMO_SCALAR_F32, "f64": L.MIMO_SCALAR_F64}[scalar_prec]
     shp = L.shape(B, U, S, K, n)
     L.check(L.lib().mimo_precode_cg(shp, hp, T.data_ptr(), code, float(beta), int(bool(normalize)),
@@ -216,3 +227,51 @@ def precode_cg_batch(frames, K: int | list, scalar_prec: str = "f32", qnorm: boo
     L.check(L.lib().mimo_precode_cg_batch(ctypes.addressof(arr), len(frames), code0, prec,
                                           _stream(stream)))
     return outs
+
+
+# ---------------------------------------------------------------- Sec. III-F
+
+def _detect_inverse(fn, H, Y, n0, es, K, qam_bits, xhat, mu, sinr, out, stream):
+    hp, code, n, B, U = _channel(H)
+    yp, S = _rhs(Y, code, n, B)
+    res, llr, xh, mu_t, sn = _detect_outputs(H.device, n, U, S, qam_bits, xhat, mu, sinr, out)
+    L.check(fn(L.shape(B, U, S, K, n), hp, yp, code, float(n0), float(es), int(qam_bits),
+               llr.data_ptr(), _ptr(xh), _ptr(mu_t), _ptr(sn), _stream(stream)))
+    return res
+
+
+def detect_cholesky(H, Y, n0: float, es: float, qam_bits: int, xhat: bool = False,
+                    mu: bool = False, sinr: bool = False, out=None, stream=None) -> dict:
+    """Exact soft-output MMSE detection through the Cholesky factorization
+    of A (the paper's reference detector).  Same outputs as detect_cg."""
+    return _detect_inverse(L.lib().mimo_detect_cholesky, H, Y, n0, es, 1, qam_bits, xhat, mu,
+                           sinr, out, stream)
+
+
+def detect_neumann(H, Y, n0: float, es: float, K: int, qam_bits: int, xhat: bool = False,
+                   mu: bool = False, sinr: bool = False, out=None, stream=None) -> dict:
+    """Soft-output detection with the K-term Neumann-series inverse."""
+    return _detect_inverse(L.lib().mimo_detect_neumann, H, Y, n0, es, K, qam_bits, xhat, mu,
+                           sinr, out, stream)
+
+
+def _precode_inverse(fn, H, T, beta, K, normalize, qnorm, out, stream):
+    hp, code, n, B, U, S, Q, qn = _precode_outputs(H, T, out, qnorm)
+    L.check(fn(L.shape(B, U, S, K, n), hp, T.data_ptr(), code, float(beta), int(bool(normalize)),
+               Q.data_ptr(), _ptr(qn), _stream(stream)))
+    return Q, qn
+
+
+def precode_cholesky(H, T: torch.Tensor, beta: float, normalize: bool = False,
+                     qnorm: bool = True, out=None, stream=None):
+    """Exact MMSE (beta > 0) or ZF (beta = 0) precoding through the
+    Cholesky factorization.  Returns (Q, qnorm)."""
+    return _precode_inverse(L.lib().mimo_precode_cholesky, H, T, beta, 1, normalize, qnorm, out,
+                            stream)
+
+
+def precode_neumann(H, T: torch.Tensor, beta: float, K: int, normalize: bool = False,
+                    qnorm: bool = True, out=None, stream=None):
+    """Precoding with the K-term Neumann-series inverse.  Returns (Q, qnorm)."""
+    return _precode_inverse(L.lib().mimo_precode_neumann, H, T, beta, K, normalize, qnorm, out,
+                            stream)

@@ -274,6 +274,99 @@ int mimo_precode_cg(const mimo_shape* shape, const void* H, const void* T, int i
                     "precode_cg launch");
 }
 
+// ---------------------------------------------------------------- Sec. III-F
+// Shared validation of the detection entry points; fills p on success.
+static int detect_args(const mimo_shape* shape, bool need_k, const void* H, const void* Y,
+                       int in_dtype, float n0, float es, int qam_bits, float* llr, void* xhat,
+                       float* mu, float* sinr, mimo::DetectParams& p) {
+  CHECK(check_shape(shape, need_k));
+  CHECK(check_dtype(in_dtype, shape->B));
+  if (!(n0 > 0.f) || !std::isfinite(n0)) return fail(MIMO_EINVAL, "n0=%g must be > 0", n0);
+  if (!(es > 0.f) || !std::isfinite(es)) return fail(MIMO_EINVAL, "es=%g must be > 0", es);
+  if (qam_bits != 2 && qam_bits != 4 && qam_bits != 6 && qam_bits != 8)
+    return fail(MIMO_EUNSUPPORTED, "qam_bits=%d not in {2,4,6,8}", qam_bits);
+  CHECK(check_ptr(H, "H", true));
+  CHECK(check_ptr(Y, "Y", true));
+  CHECK(check_ptr(llr, "llr", true));
+  CHECK(check_ptr(xhat, "xhat", false));
+  CHECK(check_ptr(mu, "mu", false));
+  CHECK(check_ptr(sinr, "sinr", false));
+  const float scale = qam_scale(es, qam_bits);
+  p = mimo::DetectParams{H, Y, shape->B, shape->U, shape->S, need_k ? shape->K : 1, shape->n_sc,
+                         n0 / es, n0, es, scale, 1.0f / scale,
+                         llr, (float2*)xhat, mu, sinr};
+  return MIMO_OK;
+}
+
+static int precode_args(const mimo_shape* shape, bool need_k, const void* H, const void* T,
+                        int in_dtype, float beta, int normalize, void* Q, float* qnorm,
+                        mimo::PrecodeParams& p) {
+  CHECK(check_shape(shape, need_k));
+  CHECK(check_dtype(in_dtype, shape->B));
+  if (!(beta >= 0.f) || !std::isfinite(beta)) return fail(MIMO_EINVAL, "beta=%g must be >= 0", beta);
+  CHECK(check_ptr(H, "H", true));
+  CHECK(check_ptr(T, "T", true));
+  CHECK(check_ptr(Q, "Q", true));
+  CHECK(check_ptr(qnorm, "qnorm", false));
+  p = mimo::PrecodeParams{H, (const float2*)T, shape->B, shape->U, shape->S,
+                          need_k ? shape->K : 1, shape->n_sc, beta, normalize ? 1 : 0,
+                          (float2*)Q, qnorm};
+  return MIMO_OK;
+}
+
+static int detect_inverse(const mimo_shape* shape, int method, const void* H, const void* Y,
+                          int in_dtype, float n0, float es, int qam_bits, float* llr, void* xhat,
+                          float* mu, float* sinr, void* stream) {
+  g_last_error[0] = 0;
+  mimo::DetectParams p;
+  CHECK(detect_args(shape, method == mimo::kInvNeumann, H, Y, in_dtype, n0, es, qam_bits, llr,
+                    xhat, mu, sinr, p));
+  if (shape->n_sc == 0) return MIMO_OK;
+  return hip_status(mimo::launch_detect_inverse(p, method, in_dtype, qam_bits,
+                                                (hipStream_t)stream),
+                    method == mimo::kInvCholesky ? "detect_cholesky launch"
+                                                 : "detect_neumann launch");
+}
+
+static int precode_inverse(const mimo_shape* shape, int method, const void* H, const void* T,
+                           int in_dtype, float beta, int normalize, void* Q, float* qnorm,
+                           void* stream) {
+  g_last_error[0] = 0;
+  mimo::PrecodeParams p;
+  CHECK(precode_args(shape, method == mimo::kInvNeumann, H, T, in_dtype, beta, normalize, Q,
+                     qnorm, p));
+  if (shape->n_sc == 0) return MIMO_OK;
+  return hip_status(mimo::launch_precode_inverse(p, method, in_dtype, (hipStream_t)stream),
+                    method == mimo::kInvCholesky ? "precode_cholesky launch"
+                                                 : "precode_neumann launch");
+}
+
+int mimo_detect_cholesky(const mimo_shape* shape, const void* H, const void* Y, int in_dtype,
+                         float n0, float es, int qam_bits, float* llr, void* xhat, float* mu,
+                         float* sinr, void* stream) {
+  return detect_inverse(shape, mimo::kInvCholesky, H, Y, in_dtype, n0, es, qam_bits, llr, xhat,
+                        mu, sinr, stream);
+}
+
+int mimo_detect_neumann(const mimo_shape* shape, const void* H, const void* Y, int in_dtype,
+                        float n0, float es, int qam_bits, float* llr, void* xhat, float* mu,
+                        float* sinr, void* stream) {
+  return detect_inverse(shape, mimo::kInvNeumann, H, Y, in_dtype, n0, es, qam_bits, llr, xhat,
+                        mu, sinr, stream);
+}
+
+int mimo_precode_cholesky(const mimo_shape* shape, const void* H, const void* T, int in_dtype,
+                          float beta, int normalize, void* Q, float* qnorm, void* stream) {
+  return precode_inverse(shape, mimo::kInvCholesky, H, T, in_dtype, beta, normalize, Q, qnorm,
+                         stream);
+}
+
+int mimo_precode_neumann(const mimo_shape* shape, const void* H, const void* T, int in_dtype,
+                         float beta, int normalize, void* Q, float* qnorm, void* stream) {
+  return precode_inverse(shape, mimo::kInvNeumann, H, T, in_dtype, beta, normalize, Q, qnorm,
+                         stream);
+}
+
 // Prefix the message of a failed check with the frame index.
 static int frame_fail(int status, int i) {
   char msg[sizeof(g_last_error)];

@@ -19,6 +19,12 @@ hipError_t launch_detect_batch(const BatchArgs& a, int max_u, int in_dtype, int 
                                int m_bits, const Schedule& sch, hipStream_t stream);
 hipError_t launch_precode_batch(const BatchArgs& a, int max_u, int in_dtype, int scalar_f64,
                                 const Schedule& sch, hipStream_t stream);
+// Comparison methods of Sec. III-F built on an explicit inverse of A.
+enum { kInvCholesky = 0, kInvNeumann = 1 };
+hipError_t launch_detect_inverse(const DetectParams& p, int method, int in_dtype, int m_bits,
+                                 hipStream_t stream);
+hipError_t launch_precode_inverse(const PrecodeParams& p, int method, int in_dtype,
+                                  hipStream_t stream);
 hipError_t launch_gram_mf(const GramParams& p, int in_dtype, hipStream_t stream);
 hipError_t launch_convert(const float2* src, uint16_t* dst, int dst_dtype, int64_t n, int R,
                           int C, hipStream_t stream);

@@ -109,6 +109,30 @@ def test_precode_gram_convert_validation():
     assert lib.mimo_workspace_bytes(s, 1, 0) == 0
 
 
+def test_comparison_methods_validation():
+    lib = L.lib()
+    s = L.shape(32, 8, 2, 3, 4)
+    for fn in (lib.mimo_detect_cholesky, lib.mimo_detect_neumann):
+        assert fn(s, P, P, 0, 0.0, 1.0, 4, P2, None, None, None, None) == L.MIMO_EINVAL   # n0
+        assert fn(s, P, P, 0, 0.5, 1.0, 5, P2, None, None, None, None) == L.MIMO_EUNSUPPORTED
+        assert fn(s, P, None, 0, 0.5, 1.0, 4, P2, None, None, None, None) == L.MIMO_EINVAL
+        assert fn(s, P, P, 0, 0.5, 1.0, 4, P2 + 4, None, None, None, None) == L.MIMO_EINVAL
+        assert fn(L.shape(32, 8, 2, 3, 0), P, P, 0, 0.5, 1.0, 4, P2, None, None, None,
+                  None) == L.MIMO_OK
+    # Neumann needs K >= 1 terms; the Cholesky detector ignores K
+    k0 = L.shape(32, 8, 2, 0, 0)
+    assert lib.mimo_detect_neumann(k0, P, P, 0, 0.5, 1.0, 4, P2, None, None, None,
+                                   None) == L.MIMO_EINVAL
+    assert lib.mimo_detect_cholesky(k0, P, P, 0, 0.5, 1.0, 4, P2, None, None, None,
+                                    None) == L.MIMO_OK
+    for fn in (lib.mimo_precode_cholesky, lib.mimo_precode_neumann):
+        assert fn(s, P, P, 0, -1.0, 0, P2, None, None) == L.MIMO_EINVAL               # beta
+        assert fn(s, P, P, 0, 0.1, 0, None, None, None) == L.MIMO_EINVAL              # Q
+        assert fn(L.shape(30, 8, 2, 3, 4), P, P, 1, 0.1, 0, P2, None, None) == L.MIMO_EINVAL
+        assert fn(L.shape(32, 8, 2, 3, 0), P, P, 0, 0.0, 1, P2, None, None) == L.MIMO_OK
+    assert lib.mimo_precode_neumann(k0, P, P, 0, 0.1, 0, P2, None, None) == L.MIMO_EINVAL
+
+
 def test_status_strings():
     lib = L.lib()
     for st in (0, -1, -2, -3, -4):
