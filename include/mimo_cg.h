@@ -218,6 +218,33 @@ int mimo_precode_neumann(const mimo_shape* shape, const void* H, const void* T,
                          int in_dtype, float beta, int normalize, void* Q,
                          float* qnorm, void* stream);
 /*
+ * CGLS on the augmented systems (Sec. III-E).  No Gram matrix is formed;
+ * each of the K iterations runs q = Hbar p and s = Hbar^H r with H on MFMA.
+ *   mimo_detect_cgls   min_x ||[y; 0] - [H; sqrt(N0/E_s) I] x|| (eq. (17))
+ *                      from x_0 = 0; xhat = x_K.  The approximate SINR of
+ *                      eqs. (13)-(15) runs on the CGLS step sizes
+ *                      (d_i = ||h_i||^2 + N0/E_s); exact SINR is not offered.
+ *                      LLRs, outputs and degenerate-case rules as
+ *                      mimo_detect_cg (a zero ||s||^2 freezes the rhs).
+ *   mimo_precode_cgls  min ||t - [H_d, sqrt(beta) I] qbar|| (eq. (18)) from
+ *                      qbar_0 = 0; q = the first B entries of qbar_K (the
+ *                      minimum-norm solution at K = U, eq. (6)); normalization
+ *                      and qnorm as mimo_precode_cg.
+ * Recursion per rhs (residual kept, s recomputed):
+ *   r_0 = ybar, s_0 = Hbar^H r_0, p_0 = s_0, gamma_0 = ||s_0||^2;
+ *   q = Hbar p, alpha = gamma/||q||^2, x += alpha p, r -= alpha q,
+ *   s = Hbar^H r, gamma' = ||s||^2, beta_k = gamma'/gamma, p = s + beta_k p.
+ * scalar_prec as mimo_detect_cg.  Antenna-length vectors of 16 right-hand
+ * sides stay in LDS (B/16 x 2 KiB for detection, 3x that for precoding);
+ * a B beyond the device's LDS per block returns MIMO_EUNSUPPORTED.
+ */
+int mimo_detect_cgls(const mimo_shape* shape, const void* H, const void* Y,
+                     int in_dtype, float n0, float es, int qam_bits, int scalar_prec,
+                     float* llr, void* xhat, float* mu, float* sinr, void* stream);
+int mimo_precode_cgls(const mimo_shape* shape, const void* H, const void* T,
+                      int in_dtype, float beta, int normalize, int scalar_prec,
+                      void* Q, float* qnorm, void* stream);
+/*
  * Kernel schedules (not part of the paper's method: how the same arithmetic
  * is mapped onto the GPU).  Each operation has kernel variants and a grid
  * size; the pair used for (op, user class, storage type) comes from a

@@ -64,6 +64,8 @@ _SIGNATURES = {
     "mimo_detect_neumann": (_i, [_shape_p, _vp, _vp, _i, _f, _f, _i, _vp, _vp, _vp, _vp, _vp]),
     "mimo_precode_cholesky": (_i, [_shape_p, _vp, _vp, _i, _f, _i, _vp, _vp, _vp]),
     "mimo_precode_neumann": (_i, [_shape_p, _vp, _vp, _i, _f, _i, _vp, _vp, _vp]),
+    "mimo_detect_cgls": (_i, [_shape_p, _vp, _vp, _i, _f, _f, _i, _i, _vp, _vp, _vp, _vp, _vp]),
+    "mimo_precode_cgls": (_i, [_shape_p, _vp, _vp, _i, _f, _i, _i, _vp, _vp, _vp]),
     "mimo_tune_set": (_i, [_i, _i, _i, _i, _i]),
     "mimo_tune_get": (_i, [_i, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "mimo_tune_variant_count": (_i, [_i]),

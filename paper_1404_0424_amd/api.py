@@ -275,3 +275,31 @@ def precode_neumann(H, T: torch.Tensor, beta: float, K: int, normalize: bool = F
     """Precoding with the K-term Neumann-series inverse.  Returns (Q, qnorm)."""
     return _precode_inverse(L.lib().mimo_precode_neumann, H, T, beta, K, normalize, qnorm, out,
                             stream)
+
+
+# ---------------------------------------------------------------- Sec. III-E
+
+def detect_cgls(H, Y, n0: float, es: float, K: int, qam_bits: int, scalar_prec: str = "f32",
+                xhat: bool = False, mu: bool = False, sinr: bool = False, out=None,
+                stream=None) -> dict:
+    """K CGLS iterations on the augmented uplink system (no Gram matrix),
+    approximate in-loop SINR.  Same outputs as detect_cg."""
+    hp, code, n, B, U = _channel(H)
+    yp, S = _rhs(Y, code, n, B)
+    res, llr, xh, mu_t, sn = _detect_outputs(H.device, n, U, S, qam_bits, xhat, mu, sinr, out)
+    prec = {"f32": L.MIMO_SCALAR_F32, "f64": L.MIMO_SCALAR_F64}[scalar_prec]
+    L.check(L.lib().mimo_detect_cgls(L.shape(B, U, S, K, n), hp, yp, code, float(n0), float(es),
+                                     int(qam_bits), prec, llr.data_ptr(), _ptr(xh), _ptr(mu_t),
+                                     _ptr(sn), _stream(stream)))
+    return res
+
+
+def precode_cgls(H, T: torch.Tensor, beta: float, K: int, normalize: bool = False,
+                 scalar_prec: str = "f32", qnorm: bool = True, out=None, stream=None):
+    """K CGLS iterations on the augmented downlink system.  Returns (Q, qnorm)."""
+    hp, code, n, B, U, S, Q, qn = _precode_outputs(H, T, out, qnorm)
+    prec = {"f32": L.MIMO_SCALAR_F32, "f64": L.MIMO_SCALAR_F64}[scalar_prec]
+    L.check(L.lib().mimo_precode_cgls(L.shape(B, U, S, K, n), hp, T.data_ptr(), code, float(beta),
+                                      int(bool(normalize)), prec, Q.data_ptr(), _ptr(qn),
+                                      _stream(stream)))
+    return Q, qn

@@ -367,6 +367,51 @@ int mimo_precode_neumann(const mimo_shape* shape, const void* H, const void* T, 
                          stream);
 }
 
+// ---------------------------------------------------------------- Sec. III-E
+// CGLS keeps antenna-length vectors of 16 right-hand sides in LDS.
+static int check_cgls_lds(int B, bool precode) {
+  int dev = 0, limit = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+      limit <= 0)
+    limit = 65536;
+  const size_t need = mimo::cgls_lds_bytes(B, precode) + 8192;   // + static LDS
+  if (need > (size_t)limit)
+    return fail(MIMO_EUNSUPPORTED, "CGLS %s with B=%d needs %zu bytes of LDS per block (limit %d)",
+                precode ? "precoding" : "detection", B, need, limit);
+  return MIMO_OK;
+}
+
+int mimo_detect_cgls(const mimo_shape* shape, const void* H, const void* Y, int in_dtype,
+                     float n0, float es, int qam_bits, int scalar_prec, float* llr, void* xhat,
+                     float* mu, float* sinr, void* stream) {
+  g_last_error[0] = 0;
+  mimo::DetectParams p;
+  CHECK(detect_args(shape, true, H, Y, in_dtype, n0, es, qam_bits, llr, xhat, mu, sinr, p));
+  if (scalar_prec != MIMO_SCALAR_F32 && scalar_prec != MIMO_SCALAR_F64)
+    return fail(MIMO_EINVAL, "scalar_prec=%d unknown", scalar_prec);
+  if (shape->n_sc == 0) return MIMO_OK;
+  CHECK(check_cgls_lds(shape->B, false));
+  return hip_status(mimo::launch_detect_cgls(p, in_dtype, scalar_prec == MIMO_SCALAR_F64,
+                                             qam_bits, (hipStream_t)stream),
+                    "detect_cgls launch");
+}
+
+int mimo_precode_cgls(const mimo_shape* shape, const void* H, const void* T, int in_dtype,
+                      float beta, int normalize, int scalar_prec, void* Q, float* qnorm,
+                      void* stream) {
+  g_last_error[0] = 0;
+  mimo::PrecodeParams p;
+  CHECK(precode_args(shape, true, H, T, in_dtype, beta, normalize, Q, qnorm, p));
+  if (scalar_prec != MIMO_SCALAR_F32 && scalar_prec != MIMO_SCALAR_F64)
+    return fail(MIMO_EINVAL, "scalar_prec=%d unknown", scalar_prec);
+  if (shape->n_sc == 0) return MIMO_OK;
+  CHECK(check_cgls_lds(shape->B, true));
+  return hip_status(mimo::launch_precode_cgls(p, in_dtype, scalar_prec == MIMO_SCALAR_F64,
+                                              (hipStream_t)stream),
+                    "precode_cgls launch");
+}
+
 // Prefix the message of a failed check with the frame index.
 static int frame_fail(int status, int i) {
   char msg[sizeof(g_last_error)];

@@ -25,6 +25,12 @@ hipError_t launch_detect_inverse(const DetectParams& p, int method, int in_dtype
                                  hipStream_t stream);
 hipError_t launch_precode_inverse(const PrecodeParams& p, int method, int in_dtype,
                                   hipStream_t stream);
+// CGLS on the augmented systems (Sec. III-E); dynamic LDS of the kernels.
+size_t cgls_lds_bytes(int B, bool precode);
+hipError_t launch_detect_cgls(const DetectParams& p, int in_dtype, int scalar_f64, int m_bits,
+                              hipStream_t stream);
+hipError_t launch_precode_cgls(const PrecodeParams& p, int in_dtype, int scalar_f64,
+                               hipStream_t stream);
 hipError_t launch_gram_mf(const GramParams& p, int in_dtype, hipStream_t stream);
 hipError_t launch_convert(const float2* src, uint16_t* dst, int dst_dtype, int64_t n, int R,
                           int C, hipStream_t stream);

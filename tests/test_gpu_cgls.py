@@ -1,0 +1,180 @@
+"""GPU parity for CGLS on the augmented systems (Sec. III-E, eqs. (17),
+(18)) through the C ABI against the FP64 oracle: detection with the
+approximate in-loop SINR on the CGLS step sizes, and precoding whose
+iterates differ from CG-P below K = U."""
+import zlib
+
+import numpy as np
+import pytest
+
+from oracle import mimo_oracle as O
+from paper_1404_0424_amd import workload as W
+
+from _parity import TOL_L, TOL_X, dev, host, llr_err, rel_err_scalar, rel_err_vec
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1404_0424_amd import _lib
+    _lib.lib()
+
+
+def api():
+    from paper_1404_0424_amd import api as A
+    return A
+
+
+# (name, n_sc, B, U, S, m, K, snr_db, channel)
+CASES = [
+    ("small_32x8", 64, 32, 8, 1, 4, 3, 10.0, "iid"),
+    ("plain_128x8_0dB", 48, 128, 8, 14, 6, 3, 0.0, "iid"),
+    ("plain_128x8_20dB", 48, 128, 8, 14, 6, 3, 20.0, "iid"),
+    ("mixed_128x16", 64, 128, 16, 14, 6, 4, 15.0, "iid"),
+    ("mixed_128x32", 40, 128, 32, 14, 6, 4, 15.0, "iid"),
+    ("corr_256x32", 24, 256, 32, 14, 8, 6, 25.0, "kronecker"),
+    ("ragged_30x5_S17", 37, 30, 5, 17, 2, 5, 5.0, "iid"),
+    ("ragged_20x20", 13, 20, 20, 3, 4, 7, 12.0, "iid"),
+    ("single_user", 9, 6, 1, 2, 8, 1, 10.0, "iid"),
+    # square channel, kappa(A) ~ 9: K = 8 stops well before convergence (past
+    # convergence the recomputed s = Hbar^H r sits at the rounding floor of
+    # each precision, so the step sizes, and the SINR tracker fed by them,
+    # are rounding noise and differ between FP32 and FP64)
+    ("square_16x16_K8", 11, 16, 16, 5, 4, 8, 15.0, "iid"),
+]
+
+
+def _uplink(case, seed=0):
+    name, n, B, U, S, m, K, snr, ch = case
+    rng = np.random.default_rng(zlib.crc32(name.encode()) + 300 + seed)
+    return W.uplink_frame(rng, n, B, U, S, m, snr, channel=ch, rho_bs=0.5, rho_ue=0.2)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("scalar", ["f32", "f64"])
+def test_detect_cgls_parity(case, scalar):
+    name, n, B, U, S, m, K, snr, ch = case
+    f = _uplink(case)
+    out = api().detect_cgls(dev(f.H), dev(f.Y), f.n0, f.es, K, m, scalar, xhat=True, mu=True,
+                            sinr=True)
+    torch.cuda.synchronize()
+    ref = O.detect_cgls(f.H, f.Y, f.n0, f.es, K, m)
+    ex = rel_err_vec(host(out["xhat"]), ref["xhat"], axis=1)
+    el = llr_err(host(out["llr"]), ref["llr"])
+    emu = rel_err_scalar(host(out["mu"]), ref["mu"])
+    erho = rel_err_scalar(host(out["sinr"]), ref["rho"])
+    print(f"cgls {name} {scalar}: eps_x={ex:.2e} eps_L={el:.2e} eps_mu={emu:.2e} "
+          f"eps_rho={erho:.2e}")
+    assert ex <= TOL_X and el <= TOL_L and emu <= TOL_X and erho <= 1e-5
+
+
+def test_detect_cgls_equals_cg_d():
+    # same iterates and step sizes in exact arithmetic (Sec. III-E)
+    f = W.uplink_frame(np.random.default_rng(51), 32, 128, 16, 14, 6, 15.0)
+    A = api()
+    a = A.detect_cgls(dev(f.H), dev(f.Y), f.n0, f.es, 4, 6, xhat=True)
+    b = A.detect_cg(dev(f.H), dev(f.Y), f.n0, f.es, 4, 6, xhat=True)
+    assert rel_err_vec(host(a["xhat"]), host(b["xhat"]).astype(np.complex128), axis=1) <= 2 * TOL_X
+    assert llr_err(host(a["llr"]), host(b["llr"]).astype(np.float64)) <= 2 * TOL_L
+
+
+def test_detect_cgls_zero_receive_vectors():
+    f = W.uplink_frame(np.random.default_rng(52), 12, 32, 8, 6, 4, 10.0)
+    Y = f.Y.copy()
+    Y[3] = 0
+    Y[7, :, 2] = 0
+    out = api().detect_cgls(dev(f.H), dev(Y), f.n0, f.es, 3, 4, xhat=True)
+    ref = O.detect_cgls(f.H, Y, f.n0, f.es, 3, 4)
+    xh = host(out["xhat"])
+    assert np.all(xh[3] == 0) and np.all(xh[7, :, 2] == 0)
+    assert np.all(np.isfinite(host(out["llr"])))
+    assert rel_err_vec(xh, ref["xhat"], axis=1) <= TOL_X
+    assert llr_err(host(out["llr"]), ref["llr"]) <= TOL_L
+
+
+@pytest.mark.parametrize("dt", ["f16", "bf16"])
+def test_cgls_16bit_storage_matches_oracle_on_quantized_inputs(dt):
+    f = W.uplink_frame(np.random.default_rng(53), 24, 128, 16, 14, 6, 15.0)
+    A = api()
+    deq = O.dequantize_f16 if dt == "f16" else O.dequantize_bf16
+    qz = O.quantize_f16 if dt == "f16" else O.quantize_bf16
+    out = A.detect_cgls(A.convert(dev(f.H), dt), A.convert(dev(f.Y), dt), f.n0, f.es, 4, 6,
+                        xhat=True)
+    ref = O.detect_cgls(deq(qz(f.H)), deq(qz(f.Y)), f.n0, f.es, 4, 6)
+    assert rel_err_vec(host(out["xhat"]), ref["xhat"], axis=1) <= TOL_X
+    assert llr_err(host(out["llr"]), ref["llr"]) <= TOL_L
+    d = W.downlink_frame(np.random.default_rng(54), 24, 128, 16, 14, 6, 15.0)
+    Q, qn = A.precode_cgls(A.convert(dev(d.H), dt), dev(d.T), d.beta, 4, True)
+    pref = O.precode_cgls(deq(qz(d.H)), d.T, d.beta, 4, True)
+    assert rel_err_vec(host(Q), pref["Q"], axis=1) <= TOL_X
+    assert rel_err_scalar(host(qn), pref["qnorm"]) <= TOL_X
+
+
+# (name, n_sc, B, U, S, K, snr_db or None for zero forcing)
+PRECODE_CASES = [
+    ("small_32x8", 64, 32, 8, 1, 3, 10.0),
+    ("plain_128x8", 48, 128, 8, 14, 3, 10.0),
+    ("mixed_128x16", 48, 128, 16, 14, 4, 15.0),
+    ("mixed_128x32", 24, 128, 32, 14, 4, 15.0),
+    ("ragged_30x5_S17", 37, 30, 5, 17, 5, 5.0),
+    ("zf_32x8_KU", 16, 32, 8, 3, 8, None),
+]
+
+
+@pytest.mark.parametrize("case", PRECODE_CASES, ids=[c[0] for c in PRECODE_CASES])
+@pytest.mark.parametrize("normalize", [False, True])
+@pytest.mark.parametrize("scalar", ["f32", "f64"])
+def test_precode_cgls_parity(case, normalize, scalar):
+    name, n, B, U, S, K, snr = case
+    rng = np.random.default_rng(zlib.crc32(name.encode()) + 400)
+    d = W.downlink_frame(rng, n, B, U, S, 6, snr)
+    Q, qn = api().precode_cgls(dev(d.H), dev(d.T), d.beta, K, normalize, scalar)
+    ref = O.precode_cgls(d.H, d.T, d.beta, K, normalize)
+    eq = rel_err_vec(host(Q), ref["Q"], axis=1)
+    en = rel_err_scalar(host(qn), ref["qnorm"])
+    print(f"cgls precode {name} norm={normalize} {scalar}: eps_q={eq:.2e} eps_qnorm={en:.2e}")
+    assert eq <= TOL_X and en <= TOL_X
+    if snr is None:     # K = U zero forcing: H_d q = t
+        HdQ = np.conj(np.swapaxes(d.H, 1, 2)) @ host(Q).astype(np.complex128)
+        if normalize:
+            HdQ = HdQ * ref["qnorm"][:, None, :]
+        assert rel_err_vec(HdQ, d.T, axis=1) <= 1e-3
+
+
+def test_precode_cgls_large_array_or_clean_refusal():
+    # B = 256 needs 96 KiB of LDS per block for the three antenna-length
+    # vectors: it runs where the device allows that, otherwise the call is
+    # refused before launch with MIMO_EUNSUPPORTED
+    from paper_1404_0424_amd import _lib as L
+    d = W.downlink_frame(np.random.default_rng(55), 16, 256, 32, 14, 8, 25.0, channel="kronecker",
+                         rho_bs=0.5, rho_ue=0.2)
+    try:
+        Q, qn = api().precode_cgls(dev(d.H), dev(d.T), d.beta, 6, True, "f64")
+    except L.MimoError as e:
+        assert e.status == L.MIMO_EUNSUPPORTED
+        print("refused:", e)
+        return
+    ref = O.precode_cgls(d.H, d.T, d.beta, 6, True)
+    assert rel_err_vec(host(Q), ref["Q"], axis=1) <= TOL_X
+
+
+def test_cgls_full_size_sampled():
+    wl = W.WORKLOADS["mixed_128x16"]
+    n = 2 * wl.n_sc
+    rng = np.random.default_rng(56)
+    f = W.uplink_frame(rng, n, wl.B, wl.U, wl.S, wl.m, wl.snr_db[0])
+    d = W.downlink_frame(rng, n, wl.B, wl.U, wl.S, wl.m, wl.snr_db[0], H=f.H)
+    A = api()
+    out = A.detect_cgls(dev(f.H), dev(f.Y), f.n0, f.es, wl.K, wl.m, xhat=True)
+    Q, _ = A.precode_cgls(dev(f.H), dev(d.T), d.beta, wl.K, True)
+    idx = np.sort(np.random.default_rng(57).choice(n, 150, replace=False))
+    ref = O.detect_cgls(f.H[idx], f.Y[idx], f.n0, f.es, wl.K, wl.m)
+    pref = O.precode_cgls(f.H[idx], d.T[idx], d.beta, wl.K, True)
+    assert rel_err_vec(host(out["xhat"])[idx], ref["xhat"], axis=1) <= TOL_X
+    assert llr_err(host(out["llr"])[idx], ref["llr"]) <= TOL_L
+    assert rel_err_vec(host(Q)[idx], pref["Q"], axis=1) <= TOL_X
