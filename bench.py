@@ -95,6 +95,8 @@ def main():
     ap.add_argument("--save-schedules", help="write the tuned schedule table to this file")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-stream leg")
     ap.add_argument("--serving-frames", type=int, default=600)
+    ap.add_argument("--no-comparison", action="store_true",
+                    help="skip the comparison-methods leg (Cholesky, Neumann, CGLS, CG-D vs K)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy 3x (reference for HBM counters)")
     args = ap.parse_args()
@@ -323,6 +325,10 @@ def main():
                                       "p99": float(np.percentile(lat, 99)),
                                       "what": "one frame, UL detect + DL precode, idle GPU"}
 
+    if not args.no_comparison:
+        result["comparison"] = comparison_leg(api, autotune, H, Y, T, llr, Q, up, dn, wl, n,
+                                              kernel_time)
+
     if not args.no_serving:
         result["serving"] = serving_leg(args.serving_frames)
 
@@ -345,6 +351,60 @@ def main():
         result["cpu_baseline"] = cpu_baseline(up, dn, wl, llr, Q, args.cpu_seconds)
 
     print(json.dumps(result), flush=True)
+
+
+def comparison_leg(api, autotune, H, Y, T, llr, Q, up, dn, wl, n, kernel_time):
+    """The comparison methods on the same batch: average launch time (HIP
+    events, back-to-back launches) and algorithmic HBM rate of CG-D for
+    K = 1..16, the Cholesky detector, the Neumann series and CGLS, and the
+    matching precoders.  Gives the K up to which CG-D is faster than the
+    exact Cholesky detector on this GPU, beside the crossover of the
+    real-multiplication count (Sec. IV-A)."""
+    from paper_1404_0424_amd import complexity
+    n0, es, beta, m = up.n0, up.es, dn.beta, wl.m
+    det_b = detect_bytes_per_sc(wl.B, wl.U, wl.S, m) * n
+    pre_b = precode_bytes_per_sc(wl.B, wl.U, wl.S) * n
+
+    def rec(sec, nbytes):
+        gbs = nbytes / sec / 1e9
+        return {"ms": sec * 1e3, "hbm_gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
+
+    det = {"cg": {}, "neumann": {}, "cgls": {}}
+    for K in range(1, 17):
+        det["cg"][K] = rec(kernel_time(lambda: api.detect_cg(
+            H, Y, n0, es, K, m, "approx", out={"llr": llr}), reps=5), det_b)
+    det["cholesky"] = rec(kernel_time(lambda: api.detect_cholesky(
+        H, Y, n0, es, m, out={"llr": llr}), reps=5), det_b)
+    for K in (1, 2, 3):
+        det["neumann"][K] = rec(kernel_time(lambda: api.detect_neumann(
+            H, Y, n0, es, K, m, out={"llr": llr}), reps=5), det_b)
+    for K in (1, 2, 3, 4):
+        det["cgls"][K] = rec(kernel_time(lambda: api.detect_cgls(
+            H, Y, n0, es, K, m, out={"llr": llr}), reps=5), det_b)
+    ch = det["cholesky"]["ms"]
+    gpu_x = max([K for K, r in det["cg"].items() if r["ms"] <= ch], default=0)
+    pre = {
+        "cg_K%d" % wl.K: rec(kernel_time(lambda: api.precode_cg(
+            H, T, beta, wl.K, True, qnorm=False, out=Q), reps=5), pre_b),
+        "cholesky": rec(kernel_time(lambda: api.precode_cholesky(
+            H, T, beta, True, qnorm=False, out=Q), reps=5), pre_b),
+        "neumann_K3": rec(kernel_time(lambda: api.precode_neumann(
+            H, T, beta, 3, True, qnorm=False, out=Q), reps=5), pre_b),
+        "cgls_K%d" % wl.K: rec(kernel_time(lambda: api.precode_cgls(
+            H, T, beta, wl.K, True, qnorm=False, out=Q), reps=5), pre_b),
+    }
+    log("comparison detect ms: cg " + " ".join(f"K{K}={r['ms']:.3f}" for K, r in det["cg"].items())
+        + f"; cholesky {ch:.3f}; neumann "
+        + " ".join(f"K{K}={r['ms']:.3f}" for K, r in det["neumann"].items()) + "; cgls "
+        + " ".join(f"K{K}={r['ms']:.3f}" for K, r in det["cgls"].items()))
+    log("comparison precode ms: " + " ".join(f"{k}={r['ms']:.3f}" for k, r in pre.items()))
+    log(f"CG-D faster than Cholesky up to K={gpu_x} on this GPU; "
+        f"real-multiplication crossover K={complexity.crossover(wl.B, wl.U)}")
+    return {"workload": wl.name, "subcarriers_per_launch": n, "detect": det, "precode": pre,
+            "cg_faster_than_cholesky_up_to_K": gpu_x,
+            "multiplication_count_crossover_K": complexity.crossover(wl.B, wl.U),
+            "what": "average launch time of back-to-back launches; hbm_gbs = algorithmic "
+                    "bytes (H, Y in, LLR out / H, T in, Q out) per launch time"}
 
 
 def serving_leg(n_frames):
