@@ -10,10 +10,57 @@
 
 namespace mimo {
 
+// Output descriptors of one subcarrier: LLR, xhat, mu and sinr as buffer
+// resources over that subcarrier's [U][S] entries (zero-size when the
+// optional output is absent), so every lane issues the same stores and
+// masked entries are dropped by the range check: no branches around the
+// stores, and the compiler's memory-counter waits stay exact.
+template <int M_BITS>
+struct DetectStore {
+  __amdgpu_buffer_rsrc_t llr, xhat, mu, sinr;
+  __device__ void init(const DetectParams& p, int64_t n) {
+    const uint32_t per = (uint32_t)(p.U * p.S);
+    llr = make_rsrc(p.llr + (size_t)n * per * M_BITS, per * M_BITS * 4u);
+    xhat = make_rsrc(p.xhat ? (const void*)(p.xhat + (size_t)n * per) : p.llr,
+                     p.xhat ? per * 8u : 0u);
+    mu = make_rsrc(p.mu ? (const void*)(p.mu + (size_t)n * per) : p.llr, p.mu ? per * 4u : 0u);
+    sinr = make_rsrc(p.sinr ? (const void*)(p.sinr + (size_t)n * per) : p.llr,
+                     p.sinr ? per * 4u : 0u);
+  }
+  // entry e = u * S + s, or -1 for a masked lane
+  __device__ void store(int e, const float (&out)[M_BITS], float2 x, float m, float rho) const {
+    const bool ok = e >= 0;
+    const uint32_t ol = ok ? (uint32_t)e * (M_BITS * 4u) : kOOB;
+    if constexpr (M_BITS == 2) {
+      bstore2(llr, ol, out[0], out[1]);
+    } else if constexpr (M_BITS == 4) {
+      bstore4(llr, ol, out[0], out[1], out[2], out[3]);
+    } else if constexpr (M_BITS == 6) {
+      bstore3(llr, ol, out[0], out[1], out[2]);
+      bstore3(llr, ol + 12u, out[3], out[4], out[5]);
+    } else {
+      bstore4(llr, ol, out[0], out[1], out[2], out[3]);
+      bstore4(llr, ol + 16u, out[4], out[5], out[6], out[7]);
+    }
+    bstore2(xhat, ok ? (uint32_t)e * 8u : kOOB, x.x, x.y);
+    const uint32_t o4 = ok ? (uint32_t)e * 4u : kOOB;
+    bstore1(mu, o4, m);
+    bstore1(sinr, o4, rho);
+  }
+};
+
+// Memory-op form per storage type, chosen by measurement on MI355X: with
+// complex64 storage the unconditional prefetch and buffer-descriptor stores
+// are faster (the compiler's load-counter waits then cover exactly the
+// block consumed); with 16-bit storage the branchy form is faster.
+template <typename IN>
+constexpr bool kUncondMem = std::is_same<IN, InC32>::value;
+
 // K iterations of Algorithm 1 with the tracker of eq. (13), then mu (eq. (14)),
 // rho (eq. (15)), z = xhat / mu and the LLRs (eq. (4)) of right-hand sides
 // s0 + 4 g + j of subcarrier n.  A^T, d and G_ii come from the Gram phase.
-template <int W, typename ST, int M_BITS>
+// BUF: stores through buffer descriptors (no branches) or plain stores.
+template <int W, typename ST, int M_BITS, bool BUF>
 __device__ __forceinline__ void cg_llr_epilogue(const DetectParams& prm, int64_t n, int s0,
                                                 const GramAcc<W>& acc, const AOperand<W>& at,
                                                 const float (&d)[W], const float* Gs,
@@ -33,6 +80,8 @@ __device__ __forceinline__ void cg_llr_epilogue(const DetectParams& prm, int64_t
     cg_step<W, ST>(st, at, Ps, c, g, al, be);
     tracker_step<W, ST>(tk, d, al, be);
   }
+  DetectStore<M_BITS> os;
+  if (BUF) os.init(prm, n);
 #pragma unroll
   for (int w = 0; w < W; ++w) {
     const int u = 16 * w + c;
@@ -49,7 +98,9 @@ __device__ __forceinline__ void cg_llr_epilogue(const DetectParams& prm, int64_t
       const float2 z = make_float2(x.x * imu, x.y * imu);
       float out[M_BITS];
       llr_maxlog<M_BITS>(z, rho, prm.scale, prm.inv_scale, out);
-      if (u < U && s < S) {
+      if (BUF) {
+        os.store((u < U && s < S) ? u * S + s : -1, out, x, mu, rho);
+      } else if (u < U && s < S) {
         const size_t idx = ((size_t)n * U + u) * S + s;
         float* lp = prm.llr + idx * M_BITS;
 #pragma unroll
@@ -110,30 +161,44 @@ __global__ __launch_bounds__(256, 2) void detect_stream_kernel(DetectParams prm)
     const int64_t nc = nn < prm.n_sc ? nn : n;        // descriptors only used if nn < n_sc
     Sub nxt;
     nxt.init(offset_sc(IN{}, prm.H, nc, B, U), offset_sc(IN{}, prm.Y, nc, B, S), B, U, S, 0, c, g);
+    if (nn >= prm.n_sc) nxt.disable();       // last subcarrier: prefetch reads nothing
     // ---- A = H^H H + (N0/E_s) I and b = H^H y (Algorithm 1, initialization)
     GramAcc<W> acc;
     acc.clear();
     // ping-pong between two block buffers: blk holds the block at b0, alt
-    // receives the next one (or the next subcarrier's first block)
+    // receives the next one (or the next subcarrier's first block).  With
+    // kUncondMem the prefetch is issued on every path (an empty descriptor
+    // after the last subcarrier), so the number of loads in flight is the
+    // same everywhere and each wait covers exactly the block consumed.
     Blk alt;
     for (int b0 = 0;; b0 += 2 * Blk::ANT) {
-      if (b0 + Blk::ANT < B) alt.template load<true>(cur, b0 + Blk::ANT);
-      else if (nn < prm.n_sc) alt.template load<true>(nxt, 0);
+      const bool more1 = b0 + Blk::ANT < B;
+      if (kUncondMem<IN>)
+        alt.template load<true>(more1 ? cur : nxt, more1 ? b0 + Blk::ANT : 0);
+      else if (more1)
+        alt.template load<true>(cur, b0 + Blk::ANT);
+      else if (nn < prm.n_sc)
+        alt.template load<true>(nxt, 0);
       blk.template mma<true, true>(acc);
-      if (b0 + Blk::ANT >= B) {                    // odd block count: hand over
+      if (!more1) {                                // odd block count: hand over
         blk = alt;
         break;
       }
-      if (b0 + 2 * Blk::ANT < B) blk.template load<true>(cur, b0 + 2 * Blk::ANT);
-      else if (nn < prm.n_sc) blk.template load<true>(nxt, 0);
+      const bool more2 = b0 + 2 * Blk::ANT < B;
+      if (kUncondMem<IN>)
+        blk.template load<true>(more2 ? cur : nxt, more2 ? b0 + 2 * Blk::ANT : 0);
+      else if (more2)
+        blk.template load<true>(cur, b0 + 2 * Blk::ANT);
+      else if (nn < prm.n_sc)
+        blk.template load<true>(nxt, 0);
       alt.template mma<true, true>(acc);
-      if (b0 + 2 * Blk::ANT >= B) break;           // even block count: blk holds the next
+      if (!more2) break;                           // even block count: blk holds the next
     }
     finish_mf(IN{}, acc);
     AOperand<W> at;
     float d[W];
     gram_to_operands<W>(acc, As, Gs, Ps, AST, prm.reg, c, g, at, d);
-    cg_llr_epilogue<W, ST, M_BITS>(prm, n, 0, acc, at, d, Gs, Ps, c, g);
+    cg_llr_epilogue<W, ST, M_BITS, kUncondMem<IN>>(prm, n, 0, acc, at, d, Gs, Ps, c, g);
     n = nn;
     cur = nxt;
   }
@@ -159,7 +224,7 @@ __device__ __forceinline__ void detect_one(const DetectParams& prm, int64_t n, f
     } else {
       gram_mf<W, false, true>(IN{}, Hn, Yn, B, U, S, s0, c, g, acc);
     }
-    cg_llr_epilogue<W, ST, M_BITS>(prm, n, s0, acc, at, d, Gs, Ps, c, g);
+    cg_llr_epilogue<W, ST, M_BITS, kUncondMem<IN>>(prm, n, s0, acc, at, d, Gs, Ps, c, g);
   }
 }
 

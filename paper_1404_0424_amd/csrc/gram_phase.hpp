@@ -39,6 +39,33 @@ __device__ __forceinline__ uint4 bload4(__amdgpu_buffer_rsrc_t r, uint32_t voff,
   return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
 
+// Buffer stores: an offset outside the descriptor's range (kOOB, or any
+// offset of a zero-size descriptor) is dropped by the hardware, so masked
+// stores need no branch and every lane issues the same instructions.
+typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u3 __attribute__((ext_vector_type(3)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void bstore1(__amdgpu_buffer_rsrc_t r, uint32_t voff, float a) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, a), r, voff, 0, 0);
+}
+__device__ __forceinline__ void bstore2(__amdgpu_buffer_rsrc_t r, uint32_t voff, float a,
+                                        float b) {
+  const u2 v = {__builtin_bit_cast(unsigned int, a), __builtin_bit_cast(unsigned int, b)};
+  __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, 0, 0);
+}
+__device__ __forceinline__ void bstore3(__amdgpu_buffer_rsrc_t r, uint32_t voff, float a,
+                                        float b, float c) {
+  const u3 v = {__builtin_bit_cast(unsigned int, a), __builtin_bit_cast(unsigned int, b),
+                __builtin_bit_cast(unsigned int, c)};
+  __builtin_amdgcn_raw_buffer_store_b96(v, r, voff, 0, 0);
+}
+__device__ __forceinline__ void bstore4(__amdgpu_buffer_rsrc_t r, uint32_t voff, float a,
+                                        float b, float c, float d) {
+  const u4 v = {__builtin_bit_cast(unsigned int, a), __builtin_bit_cast(unsigned int, b),
+                __builtin_bit_cast(unsigned int, c), __builtin_bit_cast(unsigned int, d)};
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, voff, 0, 0);
+}
+
 template <int W>
 struct GramAcc {
   static constexpr int NT = W * (W + 1) / 2;   // upper-triangular tiles
@@ -85,6 +112,11 @@ struct SubC32 {                       // per-subcarrier buffer descriptors and l
     }
     const int s = s0 + c;
     oy = s < S ? (uint32_t)(g * S + s) * 8u : kOOB;
+  }
+  // zero-size descriptors: every load reads zero without touching memory
+  __device__ void disable() {
+    rh = make_rsrc(nullptr, 0u);
+    ry = make_rsrc(nullptr, 0u);
   }
 };
 
@@ -173,6 +205,10 @@ struct Sub16 {
     }
     const int s = s0 + c;
     oy = s < S ? (uint32_t)(2 * g * S + s) * 16u : kOOB;
+  }
+  __device__ void disable() {
+    rh = make_rsrc(nullptr, 0u);
+    ry = make_rsrc(nullptr, 0u);
   }
 };
 
