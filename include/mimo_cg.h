@@ -255,7 +255,9 @@ int mimo_precode_cgls(const mimo_shape* shape, const void* H, const void* T,
  *                 2 stream with half-size load blocks; variant 1/2 apply for
  *                 S <= 16, larger S always uses 0; 3 plain = the baseline
  *                 mapping with VALU Gram/CG and one right-hand side at a time,
- *                 complex64 storage only, other storage uses 0)
+ *                 complex64 storage only, other storage uses 0; precoding:
+ *                 0 generic, 1 stream, 2 stream-small, the same prefetching
+ *                 forms, for S <= 16)
  *   blocks_per_cu 0: one wavefront per subcarrier; k in [1, 64]: persistent
  *                 grid of k four-wavefront blocks per compute unit
  * Results do not depend on the schedule (every variant performs the same

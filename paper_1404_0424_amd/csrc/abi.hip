@@ -140,7 +140,13 @@ const char* mimo_tune_variant_name(int op, int variant) {
       case mimo::kDetectStreamSmall: return "stream-small";
       case mimo::kDetectPlain: return "plain";
     }
-  } else if (variant == 0 && (op == MIMO_OP_PRECODE || op == MIMO_OP_GRAM_MF)) {
+  } else if (op == MIMO_OP_PRECODE) {
+    switch (variant) {
+      case mimo::kPrecodeGeneric: return "generic";
+      case mimo::kPrecodeStream: return "stream";
+      case mimo::kPrecodeStreamSmall: return "stream-small";
+    }
+  } else if (variant == 0 && op == MIMO_OP_GRAM_MF) {
     return "generic";
   }
   return nullptr;

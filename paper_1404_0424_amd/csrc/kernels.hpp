@@ -89,7 +89,7 @@ struct Schedule {
 };
 enum { kDetectGeneric = 0, kDetectStream = 1, kDetectStreamSmall = 2, kDetectPlain = 3,
        kDetectVariants = 4 };
-enum { kPrecodeGeneric = 0, kPrecodeVariants = 1 };
+enum { kPrecodeGeneric = 0, kPrecodeStream = 1, kPrecodeStreamSmall = 2, kPrecodeVariants = 3 };
 
 int num_compute_units();   // of the current device (cached per device)
 
