@@ -245,6 +245,14 @@ def main():
     achieved = det_bytes / det_s / 1e9
     det_kernel = DETECT_KERNEL[autotune.variants("detect")[autotune.get_schedule("detect", wl.U, 0)[0]]]
     traffic = recorded_traffic(det_kernel, wl.name, n)
+    # reference: a plain device copy moving the same number of bytes (half
+    # read, half written), timed the same way
+    src = torch.empty(det_bytes // 8, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    copy_s = kernel_time(lambda: dst.copy_(src), reps=10)
+    copy_gbs = 2 * src.numel() * 4 / copy_s / 1e9
+    del src, dst
+    log(f"device copy of the same byte count: {copy_gbs:.0f} GB/s; detection {achieved:.0f} GB/s")
 
     result = {
         "metric": METRIC,
@@ -280,6 +288,8 @@ def main():
                      "traffic": traffic["bytes_per_launch"] if traffic else None,
                      "traffic_source": traffic["file"] if traffic else None,
                      "kernel": det_kernel,
+                     "copy_reference_gbs": copy_gbs,
+                     "frac_of_copy": achieved / copy_gbs,
                      "bytes_per_subcarrier": detect_bytes_per_sc(wl.B, wl.U, wl.S, wl.m),
                      "subcarriers_per_launch": n},
     }
