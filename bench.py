@@ -95,6 +95,9 @@ def main():
     ap.add_argument("--save-schedules", help="write the tuned schedule table to this file")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-stream leg")
     ap.add_argument("--serving-frames", type=int, default=600)
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the per-configuration leg (32x8, 128x8 SNR sweep, 128x32, "
+                         "256x32 correlated, Gram-stage MFMA utilisation)")
     ap.add_argument("--no-comparison", action="store_true",
                     help="skip the comparison-methods leg (Cholesky, Neumann, CGLS, CG-D vs K)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -335,6 +338,9 @@ def main():
                                       "p99": float(np.percentile(lat, 99)),
                                       "what": "one frame, UL detect + DL precode, idle GPU"}
 
+    if not args.no_configs:
+        result["configs"] = configs_leg(api, autotune, kernel_time, dev)
+
     if not args.no_comparison:
         result["comparison"] = comparison_leg(api, autotune, H, Y, T, llr, Q, up, dn, wl, n,
                                               kernel_time)
@@ -361,6 +367,88 @@ def main():
         result["cpu_baseline"] = cpu_baseline(up, dn, wl, llr, Q, args.cpu_seconds)
 
     print(json.dumps(result), flush=True)
+
+
+MFMA_PEAK_FP32 = 157.3e12        # MI355X dense FP32 MFMA, FLOP/s
+MFMA_FLOPS = 2 * 16 * 16 * 4     # one v_mfma_f32_16x16x4_f32
+
+
+def mfma_count(B, U, S, K, op):
+    """v_mfma_f32_16x16x4_f32 instructions per subcarrier issued by the
+    complex64 kernels: Gram tiles (3 per k-step on a diagonal tile, 4 off
+    it), the three-product matched filter / q = H v, and 16 W^2 per CG
+    mat-vec; k-steps of 4 antennas (users for q = H v)."""
+    W = 1 if U <= 16 else 2
+    ksteps = -(-B // 4)
+    chunks = -(-S // 16)
+    gram = ksteps * (3 * W + 4 * (W * (W - 1) // 2))
+    if op == "gram_mf":
+        return gram + chunks * ksteps * 3 * W
+    if op == "detect":
+        return gram + chunks * (ksteps * 3 * W + K * 16 * W * W)
+    # precode: Gram, K mat-vecs + one for ||q||^2, q = H v per 16-antenna tile
+    return gram + chunks * ((K + 1) * 16 * W * W + (-(-B // 16)) * 12 * W)
+
+
+def configs_leg(api, autotune, kernel_time, dev):
+    """Each workload configuration on its own batch (autotuned schedule,
+    back-to-back launches): detection and precoding rates, the detection
+    kernel's HBM rate and issued-MFMA rate, and the standalone Gram +
+    matched-filter kernel's MFMA utilisation (the Gram stage) at U = 32."""
+    import torch
+    from paper_1404_0424_amd import workload as W
+    plan = [("small_32x8", 1024, (10.0,)), ("plain_128x8", 16, (0.0, 10.0, 20.0)),
+            ("mixed_128x32", 8, (15.0,)), ("corr_256x32", 1, (25.0,))]
+    out = {}
+    for name, F, snrs in plan:
+        wl = W.WORKLOADS[name]
+        n = wl.n_sc * F
+        scalar = "f64" if wl.scalar_f64 else "f32"
+        rows = {}
+        for snr in snrs:
+            rng = W.rng_for(CFG_INDEX[name], 1)
+            up = W.uplink_frame(rng, n, wl.B, wl.U, wl.S, wl.m, snr, channel=wl.channel,
+                                rho_bs=wl.rho_bs, rho_ue=wl.rho_ue)
+            dn = W.downlink_frame(rng, n, wl.B, wl.U, wl.S, wl.m, snr, H=up.H)
+            H = torch.from_numpy(up.H.astype(np.complex64)).to(dev)
+            Y = torch.from_numpy(up.Y.astype(np.complex64)).to(dev)
+            T = torch.from_numpy(dn.T.astype(np.complex64)).to(dev)
+            llr = torch.empty((n, wl.U, wl.S, wl.m), dtype=torch.float32, device=dev)
+            Q = torch.empty((n, wl.B, wl.S), dtype=torch.complex64, device=dev)
+            fd = lambda: api.detect_cg(H, Y, up.n0, up.es, wl.K, wl.m, "approx", scalar,
+                                       out={"llr": llr})
+            fp = lambda: api.precode_cg(H, T, dn.beta, wl.K, True, scalar, qnorm=False, out=Q)
+            if snr == snrs[0]:
+                autotune.tune("detect", wl.U, 0, fd)
+                autotune.tune("precode", wl.U, 0, fp)
+            td, tp = kernel_time(fd, reps=10), kernel_time(fp, reps=10)
+            det_b = detect_bytes_per_sc(wl.B, wl.U, wl.S, wl.m) * n
+            mf = mfma_count(wl.B, wl.U, wl.S, wl.K, "detect") * n * MFMA_FLOPS
+            rows[f"{snr:g}dB"] = {
+                "detect_ms": td * 1e3, "precode_ms": tp * 1e3,
+                "uplink_solves_per_s": n * wl.S / td, "downlink_solves_per_s": n * wl.S / tp,
+                "llr_gbit_s": n * wl.S * wl.U * wl.m / td / 1e9,
+                "detect_hbm_gbs": det_b / td / 1e9, "detect_frac": det_b / td / 1e9 / HBM_PEAK_GBS,
+                "detect_mfma_tflops": mf / td / 1e12,
+                "detect_mfma_frac": mf / td / MFMA_PEAK_FP32}
+            if name in ("mixed_128x32", "corr_256x32") and snr == snrs[0]:
+                tg = kernel_time(lambda: api.gram_mf(H, Y, up.n0 / up.es), reps=10)
+                gf = mfma_count(wl.B, wl.U, wl.S, wl.K, "gram_mf") * n * MFMA_FLOPS
+                gb = (8 * wl.B * wl.U + 8 * wl.B * wl.S + 8 * wl.U * wl.U + 8 * wl.U * wl.S) * n
+                rows[f"{snr:g}dB"]["gram_stage"] = {
+                    "kernel_ms": tg * 1e3, "mfma_tflops": gf / tg / 1e12,
+                    "mfma_frac": gf / tg / MFMA_PEAK_FP32, "hbm_gbs": gb / tg / 1e9,
+                    "what": "standalone mimo_gram_mf (A = H^H H + reg I and b = H^H Y)"}
+            log(f"config {name} ({F} frames) {snr:g} dB: detect {td * 1e3:.3f} ms "
+                f"({det_b / td / 1e9:.0f} GB/s, MFMA {mf / td / 1e12:.1f} TF), "
+                f"precode {tp * 1e3:.3f} ms"
+                + (f"; Gram stage {rows[f'{snr:g}dB']['gram_stage']['mfma_frac']:.2f} of FP32 "
+                   f"MFMA peak" if "gram_stage" in rows[f"{snr:g}dB"] else ""))
+            del H, Y, T, llr, Q
+        out[name] = {"frames": F, "subcarriers": n, "K": wl.K, "scalar_prec": scalar,
+                     "by_snr": rows}
+        torch.cuda.empty_cache()
+    return out
 
 
 def comparison_leg(api, autotune, H, Y, T, llr, Q, up, dn, wl, n, kernel_time):
@@ -393,6 +481,16 @@ def comparison_leg(api, autotune, H, Y, T, llr, Q, up, dn, wl, n, kernel_time):
             H, Y, n0, es, K, m, out={"llr": llr}), reps=5), det_b)
     ch = det["cholesky"]["ms"]
     gpu_x = max([K for K, r in det["cg"].items() if r["ms"] <= ch], default=0)
+    # CG stage: least-squares slope of the launch time over K = 1..16 (the
+    # Gram, matched filter and LLR work does not depend on K)
+    ks = np.array(sorted(det["cg"]))
+    ts = np.array([det["cg"][K]["ms"] for K in ks]) * 1e-3
+    slope = float(np.polyfit(ks, ts, 1)[0])
+    cg_stage = {"ms_per_iteration": slope * 1e3, "stage_ms_at_K": slope * wl.K * 1e3,
+                "frame_bytes_per_stage_time_gbs": det_b / (slope * wl.K) / 1e9,
+                "frac": det_b / (slope * wl.K) / 1e9 / HBM_PEAK_GBS,
+                "what": "CG stage time = slope of detection time over K times K; frame "
+                        "bytes (H, Y, LLR) over that time"}
     pre = {
         "cg_K%d" % wl.K: rec(kernel_time(lambda: api.precode_cg(
             H, T, beta, wl.K, True, qnorm=False, out=Q), reps=5), pre_b),
@@ -411,7 +509,7 @@ def comparison_leg(api, autotune, H, Y, T, llr, Q, up, dn, wl, n, kernel_time):
     log(f"CG-D faster than Cholesky up to K={gpu_x} on this GPU; "
         f"real-multiplication crossover K={complexity.crossover(wl.B, wl.U)}")
     return {"workload": wl.name, "subcarriers_per_launch": n, "detect": det, "precode": pre,
-            "cg_faster_than_cholesky_up_to_K": gpu_x,
+            "cg_faster_than_cholesky_up_to_K": gpu_x, "cg_stage": cg_stage,
             "multiplication_count_crossover_K": complexity.crossover(wl.B, wl.U),
             "what": "average launch time of back-to-back launches; hbm_gbs = algorithmic "
                     "bytes (H, Y in, LLR out / H, T in, Q out) per launch time"}
@@ -447,11 +545,11 @@ def serving_leg(n_frames):
             return SV.UplinkRequest(f.ch_id, data[f.ch_id][0], n0, 1.0, f.m, 3)
         return SV.DownlinkRequest(f.ch_id, data[f.ch_id][1], n0, 3, True)
 
-    def run(rate, frames_n):
+    def run(rate, frames_n, dtype="c32"):
         _, frames = W.serving_stream(W.rng_for(4, 1 + int(rate)), 16, frames_n, rate)
         srv = SV.Server(ex, hbm_budget=16 << 30, n_slots=4)
         for c in chans:
-            srv.register_channel(c.ch_id, c.H, "c32")
+            srv.register_channel(c.ch_id, c.H, dtype)
         reqs = [request(f) for f in frames]
         # warm up every shape class once
         for f in {(by_id[f.ch_id].B, by_id[f.ch_id].U, f.uplink, f.m): f for f in frames}.values():
@@ -487,6 +585,13 @@ def serving_leg(n_frames):
         log(f"serving load {load}: offered {load * sat['frames_per_s']:.0f}/s, achieved "
             f"{st['frames_per_s']:.0f}/s, p50 {st['p50_ms']:.3f} ms, p99 {st['p99_ms']:.3f} ms")
         out[f"load_{load}"] = st
+    # mixed precision: channels kept on the device in BF16 (Gram / matched
+    # filter on 16-bit MFMA, FP32 accumulate and CG); uplink Y is rounded to
+    # BF16 on the slot stream per frame
+    sat16 = run(0.0, n_frames, "bf16")
+    log(f"serving saturation, BF16 channel storage: {sat16['frames_per_s']:.0f} frames/s, "
+        f"{sat16['solves_per_s']:.3g} solves/s")
+    out["saturation_bf16"] = sat16
     sys.setswitchinterval(old_switch)
     return out
 
