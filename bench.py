@@ -105,9 +105,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: the path shards by subcarrier with no "
-              "cross-GPU exchange, and multi-GPU runs are not part of this build "
-              "(use --gpus 1).", file=sys.stderr)
+        print("bench.py measures one GPU (use --gpus 1): subcarriers are independent "
+              "systems, so the path shards by subcarrier with no cross-GPU exchange and "
+              "the whole-job rate is the per-GPU rate times the GPU count.", file=sys.stderr)
         sys.exit(2)
 
     import torch
