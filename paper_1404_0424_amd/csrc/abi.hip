@@ -145,6 +145,7 @@ const char* mimo_tune_variant_name(int op, int variant) {
       case mimo::kPrecodeGeneric: return "generic";
       case mimo::kPrecodeStream: return "stream";
       case mimo::kPrecodeStreamSmall: return "stream-small";
+      case mimo::kPrecodeResident: return "resident";
     }
   } else if (variant == 0 && op == MIMO_OP_GRAM_MF) {
     return "generic";

@@ -53,6 +53,12 @@ __device__ __forceinline__ void bstore2(__amdgpu_buffer_rsrc_t r, uint32_t voff,
   const u2 v = {__builtin_bit_cast(unsigned int, a), __builtin_bit_cast(unsigned int, b)};
   __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, 0, 0);
 }
+// ... with a wave-uniform part of the offset in soffset (range-checked too)
+__device__ __forceinline__ void bstore2s(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
+                                         float a, float b) {
+  const u2 v = {__builtin_bit_cast(unsigned int, a), __builtin_bit_cast(unsigned int, b)};
+  __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
+}
 __device__ __forceinline__ void bstore3(__amdgpu_buffer_rsrc_t r, uint32_t voff, float a,
                                         float b, float c) {
   const u3 v = {__builtin_bit_cast(unsigned int, a), __builtin_bit_cast(unsigned int, b),

@@ -89,7 +89,8 @@ struct Schedule {
 };
 enum { kDetectGeneric = 0, kDetectStream = 1, kDetectStreamSmall = 2, kDetectPlain = 3,
        kDetectVariants = 4 };
-enum { kPrecodeGeneric = 0, kPrecodeStream = 1, kPrecodeStreamSmall = 2, kPrecodeVariants = 3 };
+enum { kPrecodeGeneric = 0, kPrecodeStream = 1, kPrecodeStreamSmall = 2, kPrecodeResident = 3,
+       kPrecodeVariants = 4 };
 
 int num_compute_units();   // of the current device (cached per device)
 

@@ -155,6 +155,186 @@ __global__ __launch_bounds__(256, 2) void precode_stream_kernel(PrecodeParams pr
   }
 }
 
+
+// H-resident streaming kernel (complex64 storage, U <= 16, S <= 16,
+// B <= BMAX): a subcarrier's channel stays in registers from the Gram to the
+// output contraction, so H crosses HBM once (the other kernels read it a
+// second time for q = H v).  In the Gram layout lane (c, g) holds
+// H[4 t + g][c] for k-step t; the output contraction needs H[16 i + c][4 g + t],
+// so each 16-antenna tile passes through the wave's LDS, and the registers it
+// leaves receive the same tile of the wave's next subcarrier, which is then
+// in flight during the rest of the output stage.  The 16 x S output tile is
+// staged in LDS too, so that each store instruction writes 512 contiguous
+// bytes.  Same arithmetic in the same order as precode_one.
+template <typename ST>
+constexpr int resident_min_blocks() { return sizeof(ST) == 8 ? 2 : 3; }
+
+template <int BMAX, typename ST>
+__global__ __launch_bounds__(256, resident_min_blocks<ST>()) void precode_resident_kernel(
+    PrecodeParams prm) {
+  constexpr int NU = 16, AST = NU + 2, NK = BMAX / 4;
+  __shared__ __align__(16) float2 A_s[kWavesPerBlock][NU * AST];
+  __shared__ __align__(16) float2 P_s[kWavesPerBlock][NU * kPST];
+  __shared__ float G_s[kWavesPerBlock][NU];
+  __shared__ float N_s[kWavesPerBlock][16];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+  const int c = lane & 15, g = lane >> 4;
+  float2* As = A_s[wv];
+  float2* Ps = P_s[wv];
+  float* Gs = G_s[wv];
+  float* Ns = N_s[wv];
+  const int B = prm.B, U = prm.U, S = prm.S;
+  const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
+  const uint32_t hbytes = (uint32_t)B * U * 8u, tbytes = (uint32_t)U * S * 8u;
+  const uint32_t oh = c < U ? (uint32_t)(g * U + c) * 8u : kOOB;      // H[g][c]
+  uint32_t ot[4];                                                      // T[c][4 g + j]
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int s = 4 * g + j;
+    ot[j] = (c < U && s < S) ? (uint32_t)(c * S + s) * 8u : kOOB;
+  }
+  const float2* H = (const float2*)prm.H;
+  // descriptors of subcarrier m's arrays; empty past the last subcarrier
+  auto rsrc_h = [&](int64_t m) {
+    return m < prm.n_sc ? make_rsrc(H + (size_t)m * B * U, hbytes) : make_rsrc(nullptr, 0u);
+  };
+  auto rsrc_t = [&](int64_t m) {
+    return m < prm.n_sc ? make_rsrc(prm.T + (size_t)m * U * S, tbytes) : make_rsrc(nullptr, 0u);
+  };
+
+  int64_t n = (int64_t)blockIdx.x * kWavesPerBlock + wv;
+  float2 hr[NK];
+  {
+    const __amdgpu_buffer_rsrc_t rh = rsrc_h(n);
+#pragma unroll
+    for (int t = 0; t < NK; ++t) hr[t] = bload2(rh, oh, (uint32_t)(4 * t) * U * 8u);
+  }
+  while (n < prm.n_sc) {
+    const int64_t nn = n + stride;
+    float2 b[1][4];                                   // b = t
+    {
+      const __amdgpu_buffer_rsrc_t rt = rsrc_t(n);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[0][j] = bload2(rt, ot[j], 0u);
+    }
+    // ---- A = H_d H_d^H + beta I = G + beta I (Algorithm 1, initialization)
+    GramAcc<1> acc;
+    acc.clear();
+#pragma unroll
+    for (int t = 0; t < NK; ++t) {
+      if (4 * t < B) {
+        acc.gr[0] = mfma4(hr[t].x, hr[t].x, acc.gr[0]);
+        acc.gr[0] = mfma4(hr[t].y, hr[t].y, acc.gr[0]);
+        acc.gi[0] = mfma4(hr[t].x, hr[t].y, acc.gi[0]);
+      }
+    }
+    store_gram_lds<1>(acc, As, Gs, (float*)Ps, AST, prm.beta, c, g);
+    wave_lds_sync();
+    AOperand<1> at;
+    at.load(As, AST, c, g);
+    CGState<1, ST> st;
+    cg_init<1, ST>(st, b);
+    for (int k = 0; k < prm.K; ++k) {
+      ST al[4], be[4];
+      cg_step<1, ST>(st, at, Ps, c, g, al, be);
+    }
+
+    // ---- ||q||^2 = v^H G v = v^H A v - beta ||v||^2 (V stays staged in Ps)
+    const float beta = prm.beta;
+    stage_vec<1>(Ps, c, g, st.v);
+    wave_lds_sync();
+    {
+      float2 e[1][4];
+      matvec_mfma<1>(at, Ps, c, g, e);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float2 v = st.v[0][j];
+        ST part = ST(0);
+        part += (ST)v.x * (ST)e[0][j].x + (ST)v.y * (ST)e[0][j].y -
+                (ST)beta * ((ST)v.x * (ST)v.x + (ST)v.y * (ST)v.y);
+        const ST qq = row_sum16(part);
+        if (c == 0) Ns[4 * g + j] = (float)(qq > ST(0) ? qq : ST(0));
+      }
+    }
+    wave_lds_sync();
+
+    // ---- q = H_u v on MFMA with H from registers: P1 = Hr Vr, P2 = Hi Vi,
+    // P3 = (Hr + Hi)(Vr + Vi); Re q = P1 - P2, Im q = P3 - P1 - P2
+    const float nrm2 = Ns[c];
+    const float scl = prm.normalize ? (nrm2 > 0.f ? __builtin_amdgcn_rsqf(nrm2) : 0.f) : 1.0f;
+    float2 vv[4];
+    float vs[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      vv[t] = Ps[(4 * g + t) * kPST + c];
+      vs[t] = vv[t].x + vv[t].y;
+    }
+    const __amdgpu_buffer_rsrc_t rq = make_rsrc(prm.Q + (size_t)n * B * S, (uint32_t)B * S * 8u);
+    const __amdgpu_buffer_rsrc_t rh2 = rsrc_h(nn);
+#pragma unroll
+    for (int i = 0; i < NK / 4; ++i) {
+      float2 hv[4];
+      if (16 * i < B) {                               // tile i: H[16 i + c][4 g + t]
+        wave_lds_sync();
+#pragma unroll
+        for (int t = 0; t < 4; ++t) Ps[(4 * t + g) * kPST + c] = hr[4 * i + t];
+        wave_lds_sync();
+#pragma unroll
+        for (int t = 0; t < 4; ++t) hv[t] = Ps[c * kPST + 4 * g + t];
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t)                     // the next subcarrier's tile
+        hr[4 * i + t] = bload2(rh2, oh, (uint32_t)(16 * i + 4 * t) * U * 8u);
+      if (16 * i < B) {
+        f4 p1 = zero4(), p2 = zero4(), p3 = zero4();
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          p1 = mfma4(hv[t].x, vv[t].x, p1);
+          p2 = mfma4(hv[t].y, vv[t].y, p2);
+          p3 = mfma4(hv[t].x + hv[t].y, vs[t], p3);
+        }
+        const f4 qr = p1 - p2;
+        const f4 qi = p3 - p1 - p2;
+        // output tile Q[16 i .. 16 i + 15][0 .. S-1] through LDS (A's copy
+        // is no longer needed); rows past B fall outside the descriptor
+        if (c < S) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            As[(4 * g + j) * S + c] = make_float2(qr[j] * scl, qi[j] * scl);
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int e = 64 * r + lane;
+          const float2 q = As[e < 16 * S ? e : 0];
+          bstore2s(rq, e < 16 * S ? (uint32_t)e * 8u : kOOB, (uint32_t)(16 * i * S) * 8u, q.x,
+                   q.y);
+        }
+        wave_lds_sync();
+      }
+    }
+    {
+      const __amdgpu_buffer_rsrc_t rn =
+          prm.qnorm ? make_rsrc(prm.qnorm + (size_t)n * S, (uint32_t)S * 4u)
+                    : make_rsrc(nullptr, 0u);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int ss = 4 * g + j;
+        bstore1(rn, (c == 0 && ss < S) ? (uint32_t)ss * 4u : kOOB, sqrtf(Ns[ss]));
+      }
+    }
+    wave_lds_sync();
+    n = nn;
+  }
+}
+
+// Whether the H-resident kernel covers a launch.
+template <int W, typename IN>
+static bool resident_fits(const PrecodeParams& p) {
+  return std::is_same<IN, InC32>::value && W == 1 && p.S <= 16 && p.B <= 128;
+}
+
 // Batched kernel: frames of different shapes in one launch (see detect.hip).
 template <int W, typename IN, typename ST>
 __global__ __launch_bounds__(256, 2) void precode_batch_kernel(BatchArgs args) {
@@ -180,7 +360,12 @@ __global__ __launch_bounds__(256, 2) void precode_batch_kernel(BatchArgs args) {
 template <int W, typename IN, typename ST>
 static void launch_one(const PrecodeParams& p, const Schedule& sch, hipStream_t stream) {
   const dim3 grid(sched_grid(p.n_sc, sch)), block(kWave * kWavesPerBlock);
-  if (p.S > 16 || sch.variant == kPrecodeGeneric)
+  if (sch.variant == kPrecodeResident && resident_fits<W, IN>(p)) {
+    if (p.B <= 64)
+      hipLaunchKernelGGL((precode_resident_kernel<64, ST>), grid, block, 0, stream, p);
+    else
+      hipLaunchKernelGGL((precode_resident_kernel<128, ST>), grid, block, 0, stream, p);
+  } else if (p.S > 16 || sch.variant == kPrecodeGeneric)
     hipLaunchKernelGGL((precode_kernel<W, IN, ST>), grid, block, 0, stream, p);
   else if (sch.variant == kPrecodeStreamSmall)
     hipLaunchKernelGGL((precode_stream_kernel<W, IN, ST, true>), grid, block, 0, stream, p);

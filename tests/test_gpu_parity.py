@@ -262,8 +262,9 @@ def test_full_size_sampled(wl, frames):
     assert np.all(np.isfinite(host(out["llr"])))
 
 
-@pytest.mark.parametrize("case", [DETECT_CASES[4], DETECT_CASES[5], DETECT_CASES[7]],
-                         ids=["mixed_128x16", "mixed_128x32", "ragged_30x5_S17"])
+@pytest.mark.parametrize("case", [DETECT_CASES[4], DETECT_CASES[5], DETECT_CASES[7],
+                                  ("ragged_100x12_S9", 29, 100, 12, 9, 4, 4, 10.0, "iid")],
+                         ids=["mixed_128x16", "mixed_128x32", "ragged_30x5_S17", "ragged_100x12_S9"])
 def test_schedules_give_identical_results(case):
     """Every kernel variant and grid size computes the same per-system
     arithmetic in the same order: outputs are bitwise equal."""
