@@ -258,8 +258,8 @@ int mimo_precode_cgls(const mimo_shape* shape, const void* H, const void* T,
  *                 complex64 storage only, other storage uses 0; precoding:
  *                 0 generic, 1 stream, 2 stream-small, the same prefetching
  *                 forms, for S <= 16; 3 resident = H kept in registers from
- *                 the Gram to q = H v so that it is read once, for complex64
- *                 storage with U <= 16, S <= 16 and B <= 128; other shapes use
+ *                 the Gram to q = H v so that it is read once, for U <= 16,
+ *                 S <= 16 and B <= 128 in any storage type; other shapes use
  *                 1, or 0 when S > 16)
  *   blocks_per_cu 0: one wavefront per subcarrier; k in [1, 64]: persistent
  *                 grid of k four-wavefront blocks per compute unit

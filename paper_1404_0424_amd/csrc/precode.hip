@@ -156,23 +156,67 @@ __global__ __launch_bounds__(256, 2) void precode_stream_kernel(PrecodeParams pr
 }
 
 
-// H-resident streaming kernel (complex64 storage, U <= 16, S <= 16,
-// B <= BMAX): a subcarrier's channel stays in registers from the Gram to the
-// output contraction, so H crosses HBM once (the other kernels read it a
-// second time for q = H v).  In the Gram layout lane (c, g) holds
-// H[4 t + g][c] for k-step t; the output contraction needs H[16 i + c][4 g + t],
-// so each 16-antenna tile passes through the wave's LDS, and the registers it
-// leaves receive the same tile of the wave's next subcarrier, which is then
-// in flight during the rest of the output stage.  The 16 x S output tile is
-// staged in LDS too, so that each store instruction writes 512 contiguous
-// bytes.  Same arithmetic in the same order as precode_one.
+// H-resident streaming kernel (U <= 16, S <= 16, B <= BMAX): a subcarrier's
+// channel stays in registers from the Gram to the output contraction, so H
+// crosses HBM once (the other kernels read it a second time for q = H v).
+// The registers hold the Gram's k-steps (complex64: lane (c, g) holds
+// H[4 t + g][c] for k-step t; 16-bit: Re and Im of the eight antennas of
+// block 4 t + g for user c), but the output contraction needs H[16 i + c]
+// [4 g + t] in FP32, so each 16-antenna tile passes through the wave's LDS;
+// the registers a k-step leaves receive the same k-step of the wave's next
+// subcarrier, which is then in flight during the rest of the output stage.
+// The 16 x S output tile is staged in LDS too, so that each store
+// instruction writes 512 contiguous bytes.  Same arithmetic in the same
+// order as precode_one.
+template <typename IN>
+struct ResidentBlock;
+template <>
+struct ResidentBlock<InC32> {
+  using type = BlockC32<1, 1>;    // one k-step: 4 antennas
+};
+template <>
+struct ResidentBlock<InF16> {
+  using type = Block16<1, h8, 1>;   // one k-step: 32 antennas
+};
+template <>
+struct ResidentBlock<InBF16> {
+  using type = Block16<1, bf8, 1>;
+};
+
+// Output tile i (antennas 16 i .. 16 i + 15) of the resident channel to LDS
+// as Hs[antenna][user] in FP32 (row stride kPST).
+template <int NK>
+__device__ __forceinline__ void stage_h_tile(const BlockC32<1, 1> (&hb)[NK], int i,
+                                             float2* __restrict__ Hs, int c, int g) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) Hs[(4 * t + g) * kPST + c] = hb[4 * i + t].h[0][0];
+}
+template <int NK, typename V8>
+__device__ __forceinline__ void stage_h_tile(const Block16<1, V8, 1> (&hb)[NK], int i,
+                                             float2* __restrict__ Hs, int c, int g) {
+  // k-step i / 2 holds blocks 4 (i / 2) + g; tile i is blocks 2 i and 2 i + 1
+  if ((g >> 1) == (i & 1)) {
+    const V8 re = hb[i >> 1].hr[0][0], im = hb[i >> 1].hi[0][0];
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      Hs[(8 * (g & 1) + e) * kPST + c] = make_float2((float)re[e], (float)im[e]);
+  }
+}
+
+// Occupancy the register budget is sized for: 3 waves per SIMD (H takes 64
+// VGPRs at B = 128 in complex64, 32 in 16-bit storage, where 4 waves would
+// spill), 2 with FP64 scalars.
 template <typename ST>
 constexpr int resident_min_blocks() { return sizeof(ST) == 8 ? 2 : 3; }
 
-template <int BMAX, typename ST>
+template <int BMAX, typename IN, typename ST>
 __global__ __launch_bounds__(256, resident_min_blocks<ST>()) void precode_resident_kernel(
     PrecodeParams prm) {
-  constexpr int NU = 16, AST = NU + 2, NK = BMAX / 4;
+  constexpr int NU = 16, AST = NU + 2;
+  using Sub = typename Storage<IN, 1>::Sub;
+  using RB = typename ResidentBlock<IN>::type;
+  constexpr int NK = BMAX / RB::ANT;            // k-steps held in registers
+  constexpr bool C32 = std::is_same<IN, InC32>::value;
   __shared__ __align__(16) float2 A_s[kWavesPerBlock][NU * AST];
   __shared__ __align__(16) float2 P_s[kWavesPerBlock][NU * kPST];
   __shared__ float G_s[kWavesPerBlock][NU];
@@ -186,35 +230,26 @@ __global__ __launch_bounds__(256, resident_min_blocks<ST>()) void precode_reside
   float* Ns = N_s[wv];
   const int B = prm.B, U = prm.U, S = prm.S;
   const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
-  const uint32_t hbytes = (uint32_t)B * U * 8u, tbytes = (uint32_t)U * S * 8u;
-  const uint32_t oh = c < U ? (uint32_t)(g * U + c) * 8u : kOOB;      // H[g][c]
   uint32_t ot[4];                                                      // T[c][4 g + j]
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int s = 4 * g + j;
     ot[j] = (c < U && s < S) ? (uint32_t)(c * S + s) * 8u : kOOB;
   }
-  const float2* H = (const float2*)prm.H;
-  // descriptors of subcarrier m's arrays; empty past the last subcarrier
-  auto rsrc_h = [&](int64_t m) {
-    return m < prm.n_sc ? make_rsrc(H + (size_t)m * B * U, hbytes) : make_rsrc(nullptr, 0u);
-  };
-  auto rsrc_t = [&](int64_t m) {
-    return m < prm.n_sc ? make_rsrc(prm.T + (size_t)m * U * S, tbytes) : make_rsrc(nullptr, 0u);
-  };
 
   int64_t n = (int64_t)blockIdx.x * kWavesPerBlock + wv;
-  float2 hr[NK];
-  {
-    const __amdgpu_buffer_rsrc_t rh = rsrc_h(n);
+  RB hb[NK];
+  if (n < prm.n_sc) {
+    Sub cur;
+    cur.init(offset_sc(IN{}, prm.H, n, B, U), nullptr, B, U, S, 0, c, g);
 #pragma unroll
-    for (int t = 0; t < NK; ++t) hr[t] = bload2(rh, oh, (uint32_t)(4 * t) * U * 8u);
+    for (int t = 0; t < NK; ++t) hb[t].template load<false>(cur, t * RB::ANT);
   }
   while (n < prm.n_sc) {
     const int64_t nn = n + stride;
     float2 b[1][4];                                   // b = t
     {
-      const __amdgpu_buffer_rsrc_t rt = rsrc_t(n);
+      const __amdgpu_buffer_rsrc_t rt = make_rsrc(prm.T + (size_t)n * U * S, (uint32_t)U * S * 8u);
 #pragma unroll
       for (int j = 0; j < 4; ++j) b[0][j] = bload2(rt, ot[j], 0u);
     }
@@ -222,13 +257,8 @@ __global__ __launch_bounds__(256, resident_min_blocks<ST>()) void precode_reside
     GramAcc<1> acc;
     acc.clear();
 #pragma unroll
-    for (int t = 0; t < NK; ++t) {
-      if (4 * t < B) {
-        acc.gr[0] = mfma4(hr[t].x, hr[t].x, acc.gr[0]);
-        acc.gr[0] = mfma4(hr[t].y, hr[t].y, acc.gr[0]);
-        acc.gi[0] = mfma4(hr[t].x, hr[t].y, acc.gi[0]);
-      }
-    }
+    for (int t = 0; t < NK; ++t)
+      if (t * RB::ANT < B) hb[t].template mma<true, false>(acc);
     store_gram_lds<1>(acc, As, Gs, (float*)Ps, AST, prm.beta, c, g);
     wave_lds_sync();
     AOperand<1> at;
@@ -271,21 +301,26 @@ __global__ __launch_bounds__(256, resident_min_blocks<ST>()) void precode_reside
       vs[t] = vv[t].x + vv[t].y;
     }
     const __amdgpu_buffer_rsrc_t rq = make_rsrc(prm.Q + (size_t)n * B * S, (uint32_t)B * S * 8u);
-    const __amdgpu_buffer_rsrc_t rh2 = rsrc_h(nn);
+    Sub nxt;                                          // empty past the last subcarrier
+    nxt.init(offset_sc(IN{}, prm.H, nn < prm.n_sc ? nn : n, B, U), nullptr, B, U, S, 0, c, g);
+    if (nn >= prm.n_sc) nxt.disable();
 #pragma unroll
-    for (int i = 0; i < NK / 4; ++i) {
+    for (int i = 0; i < BMAX / 16; ++i) {
       float2 hv[4];
       if (16 * i < B) {                               // tile i: H[16 i + c][4 g + t]
         wave_lds_sync();
-#pragma unroll
-        for (int t = 0; t < 4; ++t) Ps[(4 * t + g) * kPST + c] = hr[4 * i + t];
+        stage_h_tile(hb, i, Ps, c, g);
         wave_lds_sync();
 #pragma unroll
         for (int t = 0; t < 4; ++t) hv[t] = Ps[c * kPST + 4 * g + t];
       }
+      // the k-steps this tile finished with receive the next subcarrier's
+      if (C32) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t)                     // the next subcarrier's tile
-        hr[4 * i + t] = bload2(rh2, oh, (uint32_t)(16 * i + 4 * t) * U * 8u);
+        for (int t = 4 * i; t < 4 * i + 4; ++t) hb[t].template load<false>(nxt, t * RB::ANT);
+      } else if (i & 1) {
+        hb[i >> 1].template load<false>(nxt, (i >> 1) * RB::ANT);
+      }
       if (16 * i < B) {
         f4 p1 = zero4(), p2 = zero4(), p3 = zero4();
 #pragma unroll
@@ -330,9 +365,9 @@ __global__ __launch_bounds__(256, resident_min_blocks<ST>()) void precode_reside
 }
 
 // Whether the H-resident kernel covers a launch.
-template <int W, typename IN>
+template <int W>
 static bool resident_fits(const PrecodeParams& p) {
-  return std::is_same<IN, InC32>::value && W == 1 && p.S <= 16 && p.B <= 128;
+  return W == 1 && p.S <= 16 && p.B <= 128;
 }
 
 // Batched kernel: frames of different shapes in one launch (see detect.hip).
@@ -360,11 +395,11 @@ __global__ __launch_bounds__(256, 2) void precode_batch_kernel(BatchArgs args) {
 template <int W, typename IN, typename ST>
 static void launch_one(const PrecodeParams& p, const Schedule& sch, hipStream_t stream) {
   const dim3 grid(sched_grid(p.n_sc, sch)), block(kWave * kWavesPerBlock);
-  if (sch.variant == kPrecodeResident && resident_fits<W, IN>(p)) {
+  if (sch.variant == kPrecodeResident && resident_fits<W>(p)) {
     if (p.B <= 64)
-      hipLaunchKernelGGL((precode_resident_kernel<64, ST>), grid, block, 0, stream, p);
+      hipLaunchKernelGGL((precode_resident_kernel<64, IN, ST>), grid, block, 0, stream, p);
     else
-      hipLaunchKernelGGL((precode_resident_kernel<128, ST>), grid, block, 0, stream, p);
+      hipLaunchKernelGGL((precode_resident_kernel<128, IN, ST>), grid, block, 0, stream, p);
   } else if (p.S > 16 || sch.variant == kPrecodeGeneric)
     hipLaunchKernelGGL((precode_kernel<W, IN, ST>), grid, block, 0, stream, p);
   else if (sch.variant == kPrecodeStreamSmall)

@@ -4,9 +4,10 @@ to q = H v, with capacity for 64 or 128 antennas.  Cases cover both
 capacities, partial 16-antenna tiles, S = 1 .. 16, U = 1 .. 16, zero forcing,
 FP32 and FP64 scalar recurrences, and persistent grids in which every
 wavefront walks several subcarriers (the next subcarrier's channel is loaded
-during the current one's output stage).  Each result is checked against the
-FP64 oracle and bitwise against the generic kernel, which performs the same
-operations in the same order."""
+during the current one's output stage), for complex64 and FP16/BF16 channel
+storage.  Each result is checked against the FP64 oracle (on the rounded
+channel for 16-bit storage) and bitwise against the generic kernel, which
+performs the same operations in the same order."""
 import zlib
 
 import numpy as np
@@ -47,17 +48,17 @@ CASES = [
 ]
 
 
-def _run(H, T, beta, K, U, normalize, scalar, schedules):
+def _run(H, T, beta, K, U, normalize, scalar, schedules, code=0):
     from paper_1404_0424_amd import autotune
-    saved = autotune.get_schedule("precode", U, 0)
+    saved = autotune.get_schedule("precode", U, code)
     outs = []
     try:
         for v, bpc in schedules:
-            autotune.set_schedule("precode", U, 0, v, bpc)
+            autotune.set_schedule("precode", U, code, v, bpc)
             Q, qn = api().precode_cg(H, T, beta, K, normalize, scalar)
             outs.append((host(Q), host(qn)))
     finally:
-        autotune.set_schedule("precode", U, 0, *saved)
+        autotune.set_schedule("precode", U, code, *saved)
     return outs
 
 
@@ -112,3 +113,57 @@ def test_resident_falls_back_outside_its_shapes():
         assert np.array_equal(outs[0][0], outs[1][0])
         ref = O.precode_cg(d.H, d.T, d.beta, 3, True)
         assert rel_err_vec(outs[0][0], ref["Q"], axis=1) <= TOL_X
+
+
+# 16-bit storage keeps B a multiple of 8; 104 and 72 antennas end in half tiles
+CASES16 = [
+    ("128x16_S14", 37, 128, 16, 14, 4, 15.0),
+    ("104x12_S9", 29, 104, 12, 9, 4, 10.0),
+    ("72x16_S16", 21, 72, 16, 16, 5, 20.0),
+    ("64x8_S1", 33, 64, 8, 1, 3, 10.0),
+    ("24x5_S7", 37, 24, 5, 7, 5, 5.0),
+    ("8x1_S3", 9, 8, 1, 3, 1, 10.0),
+]
+
+
+def _quantized(H, dt):
+    deq = O.dequantize_f16 if dt == "f16" else O.dequantize_bf16
+    qz = O.quantize_f16 if dt == "f16" else O.quantize_bf16
+    return deq(qz(H))
+
+
+@pytest.mark.parametrize("case", CASES16, ids=[c[0] for c in CASES16])
+@pytest.mark.parametrize("dt", ["f16", "bf16"])
+@pytest.mark.parametrize("scalar", ["f32", "f64"])
+def test_resident_precode_16bit_parity(case, dt, scalar):
+    name, n, B, U, S, K, snr = case
+    rng = np.random.default_rng(zlib.crc32(name.encode()) + 1)
+    d = W.downlink_frame(rng, n, B, U, S, 6, snr)
+    Hx = api().convert(dev(d.H), dt)
+    r = _resident()
+    outs = _run(Hx, dev(d.T), d.beta, K, U, True, scalar, [(r, 0), (r, 1), (0, 0)],
+                Hx.dtype_code)
+    ref = O.precode_cg(_quantized(d.H, dt), d.T, d.beta, K, True)
+    eq = rel_err_vec(outs[0][0], ref["Q"], axis=1)
+    en = rel_err_scalar(outs[0][1], ref["qnorm"])
+    print(f"resident {dt} {name} {scalar}: eps_q={eq:.2e} eps_qnorm={en:.2e}")
+    assert eq <= TOL_X and en <= TOL_X
+    for q, qn in outs[1:]:
+        assert np.array_equal(q, outs[0][0]) and np.array_equal(qn, outs[0][1])
+
+
+@pytest.mark.parametrize("dt", ["f16", "bf16"])
+def test_resident_16bit_persistent_grid_walks_subcarriers(dt):
+    n, B, U, S = 2600, 128, 16, 14
+    rng = np.random.default_rng(99)
+    d = W.downlink_frame(rng, n, B, U, S, 6, 15.0)
+    Hx = api().convert(dev(d.H), dt)
+    r = _resident()
+    outs = _run(Hx, dev(d.T), d.beta, 4, U, True, "f32", [(r, 1), (r, 3), (0, 0)],
+                Hx.dtype_code)
+    for q, qn in outs[1:]:
+        assert np.array_equal(q, outs[0][0]) and np.array_equal(qn, outs[0][1])
+    idx = np.sort(np.random.default_rng(8).choice(n, 40, replace=False))
+    idx[0], idx[-1] = 0, n - 1
+    ref = O.precode_cg(_quantized(d.H[idx], dt), d.T[idx], d.beta, 4, True)
+    assert rel_err_vec(outs[0][0][idx], ref["Q"], axis=1) <= TOL_X
