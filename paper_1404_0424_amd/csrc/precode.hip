@@ -165,8 +165,9 @@ __global__ __launch_bounds__(256, 2) void precode_stream_kernel(PrecodeParams pr
 // [4 g + t] in FP32, so each 16-antenna tile passes through the wave's LDS;
 // the registers a k-step leaves receive the same k-step of the wave's next
 // subcarrier, which is then in flight during the rest of the output stage.
-// The 16 x S output tile is staged in LDS too, so that each store
-// instruction writes 512 contiguous bytes.  Same arithmetic in the same
+// Two LDS tile buffers alternate, so tile i + 1 is staged while tile i's
+// MFMAs run.  The 16 x S output tile is staged in LDS too, so that each
+// store instruction writes 512 contiguous bytes.  Same arithmetic in the same
 // order as precode_one.
 template <typename IN>
 struct ResidentBlock;
@@ -219,6 +220,7 @@ __global__ __launch_bounds__(256, resident_min_blocks<ST>()) void precode_reside
   constexpr bool C32 = std::is_same<IN, InC32>::value;
   __shared__ __align__(16) float2 A_s[kWavesPerBlock][NU * AST];
   __shared__ __align__(16) float2 P_s[kWavesPerBlock][NU * kPST];
+  __shared__ __align__(16) float2 H2_s[kWavesPerBlock][NU * kPST];
   __shared__ float G_s[kWavesPerBlock][NU];
   __shared__ float N_s[kWavesPerBlock][16];
   const int lane = threadIdx.x & 63;
@@ -226,6 +228,7 @@ __global__ __launch_bounds__(256, resident_min_blocks<ST>()) void precode_reside
   const int c = lane & 15, g = lane >> 4;
   float2* As = A_s[wv];
   float2* Ps = P_s[wv];
+  float2* H2 = H2_s[wv];
   float* Gs = G_s[wv];
   float* Ns = N_s[wv];
   const int B = prm.B, U = prm.U, S = prm.S;
@@ -304,24 +307,23 @@ __global__ __launch_bounds__(256, resident_min_blocks<ST>()) void precode_reside
     Sub nxt;                                          // empty past the last subcarrier
     nxt.init(offset_sc(IN{}, prm.H, nn < prm.n_sc ? nn : n, B, U), nullptr, B, U, S, 0, c, g);
     if (nn >= prm.n_sc) nxt.disable();
+    // tile i is staged in buffer i % 2 (Ps, H2) one tile ahead
+    wave_lds_sync();
+    stage_h_tile(hb, 0, H2, c, g);
+    if (C32) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) hb[t].template load<false>(nxt, t * RB::ANT);
+    }
 #pragma unroll
     for (int i = 0; i < BMAX / 16; ++i) {
-      float2 hv[4];
-      if (16 * i < B) {                               // tile i: H[16 i + c][4 g + t]
-        wave_lds_sync();
-        stage_h_tile(hb, i, Ps, c, g);
-        wave_lds_sync();
-#pragma unroll
-        for (int t = 0; t < 4; ++t) hv[t] = Ps[c * kPST + 4 * g + t];
-      }
-      // the k-steps this tile finished with receive the next subcarrier's
-      if (C32) {
-#pragma unroll
-        for (int t = 4 * i; t < 4 * i + 4; ++t) hb[t].template load<false>(nxt, t * RB::ANT);
-      } else if (i & 1) {
-        hb[i >> 1].template load<false>(nxt, (i >> 1) * RB::ANT);
-      }
+      float2* cur_t = (i & 1) ? Ps : H2;
+      float2* nxt_t = (i & 1) ? H2 : Ps;
       if (16 * i < B) {
+        wave_lds_sync();
+        float2 hv[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) hv[t] = cur_t[c * kPST + 4 * g + t];
+        if (i + 1 < BMAX / 16 && 16 * (i + 1) < B) stage_h_tile(hb, i + 1, nxt_t, c, g);
         f4 p1 = zero4(), p2 = zero4(), p3 = zero4();
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -331,22 +333,34 @@ __global__ __launch_bounds__(256, resident_min_blocks<ST>()) void precode_reside
         }
         const f4 qr = p1 - p2;
         const f4 qi = p3 - p1 - p2;
-        // output tile Q[16 i .. 16 i + 15][0 .. S-1] through LDS (A's copy
-        // is no longer needed); rows past B fall outside the descriptor
         if (c < S) {
 #pragma unroll
           for (int j = 0; j < 4; ++j)
             As[(4 * g + j) * S + c] = make_float2(qr[j] * scl, qi[j] * scl);
         }
         wave_lds_sync();
+        float2 q[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int e = 64 * r + lane;
-          const float2 q = As[e < 16 * S ? e : 0];
-          bstore2s(rq, e < 16 * S ? (uint32_t)e * 8u : kOOB, (uint32_t)(16 * i * S) * 8u, q.x,
-                   q.y);
+          q[r] = As[e < 16 * S ? e : 0];
         }
-        wave_lds_sync();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int e = 64 * r + lane;
+          bstore2s(rq, e < 16 * S ? (uint32_t)e * 8u : kOOB, (uint32_t)(16 * i * S) * 8u, q[r].x,
+                   q[r].y);
+        }
+      }
+      // k-steps of tile i + 1 (now staged) receive the next subcarrier's
+      if (C32) {
+        if (i + 1 < BMAX / 16) {
+#pragma unroll
+          for (int t = 4 * (i + 1); t < 4 * (i + 1) + 4; ++t)
+            hb[t].template load<false>(nxt, t * RB::ANT);
+        }
+      } else if (i & 1) {
+        hb[i >> 1].template load<false>(nxt, (i >> 1) * RB::ANT);
       }
     }
     {
