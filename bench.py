@@ -94,7 +94,9 @@ def main():
                     "(or the autotuner) instead of tuning")
     ap.add_argument("--save-schedules", help="write the tuned schedule table to this file")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-stream leg")
-    ap.add_argument("--serving-frames", type=int, default=600)
+    ap.add_argument("--serving-frames", type=int, default=2000)
+    ap.add_argument("--serving-skip", type=int, default=200,
+                    help="serving frames left out of the statistics (warm-up)")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the per-configuration leg (32x8, 128x8 SNR sweep, 128x32, "
                          "256x32 correlated, Gram-stage MFMA utilisation)")
@@ -297,6 +299,7 @@ def main():
                      "subcarriers_per_launch": n},
     }
 
+    samples = []          # GPU results checked against the oracle in the baseline leg
     if not args.no_variants:
         variants = {}
         for dt in ("f16", "bf16"):
@@ -308,6 +311,16 @@ def main():
                 autotune.tune("precode", wl.U, H16.dtype_code, lambda: api.precode_cg(
                     H16, T, beta, K, normalize=True, scalar_prec=scalar, qnorm=False, out=Q))
             w2, d2, p2 = timed(H16, Y16, dt)
+            o = api.detect_cg(H16, Y16, n0, es, K, m, "approx", scalar, xhat=True,
+                              out={"llr": llr})
+            api.precode_cg(H16, T, beta, K, normalize=True, scalar_prec=scalar, qnorm=False,
+                           out=Q)
+            idx = sample_index(n, 24, 2)
+            samples += [detect_sample(f"{wl.name}/{dt}/detect", idx, up.H, up.Y, n0, es, K, m,
+                                      o, dt),
+                        precode_sample(f"{wl.name}/{dt}/precode", idx, up.H, dn.T, beta, K, Q,
+                                       dt)]
+            del o
             b16 = detect_bytes_per_sc(wl.B, wl.U, wl.S, wl.m, elem_bytes=4) * n
             variants[dt] = {"solves_per_s": solves / w2, "ms_per_step": w2 * 1e3,
                             "uplink_solves_per_s": n * wl.S / d2,
@@ -339,14 +352,14 @@ def main():
                                       "what": "one frame, UL detect + DL precode, idle GPU"}
 
     if not args.no_configs:
-        result["configs"] = configs_leg(api, autotune, kernel_time, dev)
+        result["configs"] = configs_leg(api, autotune, kernel_time, dev, samples)
 
     if not args.no_comparison:
         result["comparison"] = comparison_leg(api, autotune, H, Y, T, llr, Q, up, dn, wl, n,
                                               kernel_time)
 
     if not args.no_serving:
-        result["serving"] = serving_leg(args.serving_frames)
+        result["serving"] = serving_leg(args.serving_frames, args.serving_skip)
 
     if args.copy_calibration:
         nbytes = 512 << 20
@@ -361,16 +374,90 @@ def main():
 
     if not args.no_cpu_baseline:
         # the complex64 outputs (the variants above reused the buffers)
-        api.detect_cg(H, Y, n0, es, K, m, "approx", scalar, out={"llr": llr})
+        o = api.detect_cg(H, Y, n0, es, K, m, "approx", scalar, xhat=True, out={"llr": llr})
         api.precode_cg(H, T, beta, K, normalize=True, scalar_prec=scalar, qnorm=False, out=Q)
         torch.cuda.synchronize()
-        result["cpu_baseline"] = cpu_baseline(up, dn, wl, llr, Q, args.cpu_seconds)
+        idx = sample_index(n, 24, 1)
+        samples[:0] = [detect_sample(f"{wl.name}/c32/detect", idx, up.H, up.Y, n0, es, K, m, o),
+                       precode_sample(f"{wl.name}/c32/precode", idx, up.H, dn.T, beta, K, Q)]
+        del o
+        result["cpu_baseline"] = cpu_baseline(up, dn, wl, llr, Q, args.cpu_seconds, samples)
 
     print(json.dumps(result), flush=True)
 
 
 MFMA_PEAK_FP32 = 157.3e12        # MI355X dense FP32 MFMA, FLOP/s
 MFMA_FLOPS = 2 * 16 * 16 * 4     # one v_mfma_f32_16x16x4_f32
+
+
+def sample_index(n, k, seed):
+    """k sorted subcarrier indices of a batch of n, the last one included."""
+    idx = np.sort(np.random.default_rng(seed).choice(n, min(k, n), replace=False))
+    idx[-1] = n - 1
+    return idx
+
+
+def detect_sample(label, idx, H, Y, n0, es, K, m, out, storage="c32"):
+    """Sampled detection outputs copied to the host, with the FP64 inputs
+    they came from, for the oracle check in the CPU-baseline leg."""
+    import torch
+    it = torch.from_numpy(idx).to(out["llr"].device)
+    return {"label": label, "op": "detect", "storage": storage, "H": H[idx], "Y": Y[idx],
+            "n0": n0, "es": es, "K": K, "m": m,
+            "xhat": out["xhat"][it].cpu().numpy(), "llr": out["llr"][it].cpu().numpy()}
+
+
+def precode_sample(label, idx, H, T, beta, K, Q, storage="c32"):
+    """Sampled (normalized) precoder outputs, as detect_sample."""
+    import torch
+    it = torch.from_numpy(idx).to(Q.device)
+    return {"label": label, "op": "precode", "storage": storage, "H": H[idx], "T": T[idx],
+            "beta": beta, "K": K, "Q": Q[it].cpu().numpy()}
+
+
+def rel_err_vec(x, ref, axis):
+    """max over vectors of the relative 2-norm error along ``axis``."""
+    num = np.linalg.norm(np.asarray(x, dtype=np.complex128) - ref, axis=axis)
+    den = np.linalg.norm(ref, axis=axis)
+    return float(np.max(np.where(den > 0, num / np.where(den > 0, den, 1.0), num)))
+
+
+def llr_err(L, ref):
+    """max over symbols of max_b |L - L_ref| / max(1, max_b |L_ref|)."""
+    d = np.max(np.abs(np.asarray(L, dtype=np.float64) - ref), axis=-1)
+    return float(np.max(d / np.maximum(1.0, np.max(np.abs(ref), axis=-1))))
+
+
+def oracle_errors(samples, O):
+    """Error of each sampled GPU result against the FP64 oracle on the same
+    inputs; for 16-bit storage also against the oracle on the RNE-rounded
+    inputs the GPU actually read."""
+    out = {}
+    for smp in samples:
+        st = smp["storage"]
+        rnd = None
+        if st != "c32":
+            qz, deq = ((O.quantize_f16, O.dequantize_f16) if st == "f16"
+                       else (O.quantize_bf16, O.dequantize_bf16))
+            rnd = lambda x: deq(qz(x))                       # noqa: E731
+        if smp["op"] == "detect":
+            args = (smp["n0"], smp["es"], smp["K"], smp["m"], "approx")
+            r = O.detect_cg(smp["H"], smp["Y"], *args)
+            rec = {"eps_x": rel_err_vec(smp["xhat"], r["xhat"], axis=1),
+                   "eps_llr": llr_err(smp["llr"], r["llr"])}
+            if rnd is not None:
+                r = O.detect_cg(rnd(smp["H"]), rnd(smp["Y"]), *args)
+                rec["eps_x_vs_rounded_inputs"] = rel_err_vec(smp["xhat"], r["xhat"], axis=1)
+                rec["eps_llr_vs_rounded_inputs"] = llr_err(smp["llr"], r["llr"])
+        else:
+            p = O.precode_cg(smp["H"], smp["T"], smp["beta"], smp["K"], normalize=True)
+            rec = {"eps_q": rel_err_vec(smp["Q"], p["Q"], axis=1)}
+            if rnd is not None:
+                p = O.precode_cg(rnd(smp["H"]), smp["T"], smp["beta"], smp["K"], normalize=True)
+                rec["eps_q_vs_rounded_inputs"] = rel_err_vec(smp["Q"], p["Q"], axis=1)
+        rec["subcarriers"] = int(smp["H"].shape[0])
+        out[smp["label"]] = rec
+    return out
 
 
 def mfma_count(B, U, S, K, op):
@@ -390,7 +477,7 @@ def mfma_count(B, U, S, K, op):
     return gram + chunks * ((K + 1) * 16 * W * W + (-(-B // 16)) * 12 * W)
 
 
-def configs_leg(api, autotune, kernel_time, dev):
+def configs_leg(api, autotune, kernel_time, dev, samples):
     """Each workload configuration on its own batch (autotuned schedule,
     back-to-back launches): detection and precoding rates, the detection
     kernel's HBM rate and issued-MFMA rate, and the standalone Gram +
@@ -422,6 +509,14 @@ def configs_leg(api, autotune, kernel_time, dev):
                 autotune.tune("detect", wl.U, 0, fd)
                 autotune.tune("precode", wl.U, 0, fp)
             td, tp = kernel_time(fd, reps=10), kernel_time(fp, reps=10)
+            o = api.detect_cg(H, Y, up.n0, up.es, wl.K, wl.m, "approx", scalar, xhat=True,
+                              out={"llr": llr})
+            idx = sample_index(n, 24, 3)
+            samples += [detect_sample(f"{name}/{snr:g}dB/detect", idx, up.H, up.Y, up.n0, up.es,
+                                      wl.K, wl.m, o),
+                        precode_sample(f"{name}/{snr:g}dB/precode", idx, up.H, dn.T, dn.beta,
+                                       wl.K, Q)]
+            del o
             det_b = detect_bytes_per_sc(wl.B, wl.U, wl.S, wl.m) * n
             mf = mfma_count(wl.B, wl.U, wl.S, wl.K, "detect") * n * MFMA_FLOPS
             rows[f"{snr:g}dB"] = {
@@ -515,10 +610,12 @@ def comparison_leg(api, autotune, H, Y, T, llr, Q, up, dn, wl, n, kernel_time):
                     "bytes (H, Y in, LLR out / H, T in, Q out) per launch time"}
 
 
-def serving_leg(n_frames):
+def serving_leg(n_frames, skip):
     """Mixed-shape uplink/downlink frames through the continuous-batching
     server: saturation throughput (all frames arrive at once), then Poisson
-    arrivals at 50% and 80% of it; p50/p99 arrival-to-completion latency."""
+    arrivals at 50%, 80% and 95% of it, and 80% under a small HBM budget that
+    makes requests wait for memory; p50/p99 arrival-to-completion latency
+    over all but the first ``skip`` frames of each run."""
     import torch
 
     from paper_1404_0424_amd import serving as SV
@@ -545,9 +642,9 @@ def serving_leg(n_frames):
             return SV.UplinkRequest(f.ch_id, data[f.ch_id][0], n0, 1.0, f.m, 3)
         return SV.DownlinkRequest(f.ch_id, data[f.ch_id][1], n0, 3, True)
 
-    def run(rate, frames_n, dtype="c32"):
-        _, frames = W.serving_stream(W.rng_for(4, 1 + int(rate)), 16, frames_n, rate)
-        srv = SV.Server(ex, hbm_budget=16 << 30, n_slots=4)
+    def run(rate, frames_n, dtype="c32", budget=16 << 30):
+        frames = W.serving_frames(W.rng_for(4, 1 + int(rate)), 16, frames_n, rate)
+        srv = SV.Server(ex, hbm_budget=budget, n_slots=4)
         for c in chans:
             srv.register_channel(c.ch_id, c.H, dtype)
         reqs = [request(f) for f in frames]
@@ -565,8 +662,10 @@ def serving_leg(n_frames):
                 time.sleep(d - 1e-4 if d > 2e-4 else 0)
             srv.submit(r)
         srv.drain(timeout=120)
-        st = srv.stats()
+        st = srv.stats(skip=min(skip, len(frames) // 2))
         st["mean_batch"] = float(np.mean(srv.batch_sizes[-len(frames):])) if srv.batch_sizes else 0
+        st["budget_bytes"] = budget
+        st["budget_waits"] = srv.budget_waits
         srv.close()
         return st
 
@@ -579,12 +678,24 @@ def serving_leg(n_frames):
     out = {"workload": "Poisson uplink/downlink frames, B in {64,128,256}, U in {8,16,32}, "
                        "300-1200 subcarriers x 14 symbols, 16/64/256-QAM, 5-25 dB, K=3, "
                        "16 device-resident channels, 4 stream slots, 16 GiB budget",
+           "frames_per_run": n_frames, "frames_left_out": min(skip, n_frames // 2),
            "saturation": sat}
-    for load in (0.5, 0.8):
+    for load in (0.5, 0.8, 0.95):
         st = run(load * sat["frames_per_s"], n_frames)
         log(f"serving load {load}: offered {load * sat['frames_per_s']:.0f}/s, achieved "
             f"{st['frames_per_s']:.0f}/s, p50 {st['p50_ms']:.3f} ms, p99 {st['p99_ms']:.3f} ms")
         out[f"load_{load}"] = st
+    # small budget: the channel cache plus room for two of the largest
+    # requests, so that admission waits for memory
+    need = max(ex.request_bytes(r) for c in chans for r in (
+        SV.UplinkRequest(c.ch_id, data[c.ch_id][0], 1.0, 1.0, 8, 3),
+        SV.DownlinkRequest(c.ch_id, data[c.ch_id][1], 1.0, 3, True)))
+    cache = sum(ex.channel_bytes(c.H, "c32") for c in chans)
+    st = run(0.8 * sat["frames_per_s"], n_frames, budget=cache + 2 * need)
+    log(f"serving load 0.8, budget {(cache + 2 * need) / 2**20:.0f} MiB: achieved "
+        f"{st['frames_per_s']:.0f}/s, p50 {st['p50_ms']:.3f} ms, p99 {st['p99_ms']:.3f} ms, "
+        f"{st['budget_waits']} budget waits")
+    out["load_0.8_small_budget"] = st
     # mixed precision: channels kept on the device in BF16 (Gram / matched
     # filter on 16-bit MFMA, FP32 accumulate and CG); uplink Y is rounded to
     # BF16 on the slot stream per frame
@@ -596,9 +707,10 @@ def serving_leg(n_frames):
     return out
 
 
-def cpu_baseline(up, dn, wl, llr_gpu, Q_gpu, seconds):
+def cpu_baseline(up, dn, wl, llr_gpu, Q_gpu, seconds, samples=()):
     """The FP64 oracle on the host, single-threaded, on a bounded sample of the
-    same workload; also reports the GPU's error against it on that sample."""
+    same workload; also reports the GPU's error against it on that sample and
+    on the sampled results of every other leg (storage types, configurations)."""
     sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
     from oracle import mimo_oracle as O
     from threadpoolctl import threadpool_limits
@@ -624,10 +736,15 @@ def cpu_baseline(up, dn, wl, llr_gpu, Q_gpu, seconds):
         el_s = time.perf_counter() - t0
     solves = 2 * done * wl.S
     log(f"cpu oracle: {done} subcarriers in {el_s:.1f}s")
+    errors = oracle_errors(samples, O)
+    for k, v in errors.items():
+        log(f"error vs oracle {k}: " + ", ".join(f"{a}={b:.2e}" for a, b in v.items()
+                                                if a != "subcarriers"))
     return {"value": solves / el_s, "unit": "subcarrier-solves/s", "cores": 1, "kind": "oracle",
             "sample": f"{done} random subcarriers of the timed batch ({wl.S} symbols each), "
                       f"uplink detection + downlink precoding, numpy FP64, 1 thread",
-            "gpu_error_vs_oracle_on_sample": {"eps_llr": el, "eps_q": eq}}
+            "gpu_error_vs_oracle_on_sample": {"eps_llr": el, "eps_q": eq},
+            "gpu_error_vs_oracle_by_result": errors}
 
 
 if __name__ == "__main__":

@@ -22,6 +22,7 @@ from __future__ import annotations
 import collections
 import concurrent.futures as cf
 import dataclasses
+import itertools
 import threading
 import time
 
@@ -69,7 +70,7 @@ class AdmissionError(RuntimeError):
     """A request can never fit the HBM budget."""
 
 
-@dataclasses.dataclass
+@dataclasses.dataclass(eq=False)          # queue entries compare by identity
 class _Pending:
     req: object
     fut: cf.Future
@@ -102,6 +103,8 @@ class Server:
         self._running = True
         self._t_first = None
         self.peak_bytes = 0                # largest reserved + cached bytes seen
+        self.budget_waits = 0              # queue heads that waited for HBM budget
+        self._blocked = None               # the head currently waiting for budget
         self.admit_order: list = []        # ids of requests in admission order
         self._thread = threading.Thread(target=self._loop, name="mimo-serving", daemon=True)
         self._thread.start()
@@ -125,6 +128,12 @@ class Server:
 
     def _cache_bytes(self) -> int:
         return sum(self._channels.values())
+
+    @property
+    def cache_bytes(self) -> int:
+        """Device bytes held by registered channels (part of the budget)."""
+        with self._lock:
+            return self._cache_bytes()
 
     # ------------------------------------------------------------ requests
     def submit(self, req) -> cf.Future:
@@ -165,12 +174,15 @@ class Server:
         self._thread.join()
 
     # ------------------------------------------------------------ stats
-    def stats(self, reset: bool = False) -> dict:
+    def stats(self, reset: bool = False, skip: int = 0) -> dict:
+        """Latency and throughput of the completed requests; ``skip`` leaves
+        out the first requests by submission time (a warm-up)."""
         with self._lock:
             done = list(self._done)
             if reset:
                 self._done.clear()
                 self._t_first = None
+        done = sorted(done, key=lambda r: r.t_submit)[skip:]
         if not done:
             return {"frames": 0}
         lat = np.array([r.latency for r in done])
@@ -208,10 +220,13 @@ class Server:
             head = self._queue[0]
             cache = self._cache_bytes()
             if self._reserved + head.need + cache > self.budget:
+                if self._blocked is not head:
+                    self._blocked = head
+                    self.budget_waits += 1
                 return
             key = self.ex.batch_key(head.req)
             group, total = [head], head.need
-            for p in list(self._queue)[1:self.lookahead]:
+            for p in itertools.islice(self._queue, 1, self.lookahead):
                 if len(group) >= self.max_batch:
                     break
                 if (self.ex.batch_key(p.req) == key

@@ -258,9 +258,16 @@ def serving_stream(rng: np.random.Generator, n_channels: int, n_frames: int, rat
         U = int(rng.choice(U_set))
         n_sc = int(rng.integers(n_sc_range[0], n_sc_range[1] + 1))
         chans.append(StreamChannel(c, B, U, n_sc, iid_channel(rng, n_sc, B, U)))
+    return chans, serving_frames(rng, n_channels, n_frames, rate, m_set, snr_range,
+                                 uplink_share)
+
+
+def serving_frames(rng: np.random.Generator, n_channels: int, n_frames: int, rate: float,
+                   m_set=(4, 6, 8), snr_range=(5.0, 25.0), uplink_share: float = 0.5):
+    """The frames of a serving stream over existing channels 0 .. n_channels-1
+    (see serving_stream)."""
     gaps = (rng.exponential(1.0 / rate, n_frames) if rate > 0 else np.zeros(n_frames))
     t = np.cumsum(gaps) - (gaps[0] if n_frames else 0.0)
-    frames = [StreamFrame(float(t[i]), int(rng.integers(n_channels)),
-                          bool(rng.random() < uplink_share), int(rng.choice(m_set)),
-                          float(rng.uniform(*snr_range))) for i in range(n_frames)]
-    return chans, frames
+    return [StreamFrame(float(t[i]), int(rng.integers(n_channels)),
+                        bool(rng.random() < uplink_share), int(rng.choice(m_set)),
+                        float(rng.uniform(*snr_range))) for i in range(n_frames)]

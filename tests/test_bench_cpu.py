@@ -1,10 +1,13 @@
 """Host-side logic of bench.py (no GPU): the algorithmic byte and MFMA counts
-it reports, the guard on recorded HBM traffic, and the one-GPU contract."""
+it reports, the guard on recorded HBM traffic, the one-GPU contract, and the
+report of sampled GPU results against the oracle."""
 import os
 import subprocess
 import sys
 
 import bench
+import numpy as np
+import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -40,3 +43,57 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120, cwd=ROOT)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_sample_index_is_sorted_and_keeps_the_last_subcarrier():
+    idx = bench.sample_index(100, 24, 3)
+    assert len(idx) == 24 and idx[-1] == 99 and np.all(np.diff(idx) > 0)
+    assert list(bench.sample_index(5, 24, 3)) == [0, 1, 2, 3, 4]
+
+
+def _detect_precode_refs(rng):
+    from oracle import mimo_oracle as O
+    from paper_1404_0424_amd import workload as W
+    up = W.uplink_frame(rng, 6, 16, 4, 3, 4, 10.0)
+    dn = W.downlink_frame(rng, 6, 16, 4, 3, 4, 10.0, H=up.H)
+    return O, up, dn
+
+
+def test_oracle_errors_measure_a_planted_deviation():
+    """The error report against the oracle finds deviations planted in
+    otherwise exact results, with the metrics' definitions."""
+    O, up, dn = _detect_precode_refs(np.random.default_rng(5))
+    r = O.detect_cg(up.H, up.Y, up.n0, up.es, 3, 4, "approx")
+    p = O.precode_cg(up.H, dn.T, dn.beta, 3, normalize=True)
+    x, L, Q = r["xhat"].copy(), r["llr"].copy(), p["Q"].copy()
+    x[2, :, 1] *= 1 + 1e-3                           # one user vector, 1e-3 relative
+    scale = max(1.0, float(np.abs(L[4, 1, 2]).max()))
+    L[4, 1, 2, 0] += 0.5 * scale                     # one LLR, 0.5 of its symbol's scale
+    Q[1, :, 0] *= 1 - 2e-4                           # one precoded vector
+    samples = [{"label": "d", "op": "detect", "storage": "c32", "H": up.H, "Y": up.Y,
+                "n0": up.n0, "es": up.es, "K": 3, "m": 4, "xhat": x, "llr": L},
+               {"label": "p", "op": "precode", "storage": "c32", "H": up.H, "T": dn.T,
+                "beta": dn.beta, "K": 3, "Q": Q}]
+    e = bench.oracle_errors(samples, O)
+    assert e["d"]["eps_x"] == pytest.approx(1e-3, rel=1e-6)
+    assert e["d"]["eps_llr"] == pytest.approx(0.5, rel=1e-9)
+    assert e["p"]["eps_q"] == pytest.approx(2e-4, rel=1e-6)
+    assert e["d"]["subcarriers"] == 6
+
+
+def test_oracle_errors_16bit_against_rounded_inputs():
+    """For 16-bit storage the report also compares with the oracle on the
+    rounded inputs: exact there for results computed from them."""
+    O, up, dn = _detect_precode_refs(np.random.default_rng(6))
+    rnd = lambda z: O.dequantize_bf16(O.quantize_bf16(z))          # noqa: E731
+    r = O.detect_cg(rnd(up.H), rnd(up.Y), up.n0, up.es, 3, 4, "approx")
+    p = O.precode_cg(rnd(up.H), dn.T, dn.beta, 3, normalize=True)
+    samples = [{"label": "d", "op": "detect", "storage": "bf16", "H": up.H, "Y": up.Y,
+                "n0": up.n0, "es": up.es, "K": 3, "m": 4, "xhat": r["xhat"], "llr": r["llr"]},
+               {"label": "p", "op": "precode", "storage": "bf16", "H": up.H, "T": dn.T,
+                "beta": dn.beta, "K": 3, "Q": p["Q"]}]
+    e = bench.oracle_errors(samples, O)
+    assert e["d"]["eps_x_vs_rounded_inputs"] == 0.0
+    assert e["d"]["eps_llr_vs_rounded_inputs"] == 0.0
+    assert e["p"]["eps_q_vs_rounded_inputs"] == 0.0
+    assert 1e-4 < e["d"]["eps_x"] < 3e-2 and 1e-4 < e["p"]["eps_q"] < 3e-2

@@ -92,6 +92,22 @@ def test_budget_is_never_exceeded_and_waiters_are_admitted():
     srv.close()
     assert srv.peak_bytes <= budget
     assert ex.max_running == 2                                # memory, not slots, limited it
+    assert srv.budget_waits >= 1 and srv.cache_bytes == cache
+
+
+def test_stats_skip_leaves_out_the_first_requests():
+    ex = FakeExecutor(0.001)
+    srv = SV.Server(ex, hbm_budget=1 << 30, n_slots=2)
+    srv.register_channel("a", np.zeros((10, 8, 4)))
+    futs = [srv.submit(_up("a")) for _ in range(10)]
+    res = [f.result(timeout=10) for f in futs]
+    srv.close()
+    assert srv.budget_waits == 0
+    full, tail = srv.stats(), srv.stats(skip=4)
+    assert full["frames"] == 10 and tail["frames"] == 6
+    lat = sorted(r.latency for r in sorted(res, key=lambda r: r.t_submit)[4:])
+    assert tail["p50_ms"] == pytest.approx(float(np.percentile(lat, 50)) * 1e3)
+    assert srv.stats(skip=10) == {"frames": 0}
 
 
 def test_rejections():
