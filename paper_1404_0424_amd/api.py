@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
+import math
 
 import torch
 
@@ -172,29 +173,45 @@ def workspace_bytes(B, U, S, K, n_sc, op: str = "detect", sinr_mode: str = "appr
     return int(L.lib().mimo_workspace_bytes(L.shape(B, U, S, K, n_sc), opc, mode))
 
 
+def _views(dev, dtype, shapes):
+    """One allocation for a batch's outputs; a view of it per shape (each
+    starting on a 64-element boundary)."""
+    sizes = [math.prod(s) for s in shapes]
+    offs = [0]
+    for z in sizes:
+        offs.append(offs[-1] + (z + 63) // 64 * 64)
+    buf = torch.empty(offs[-1], dtype=dtype, device=dev)
+    return [buf[o:o + z].view(s) for o, z, s in zip(offs, sizes, shapes)]
+
+
 def detect_cg_batch(frames, K: int | list, qam_bits: int, scalar_prec: str = "f32",
                     xhat: bool = False, stream=None) -> list[dict]:
     """Detect up to MIMO_MAX_BATCH frames of different shapes in one launch.
     ``frames`` is a list of (H, Y, n0, es) with the same storage type; K is
-    one value or one per frame.  Returns one output dict per frame."""
+    one value or one per frame.  Returns one output dict per frame (views of
+    one allocation per output kind)."""
     if not frames:
         return []
     Ks = K if isinstance(K, (list, tuple)) else [K] * len(frames)
     arr = (L.MimoFrame * len(frames))()
-    outs, code0 = [], None
-    for i, ((H, Y, n0, es), k) in enumerate(zip(frames, Ks)):
+    code0, dims = None, []
+    for H, Y, n0, es in frames:
         hp, code, n, B, U = _channel(H)
         if code0 is None:
             code0 = code
         elif code != code0:
             raise ValueError("all frames of a batch need the same storage type")
         yp, S = _rhs(Y, code, n, B)
-        dev = H.device
-        llr = torch.empty((n, U, S, qam_bits), dtype=torch.float32, device=dev)
-        xh = torch.empty((n, U, S), dtype=torch.complex64, device=dev) if xhat else None
-        arr[i] = L.MimoFrame(n, B, U, S, int(k), hp, yp, llr.data_ptr(), _ptr(xh),
+        dims.append((hp, yp, n, B, U, S))
+    dev = frames[0][0].device
+    llrs = _views(dev, torch.float32, [(n, U, S, qam_bits) for _, _, n, _, U, S in dims])
+    xhs = (_views(dev, torch.complex64, [(n, U, S) for _, _, n, _, U, S in dims]) if xhat
+           else [None] * len(frames))
+    outs = []
+    for i, ((hp, yp, n, B, U, S), (_, _, n0, es), k) in enumerate(zip(dims, frames, Ks)):
+        arr[i] = L.MimoFrame(n, B, U, S, int(k), hp, yp, llrs[i].data_ptr(), _ptr(xhs[i]),
                              float(n0), float(es), 0.0, 0)
-        outs.append({"llr": llr, "xhat": xh} if xhat else {"llr": llr})
+        outs.append({"llr": llrs[i], "xhat": xhs[i]} if xhat else {"llr": llrs[i]})
     prec = {"f32": L.MIMO_SCALAR_F32, "f64": L.MIMO_SCALAR_F64}[scalar_prec]
     L.check(L.lib().mimo_detect_cg_batch(ctypes.addressof(arr), len(frames), code0,
                                          int(qam_bits), prec, _stream(stream)))
@@ -204,25 +221,32 @@ def detect_cg_batch(frames, K: int | list, qam_bits: int, scalar_prec: str = "f3
 def precode_cg_batch(frames, K: int | list, scalar_prec: str = "f32", qnorm: bool = False,
                      stream=None) -> list[tuple]:
     """Precode up to MIMO_MAX_BATCH frames in one launch.  ``frames`` is a
-    list of (H, T, beta, normalize).  Returns (Q, qnorm) per frame."""
+    list of (H, T, beta, normalize).  Returns (Q, qnorm) per frame (views of
+    one allocation per output kind)."""
     if not frames:
         return []
     Ks = K if isinstance(K, (list, tuple)) else [K] * len(frames)
     arr = (L.MimoFrame * len(frames))()
-    outs, code0 = [], None
-    for i, ((H, T, beta, normalize), k) in enumerate(zip(frames, Ks)):
+    code0, dims = None, []
+    for H, T, beta, normalize in frames:
         hp, code, n, B, U = _channel(H)
         if code0 is None:
             code0 = code
         elif code != code0:
             raise ValueError("all frames of a batch need the same storage type")
         _check_c64(T, "T")
-        S = T.shape[2]
-        Q = torch.empty((n, B, S), dtype=torch.complex64, device=T.device)
-        qn = torch.empty((n, S), dtype=torch.float32, device=T.device) if qnorm else None
-        arr[i] = L.MimoFrame(n, B, U, S, int(k), hp, T.data_ptr(), Q.data_ptr(), _ptr(qn),
-                             0.0, 0.0, float(beta), int(bool(normalize)))
-        outs.append((Q, qn))
+        if T.dim() != 3 or T.shape[0] != n or T.shape[1] != U:
+            raise ValueError(f"T shape {tuple(T.shape)} does not match H ({n}, {B}, {U})")
+        dims.append((hp, n, B, U, T.shape[2]))
+    dev = frames[0][1].device
+    Qs = _views(dev, torch.complex64, [(n, B, S) for _, n, B, _, S in dims])
+    qns = (_views(dev, torch.float32, [(n, S) for _, n, _, _, S in dims]) if qnorm
+           else [None] * len(frames))
+    outs = []
+    for i, ((hp, n, B, U, S), (_, T, beta, normalize), k) in enumerate(zip(dims, frames, Ks)):
+        arr[i] = L.MimoFrame(n, B, U, S, int(k), hp, T.data_ptr(), Qs[i].data_ptr(),
+                             _ptr(qns[i]), 0.0, 0.0, float(beta), int(bool(normalize)))
+        outs.append((Qs[i], qns[i]))
     prec = {"f32": L.MIMO_SCALAR_F32, "f64": L.MIMO_SCALAR_F64}[scalar_prec]
     L.check(L.lib().mimo_precode_cg_batch(ctypes.addressof(arr), len(frames), code0, prec,
                                           _stream(stream)))

@@ -77,6 +77,7 @@ class _Pending:
     t_submit: float
     need: int
     ready: object = None
+    key: object = None        # executor batch key, computed once at submission
 
 
 class Server:
@@ -152,7 +153,7 @@ class Server:
             if self._t_first is None:
                 self._t_first = t
             ready = self.ex.on_submit(req) if hasattr(self.ex, "on_submit") else None
-            self._queue.append(_Pending(req, fut, t, need, ready))
+            self._queue.append(_Pending(req, fut, t, need, ready, self.ex.batch_key(req)))
             self._lock.notify_all()
         return fut
 
@@ -224,12 +225,12 @@ class Server:
                     self._blocked = head
                     self.budget_waits += 1
                 return
-            key = self.ex.batch_key(head.req)
+            key = head.key
             group, total = [head], head.need
             for p in itertools.islice(self._queue, 1, self.lookahead):
                 if len(group) >= self.max_batch:
                     break
-                if (self.ex.batch_key(p.req) == key
+                if (p.key == key
                         and self._reserved + total + p.need + cache <= self.budget):
                     group.append(p)
                     total += p.need
