@@ -527,12 +527,16 @@ def configs_leg(api, autotune, kernel_time, dev, samples):
                 "detect_mfma_tflops": mf / td / 1e12,
                 "detect_mfma_frac": mf / td / MFMA_PEAK_FP32}
             if name in ("mixed_128x32", "corr_256x32") and snr == snrs[0]:
-                tg = kernel_time(lambda: api.gram_mf(H, Y, up.n0 / up.es), reps=10)
+                fg = lambda: api.gram_mf(H, Y, up.n0 / up.es)
+                eg = autotune.tune("gram_mf", wl.U, 0, fg)
+                tg = kernel_time(fg, reps=10)
                 gf = mfma_count(wl.B, wl.U, wl.S, wl.K, "gram_mf") * n * MFMA_FLOPS
                 gb = (8 * wl.B * wl.U + 8 * wl.B * wl.S + 8 * wl.U * wl.U + 8 * wl.U * wl.S) * n
                 rows[f"{snr:g}dB"]["gram_stage"] = {
                     "kernel_ms": tg * 1e3, "mfma_tflops": gf / tg / 1e12,
                     "mfma_frac": gf / tg / MFMA_PEAK_FP32, "hbm_gbs": gb / tg / 1e9,
+                    "schedule": {"variant": autotune.variants("gram_mf")[eg["best"]["variant"]],
+                                 "blocks_per_cu": eg["best"]["blocks_per_cu"]},
                     "what": "standalone mimo_gram_mf (A = H^H H + reg I and b = H^H Y)"}
             log(f"config {name} ({F} frames) {snr:g} dB: detect {td * 1e3:.3f} ms "
                 f"({det_b / td / 1e9:.0f} GB/s, MFMA {mf / td / 1e12:.1f} TF), "

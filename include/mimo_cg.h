@@ -260,7 +260,9 @@ int mimo_precode_cgls(const mimo_shape* shape, const void* H, const void* T,
  *                 forms, for S <= 16; 3 resident = H kept in registers from
  *                 the Gram to q = H v so that it is read once, for U <= 16,
  *                 S <= 16 and B <= 128 in any storage type; other shapes use
- *                 1, or 0 when S > 16)
+ *                 1, or 0 when S > 16; Gram + matched filter: 0 generic,
+ *                 1 stream = next block and next subcarrier in flight, for
+ *                 S <= 16 or no Y, larger S uses 0)
  *   blocks_per_cu 0: one wavefront per subcarrier; k in [1, 64]: persistent
  *                 grid of k four-wavefront blocks per compute unit
  * Results do not depend on the schedule (every variant performs the same

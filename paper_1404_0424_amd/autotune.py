@@ -23,7 +23,8 @@ from . import _lib as L
 
 BLOCKS_PER_CU = (0, 1, 2, 3, 4, 5, 6, 8)
 BASELINE_VARIANTS = {"plain"}      # reference mappings, never chosen
-OPS = {"detect": L.MIMO_OP_DETECT, "precode": L.MIMO_OP_PRECODE}
+OPS = {"detect": L.MIMO_OP_DETECT, "precode": L.MIMO_OP_PRECODE,
+       "gram_mf": L.MIMO_OP_GRAM_MF}
 
 
 def variants(op: str) -> list[str]:

@@ -79,7 +79,8 @@ void sched_defaults() {
   for (int u = 0; u < kUClasses; ++u)
     for (int d = 0; d < kDtypes; ++d) {
       g_sched[MIMO_OP_DETECT][u][d].store(pack(mimo::kDetectStream, 0));
-      g_sched[MIMO_OP_PRECODE][u][d].store(pack(mimo::kPrecodeGeneric, 4));
+      g_sched[MIMO_OP_PRECODE][u][d].store(pack(mimo::kPrecodeResident, 8));
+      g_sched[MIMO_OP_GRAM_MF][u][d].store(pack(mimo::kGramStream, 0));
     }
 }
 
@@ -93,7 +94,7 @@ int variant_count(int op) {
   switch (op) {
     case MIMO_OP_DETECT: return mimo::kDetectVariants;
     case MIMO_OP_PRECODE: return mimo::kPrecodeVariants;
-    case MIMO_OP_GRAM_MF: return 1;
+    case MIMO_OP_GRAM_MF: return mimo::kGramVariants;
   }
   return 0;
 }
@@ -147,8 +148,11 @@ const char* mimo_tune_variant_name(int op, int variant) {
       case mimo::kPrecodeStreamSmall: return "stream-small";
       case mimo::kPrecodeResident: return "resident";
     }
-  } else if (variant == 0 && op == MIMO_OP_GRAM_MF) {
-    return "generic";
+  } else if (op == MIMO_OP_GRAM_MF) {
+    switch (variant) {
+      case mimo::kGramGeneric: return "generic";
+      case mimo::kGramStream: return "stream";
+    }
   }
   return nullptr;
 }
@@ -215,7 +219,9 @@ int mimo_gram_mf(const mimo_shape* shape, const void* H, const void* Y, int in_d
   if (b && !Y) return fail(MIMO_EINVAL, "b requested without Y");
   if (shape->n_sc == 0) return MIMO_OK;
   mimo::GramParams p{H, Y, shape->B, shape->U, shape->S, shape->n_sc, reg, (float2*)A, (float2*)b};
-  return hip_status(mimo::launch_gram_mf(p, in_dtype, (hipStream_t)stream), "gram_mf launch");
+  return hip_status(mimo::launch_gram_mf(p, in_dtype, get_sched(MIMO_OP_GRAM_MF, shape->U, in_dtype),
+                                         (hipStream_t)stream),
+                    "gram_mf launch");
 }
 
 int mimo_detect_cg(const mimo_shape* shape, const void* H, const void* Y, int in_dtype, float n0,

@@ -51,10 +51,88 @@ __global__ __launch_bounds__(256) void gram_mf_kernel(GramParams prm) {
   }
 }
 
+// Streaming form for S <= 16 (one right-hand-side chunk): the H / Y blocks
+// ping-pong between two register buffers with the next block's loads in
+// flight during the current block's MFMAs, and the first block of the
+// wave's next subcarrier is issued before A and b of the current one are
+// written.  Loads are issued on every path (an empty descriptor after the
+// last subcarrier).  Same arithmetic in the same order as gram_mf_kernel.
+template <int W, typename IN, bool HAS_Y>
+__global__ __launch_bounds__(256, W == 1 ? 3 : 2) void gram_mf_stream_kernel(GramParams prm) {
+  constexpr int NU = 16 * W;
+  constexpr int AST = NU + 2;
+  using Sub = typename Storage<IN, W>::Sub;
+  using Blk = typename Storage<IN, W>::SmallBlock;
+  __shared__ __align__(16) float2 A_s[kWavesPerBlock][NU * AST];
+  __shared__ float G_s[kWavesPerBlock][NU];
+  __shared__ float X_s[kWavesPerBlock][gram_scratch_floats<W>()];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+  const int c = lane & 15, g = lane >> 4;
+  float2* As = A_s[wv];
+  const int B = prm.B, U = prm.U, S = prm.S;
+  const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
+  auto y_of = [&](int64_t m) { return HAS_Y ? offset_sc(IN{}, prm.Y, m, B, S) : nullptr; };
+
+  int64_t n = (int64_t)blockIdx.x * kWavesPerBlock + wv;
+  Sub cur;
+  Blk blk;
+  if (n < prm.n_sc) {
+    cur.init(offset_sc(IN{}, prm.H, n, B, U), y_of(n), B, U, S, 0, c, g);
+    blk.template load<HAS_Y>(cur, 0);
+  }
+  while (n < prm.n_sc) {
+    const int64_t nn = n + stride;
+    const int64_t nc = nn < prm.n_sc ? nn : n;
+    Sub nxt;
+    nxt.init(offset_sc(IN{}, prm.H, nc, B, U), y_of(nc), B, U, S, 0, c, g);
+    if (nn >= prm.n_sc) nxt.disable();
+    GramAcc<W> acc;
+    acc.clear();
+    Blk alt;
+    for (int b0 = 0;; b0 += 2 * Blk::ANT) {
+      const bool more1 = b0 + Blk::ANT < B;
+      alt.template load<HAS_Y>(more1 ? cur : nxt, more1 ? b0 + Blk::ANT : 0);
+      blk.template mma<true, HAS_Y>(acc);
+      if (!more1) {
+        blk = alt;
+        break;
+      }
+      const bool more2 = b0 + 2 * Blk::ANT < B;
+      blk.template load<HAS_Y>(more2 ? cur : nxt, more2 ? b0 + 2 * Blk::ANT : 0);
+      alt.template mma<true, HAS_Y>(acc);
+      if (!more2) break;
+    }
+    if (HAS_Y) finish_mf(IN{}, acc);
+    store_gram_lds<W>(acc, As, G_s[wv], X_s[wv], AST, prm.reg, c, g);
+    wave_lds_sync();
+    float2* An = prm.A + (size_t)n * U * U;
+    for (int idx = lane; idx < U * U; idx += kWave) An[idx] = As[(idx / U) * AST + idx % U];
+    if (HAS_Y && prm.b) {
+#pragma unroll
+      for (int w = 0; w < W; ++w)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int u = 16 * w + c, s = 4 * g + j;
+          if (u < U && s < S)
+            prm.b[((size_t)n * U + u) * S + s] = make_float2(acc.dr[w][j], acc.di[w][j]);
+        }
+    }
+    wave_lds_sync();
+    n = nn;
+    cur = nxt;
+  }
+}
+
 template <int W, typename IN>
-static hipError_t launch_y(const GramParams& p, hipStream_t stream) {
-  const dim3 grid(wave_grid(p.n_sc)), block(kWave * kWavesPerBlock);
-  if (p.Y)
+static hipError_t launch_y(const GramParams& p, const Schedule& sch, hipStream_t stream) {
+  const dim3 grid(sched_grid(p.n_sc, sch)), block(kWave * kWavesPerBlock);
+  const bool stream_form = sch.variant == kGramStream && (!p.Y || p.S <= 16);
+  if (p.Y && stream_form)
+    hipLaunchKernelGGL((gram_mf_stream_kernel<W, IN, true>), grid, block, 0, stream, p);
+  else if (stream_form)
+    hipLaunchKernelGGL((gram_mf_stream_kernel<W, IN, false>), grid, block, 0, stream, p);
+  else if (p.Y)
     hipLaunchKernelGGL((gram_mf_kernel<W, IN, true>), grid, block, 0, stream, p);
   else
     hipLaunchKernelGGL((gram_mf_kernel<W, IN, false>), grid, block, 0, stream, p);
@@ -62,18 +140,20 @@ static hipError_t launch_y(const GramParams& p, hipStream_t stream) {
 }
 
 template <int W>
-static hipError_t launch_in(const GramParams& p, int in_dtype, hipStream_t stream) {
+static hipError_t launch_in(const GramParams& p, int in_dtype, const Schedule& sch,
+                            hipStream_t stream) {
   switch (in_dtype) {
-    case 0: return launch_y<W, InC32>(p, stream);
-    case 1: return launch_y<W, InF16>(p, stream);
-    case 2: return launch_y<W, InBF16>(p, stream);
+    case 0: return launch_y<W, InC32>(p, sch, stream);
+    case 1: return launch_y<W, InF16>(p, sch, stream);
+    case 2: return launch_y<W, InBF16>(p, sch, stream);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_gram_mf(const GramParams& p, int in_dtype, hipStream_t stream) {
-  if (p.U <= 16) return launch_in<1>(p, in_dtype, stream);
-  return launch_in<2>(p, in_dtype, stream);
+hipError_t launch_gram_mf(const GramParams& p, int in_dtype, const Schedule& sch,
+                          hipStream_t stream) {
+  if (p.U <= 16) return launch_in<1>(p, in_dtype, sch, stream);
+  return launch_in<2>(p, in_dtype, sch, stream);
 }
 
 // ---------------------------------------------------------------- ingest

@@ -31,7 +31,11 @@ hipError_t launch_detect_cgls(const DetectParams& p, int in_dtype, int scalar_f6
                               hipStream_t stream);
 hipError_t launch_precode_cgls(const PrecodeParams& p, int in_dtype, int scalar_f64,
                                hipStream_t stream);
-hipError_t launch_gram_mf(const GramParams& p, int in_dtype, hipStream_t stream);
+// Standalone Gram + matched filter: generic, or streaming (next block and
+// next subcarrier in flight; S <= 16, larger S uses the generic kernel).
+enum { kGramGeneric = 0, kGramStream = 1, kGramVariants = 2 };
+hipError_t launch_gram_mf(const GramParams& p, int in_dtype, const Schedule& sch,
+                          hipStream_t stream);
 hipError_t launch_convert(const float2* src, uint16_t* dst, int dst_dtype, int64_t n, int R,
                           int C, hipStream_t stream);
 

@@ -191,6 +191,48 @@ def test_gram_mf_parity(B, U, S, n):
     assert np.max(np.abs(host(A2) - O.gram(f.H))) <= 2e-6 * np.max(np.abs(A0))
 
 
+GRAM_SCHEDULE_CASES = [(B, U, S, n, dt) for dt in ("c32", "bf16")
+                       for (B, U, S, n) in [(128, 16, 14, 2600), (128, 32, 14, 1100),
+                                            (30, 5, 9, 37), (24, 20, 16, 13), (256, 32, 33, 6)]
+                       if dt == "c32" or B % 8 == 0]       # 16-bit storage: B % 8 == 0
+
+
+@pytest.mark.parametrize("B,U,S,n,dt", GRAM_SCHEDULE_CASES)
+def test_gram_mf_schedules_are_bitwise_equal(B, U, S, n, dt):
+    """The streaming Gram / matched-filter kernel (next block and next
+    subcarrier in flight) equals the generic one bitwise, with and without
+    Y, on one-wave-per-subcarrier and persistent grids (2600 subcarriers on
+    one block per CU: every wave walks several subcarriers); S > 16 falls
+    back to the generic kernel."""
+    from paper_1404_0424_amd import autotune
+    rng = np.random.default_rng(B + 7 * U + S)
+    f = W.uplink_frame(rng, n, B, U, S, 4, 10.0)
+    H, Y = dev(f.H), dev(f.Y)
+    code = 0
+    if dt != "c32":
+        H, Y = api().convert(H, dt), api().convert(Y, dt)
+        code = H.dtype_code
+    names = autotune.variants("gram_mf")
+    saved = autotune.get_schedule("gram_mf", U, code)
+    outs = []
+    try:
+        for v, bpc in [(names.index("generic"), 0), (names.index("stream"), 0),
+                       (names.index("stream"), 1), (names.index("stream"), 3)]:
+            autotune.set_schedule("gram_mf", U, code, v, bpc)
+            A, b = api().gram_mf(H, Y, reg=0.21)
+            A2, _ = api().gram_mf(H, None, reg=0.0)
+            outs.append((host(A), host(b), host(A2)))
+    finally:
+        autotune.set_schedule("gram_mf", U, code, *saved)
+    for o in outs[1:]:
+        for a, r in zip(o, outs[0]):
+            assert np.array_equal(a, r)
+    if dt == "c32":
+        A0 = O.regularized_gram(f.H, 0.21)
+        eA = np.max(np.linalg.norm(outs[0][0] - A0, axis=(1, 2)) / np.linalg.norm(A0, axis=(1, 2)))
+        assert eA <= 2e-6
+
+
 # ---------------------------------------------------------------- 16-bit ingest
 
 @pytest.mark.parametrize("dt", ["f16", "bf16"])
