@@ -304,6 +304,64 @@ def test_full_size_sampled(wl, frames):
     assert np.all(np.isfinite(host(out["llr"])))
 
 
+# bench.py's batches: (workload, frames, detection schedules, precoding schedules);
+# the schedules are the ones the autotuner has picked on MI355X
+BENCH_BATCHES = [
+    ("mixed_128x16", 16, [("stream-small", 0), ("stream", 0)], [("resident", 8), ("stream-small", 0)]),
+    ("plain_128x8", 16, [("stream-small", 0)], [("resident", 8)]),
+    ("mixed_128x32", 8, [("stream", 0)], [("stream", 0)]),
+    ("small_32x8", 1024, [("stream-small", 0)], [("resident", 8)]),
+    ("corr_256x32", 1, [("stream", 0)], [("stream", 0)]),
+]
+
+
+@pytest.mark.parametrize("wl,frames,dsched,psched", BENCH_BATCHES,
+                         ids=[b[0] for b in BENCH_BATCHES])
+def test_bench_batches_sampled(wl, frames, dsched, psched):
+    """bench.py's full batches under the schedules it times: detection and
+    precoding of every subcarrier on the GPU, a sample (the last subcarrier
+    included) checked against the oracle, and the schedules bitwise equal."""
+    from paper_1404_0424_amd import autotune
+    w = W.WORKLOADS[wl]
+    rng = W.rng_for(11, 0)
+    snr = w.snr_db[0] if len(w.snr_db) == 1 else 10.0
+    f = W.uplink_frame(rng, w.n_sc * frames, w.B, w.U, w.S, w.m, snr, channel=w.channel,
+                       rho_bs=w.rho_bs, rho_ue=w.rho_ue)
+    d = W.downlink_frame(rng, f.H.shape[0], w.B, w.U, w.S, w.m, snr, H=f.H)
+    sc = "f64" if w.scalar_f64 else "f32"
+    H, Y, T = dev(f.H), dev(f.Y), dev(d.T)
+    saved = [autotune.get_schedule(op, w.U, 0) for op in ("detect", "precode")]
+    dets, pres = [], []
+    try:
+        for name, bpc in dsched:
+            autotune.set_schedule("detect", w.U, 0, autotune.variants("detect").index(name), bpc)
+            o = api().detect_cg(H, Y, f.n0, f.es, w.K, w.m, "approx", sc, xhat=True)
+            dets.append((host(o["llr"]), host(o["xhat"])))
+        for name, bpc in psched:
+            autotune.set_schedule("precode", w.U, 0, autotune.variants("precode").index(name), bpc)
+            q, qn = api().precode_cg(H, T, d.beta, w.K, True, sc)
+            pres.append((host(q), host(qn)))
+    finally:
+        for op, (v, b) in zip(("detect", "precode"), saved):
+            autotune.set_schedule(op, w.U, 0, v, b)
+    for o in dets[1:]:
+        assert np.array_equal(o[0], dets[0][0]) and np.array_equal(o[1], dets[0][1])
+    for o in pres[1:]:
+        assert np.array_equal(o[0], pres[0][0]) and np.array_equal(o[1], pres[0][1])
+    n = f.H.shape[0]
+    idx = np.sort(np.random.default_rng(2).choice(n, min(24, n), replace=False))
+    idx[-1] = n - 1
+    ref = O.detect_cg(f.H[idx], f.Y[idx], f.n0, f.es, w.K, w.m, "approx")
+    ex = rel_err_vec(dets[0][1][idx], ref["xhat"], axis=1)
+    el = llr_err(dets[0][0][idx], ref["llr"])
+    rp = O.precode_cg(f.H[idx], d.T[idx], d.beta, w.K, True)
+    eq = rel_err_vec(pres[0][0][idx], rp["Q"], axis=1)
+    en = rel_err_scalar(pres[0][1][idx], rp["qnorm"])
+    print(f"{wl} x{frames}: eps_x={ex:.2e} eps_L={el:.2e} eps_q={eq:.2e} eps_qnorm={en:.2e}")
+    assert ex <= TOL_X and el <= TOL_L and eq <= TOL_X and en <= TOL_X
+    assert np.all(np.isfinite(dets[0][0])) and np.all(np.isfinite(pres[0][0]))
+
+
 @pytest.mark.parametrize("case", [DETECT_CASES[4], DETECT_CASES[5], DETECT_CASES[7],
                                   ("ragged_100x12_S9", 29, 100, 12, 9, 4, 4, 10.0, "iid")],
                          ids=["mixed_128x16", "mixed_128x32", "ragged_30x5_S17", "ragged_100x12_S9"])
