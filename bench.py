@@ -616,7 +616,7 @@ def comparison_leg(api, autotune, H, Y, T, llr, Q, up, dn, wl, n, kernel_time):
 
 def serving_leg(n_frames, skip):
     """Mixed-shape uplink/downlink frames through the continuous-batching
-    server: saturation throughput (all frames arrive at once), then Poisson
+    server: saturation throughput (all frames queued, then released at once), then Poisson
     arrivals at 50%, 80% and 95% of it, and 80% under a small HBM budget that
     makes requests wait for memory; p50/p99 arrival-to-completion latency
     over all but the first ``skip`` frames of each run."""
@@ -655,6 +655,9 @@ def serving_leg(n_frames, skip):
         # warm up every shape class once
         for f in {(by_id[f.ch_id].B, by_id[f.ch_id].U, f.uplink, f.m): f for f in frames}.values():
             srv.submit(request(f)).result(timeout=60)
+        srv.drain(timeout=60)
+        if rate <= 0:
+            srv.pause()          # saturation: queue every frame, then release them at once
         srv.stats(reset=True)
         t0 = time.perf_counter()
         for f, r in zip(frames, reqs):
@@ -665,6 +668,7 @@ def serving_leg(n_frames, skip):
                     break
                 time.sleep(d - 1e-4 if d > 2e-4 else 0)
             srv.submit(r)
+        srv.resume()
         srv.drain(timeout=120)
         st = srv.stats(skip=min(skip, len(frames) // 2))
         st["mean_batch"] = float(np.mean(srv.batch_sizes[-len(frames):])) if srv.batch_sizes else 0

@@ -85,7 +85,8 @@ class Server:
     ``hbm_budget`` bytes (channel cache included)."""
 
     def __init__(self, executor, hbm_budget: int = 16 << 30, n_slots: int = 4,
-                 poll_interval: float = 20e-6, max_batch: int = 32, lookahead: int = 128):
+                 poll_interval: float = 20e-6, max_batch: int = 32, lookahead: int = 128,
+                 start_paused: bool = False):
         self.ex = executor
         self.max_batch = max_batch
         self.lookahead = lookahead
@@ -102,6 +103,8 @@ class Server:
         self._channels: dict = {}          # ch_id -> bytes
         self._done: list[Result] = []
         self._running = True
+        self._paused = bool(start_paused)  # queue requests without admitting them
+        self._t_resume = None              # when a paused server was released
         self._t_first = None
         self.peak_bytes = 0                # largest reserved + cached bytes seen
         self.budget_waits = 0              # queue heads that waited for HBM budget
@@ -157,6 +160,22 @@ class Server:
             self._lock.notify_all()
         return fut
 
+    def pause(self) -> None:
+        """Stop admitting new requests (those in flight complete); submissions
+        queue until :meth:`resume`."""
+        with self._lock:
+            self._paused = True
+            self._t_resume = None
+
+    def resume(self) -> None:
+        """Start admitting (a server created with start_paused=True queues
+        submissions until then, so a backlog can be released at once)."""
+        with self._lock:
+            if self._paused:
+                self._paused = False
+                self._t_resume = self.ex.now()
+                self._lock.notify_all()
+
     def drain(self, timeout: float | None = None) -> None:
         """Wait until every submitted request has completed."""
         deadline = None if timeout is None else time.perf_counter() + timeout
@@ -177,17 +196,21 @@ class Server:
     # ------------------------------------------------------------ stats
     def stats(self, reset: bool = False, skip: int = 0) -> dict:
         """Latency and throughput of the completed requests; ``skip`` leaves
-        out the first requests by submission time (a warm-up)."""
+        out the first requests by submission time (a warm-up).  For a server
+        started paused, time counts from its release (requests submitted
+        before it arrive then)."""
         with self._lock:
             done = list(self._done)
+            t_rel = self._t_resume
             if reset:
                 self._done.clear()
                 self._t_first = None
         done = sorted(done, key=lambda r: r.t_submit)[skip:]
         if not done:
             return {"frames": 0}
-        lat = np.array([r.latency for r in done])
-        t0 = min(r.t_submit for r in done)
+        arrive = (lambda r: r.t_submit) if t_rel is None else (lambda r: max(r.t_submit, t_rel))
+        lat = np.array([r.t_done - arrive(r) for r in done])
+        t0 = min(arrive(r) for r in done)
         t1 = max(r.t_done for r in done)
         span = max(t1 - t0, 1e-12)
         return {"frames": len(done),
@@ -204,6 +227,9 @@ class Server:
             with self._lock:
                 if not self._running:
                     return
+                if self._paused:
+                    self._lock.wait(timeout=0.01)
+                    continue
                 self._admit_locked()
                 busy = bool(self._inflight)
                 if not busy and not self._queue:
