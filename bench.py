@@ -627,7 +627,7 @@ def serving_leg(n_frames, skip):
 
     rng = W.rng_for(4, 0)
     chans, _ = W.serving_stream(rng, 16, 0, 0.0)
-    ex = SV.GpuExecutor(n_slots=4)
+    ex = SV.GpuExecutor(n_slots=4, input_events=False)    # inputs synchronized below
     dev = torch.device("cuda")
     data = {}
     for ch in chans:

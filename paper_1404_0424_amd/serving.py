@@ -307,9 +307,13 @@ class Server:
 
 class GpuExecutor:
     """Device work for :class:`Server` through the C ABI, one HIP stream per
-    slot (all at default priority)."""
+    slot (all at default priority).  With ``input_events`` (default) each
+    submission records an event on the caller's current stream that the slot
+    stream waits for, so inputs written there just before submitting are
+    complete; a caller whose inputs are already synchronized can turn it off
+    and save that per-request cost."""
 
-    def __init__(self, n_slots: int = 4, device: int = 0):
+    def __init__(self, n_slots: int = 4, device: int = 0, input_events: bool = True):
         import torch
 
         from . import api
@@ -317,6 +321,7 @@ class GpuExecutor:
         self.api = api
         self.dev = torch.device("cuda", device)
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(n_slots)]
+        self.input_events = input_events
         self.channels: dict = {}
         # host/device clock alignment: a reference event whose host time is
         # bracketed as tightly as possible (best of several round trips)
@@ -381,6 +386,8 @@ class GpuExecutor:
     def on_submit(self, req):
         """Called at submission: device inputs written on the caller's stream
         must be complete before the slot stream reads them."""
+        if not self.input_events:
+            return None
         ev = self.torch.cuda.Event()
         ev.record()
         return ev
