@@ -5,6 +5,7 @@
 // and matched filter on MFMA as in CG-D, the explicit (approximate) inverse
 // X of A in LDS, then xhat = X b on MFMA with the soft output of the linear
 // detector W = X H^H (eqs. (2)-(4)), or v = X t and q = H_u v (eq. (5)).
+#include "gram_stream.hpp"
 #include "inverse.hpp"
 #include "launch.hpp"
 #include "llr.hpp"
@@ -49,9 +50,71 @@ __device__ __forceinline__ void apply_inverse(InverseLds<W>& sm, const float2 (&
   wave_lds_sync();
 }
 
+// After the Gram phase of chunk s0 (acc: Gram tiles on the first chunk, the
+// matched filter b of rhs s0 .. s0 + 15): on the first chunk build X and the
+// per-user gain and SINR, then xhat = X b and the LLRs of the chunk.
+template <int W, int M_BITS, int METHOD>
+__device__ __forceinline__ void detect_inverse_chunk(const DetectParams& prm, InverseLds<W>& sm,
+                                                     int64_t n, int s0, const GramAcc<W>& acc,
+                                                     int lane, int c, int g) {
+  constexpr int AST = InverseLds<W>::AST;
+  const int U = prm.U, S = prm.S;
+  if (s0 == 0) {
+    store_gram_lds<W>(acc, sm.A, sm.G, (float*)sm.P, AST, prm.reg, c, g);
+    wave_lds_sync();
+    build_inverse<W, METHOD>(sm, U, prm.K, lane, c, g);
+    if (METHOD == kInvCholesky) {
+      // unbiased MMSE: mu_i = (A^{-1} G)_ii = 1 - (N0/E_s)(A^{-1})_ii and
+      // rho_i = mu_i^2 / nu_i^2 = mu_i / (N0 (A^{-1})_ii)
+      if (lane < U) {
+        const float d = sm.Dinv[lane];
+        const float mu = 1.f - prm.reg * d;
+        sm.MU[lane] = mu;
+        sm.RHO[lane] = mu / (prm.n0 * d);
+      }
+    } else {
+      linear_sinr<W>(sm.A, sm.G, sm.X, AST, prm.es, prm.n0, c, g, sm.MU, sm.RHO);
+    }
+    wave_lds_sync();
+  }
+  float2 b[W][4], x[W][4];
+#pragma unroll
+  for (int w = 0; w < W; ++w)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[w][j] = make_float2(acc.dr[w][j], acc.di[w][j]);
+  apply_inverse<W>(sm, b, c, g, x);                      // xhat = X H^H y
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const int u = 16 * w + c;
+    const int uu = u < U ? u : 0;
+    const float mu = sm.MU[uu];
+    // mu = 0 (a zero channel column): z = 0 and rho = G_ii / N0
+    const bool live = fabsf(mu) >= __FLT_MIN__;
+    const float rho = live ? sm.RHO[uu] : sm.G[uu] / prm.n0;
+    const float imu = live ? __builtin_amdgcn_rcpf(mu) : 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int s = s0 + 4 * g + j;
+      const float2 xx = x[w][j];
+      float out[M_BITS];
+      llr_maxlog<M_BITS>(make_float2(xx.x * imu, xx.y * imu), rho, prm.scale, prm.inv_scale,
+                         out);
+      if (u < U && s < S) {
+        const size_t idx = ((size_t)n * U + u) * S + s;
+        float* lp = prm.llr + idx * M_BITS;
+#pragma unroll
+        for (int q = 0; q < M_BITS; ++q) lp[q] = out[q];
+        if (prm.xhat) prm.xhat[idx] = xx;
+        if (prm.mu) prm.mu[idx] = mu;
+        if (prm.sinr) prm.sinr[idx] = rho;
+      }
+    }
+  }
+}
+
+// Generic form (any S): one subcarrier per block in turn, rhs in chunks of 16.
 template <int W, typename IN, int M_BITS, int METHOD>
 __global__ __launch_bounds__(64) void detect_inverse_kernel(DetectParams prm) {
-  constexpr int AST = InverseLds<W>::AST;
   __shared__ InverseLds<W> sm;
   const int lane = threadIdx.x;
   const int c = lane & 15, g = lane >> 4;
@@ -62,67 +125,81 @@ __global__ __launch_bounds__(64) void detect_inverse_kernel(DetectParams prm) {
     for (int s0 = 0; s0 < S; s0 += 16) {
       GramAcc<W> acc;
       acc.clear();
-      if (s0 == 0) {
+      if (s0 == 0)
         gram_mf<W, true, true>(IN{}, Hn, Yn, B, U, S, 0, c, g, acc);
-        store_gram_lds<W>(acc, sm.A, sm.G, (float*)sm.P, AST, prm.reg, c, g);
-        wave_lds_sync();
-        build_inverse<W, METHOD>(sm, U, prm.K, lane, c, g);
-        if (METHOD == kInvCholesky) {
-          // unbiased MMSE: mu_i = (A^{-1} G)_ii = 1 - (N0/E_s)(A^{-1})_ii and
-          // rho_i = mu_i^2 / nu_i^2 = mu_i / (N0 (A^{-1})_ii)
-          if (lane < U) {
-            const float d = sm.Dinv[lane];
-            const float mu = 1.f - prm.reg * d;
-            sm.MU[lane] = mu;
-            sm.RHO[lane] = mu / (prm.n0 * d);
-          }
-        } else {
-          linear_sinr<W>(sm.A, sm.G, sm.X, AST, prm.es, prm.n0, c, g, sm.MU, sm.RHO);
-        }
-        wave_lds_sync();
-      } else {
+      else
         gram_mf<W, false, true>(IN{}, Hn, Yn, B, U, S, s0, c, g, acc);
-      }
-      float2 b[W][4], x[W][4];
-#pragma unroll
-      for (int w = 0; w < W; ++w)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) b[w][j] = make_float2(acc.dr[w][j], acc.di[w][j]);
-      apply_inverse<W>(sm, b, c, g, x);                      // xhat = X H^H y
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        const int u = 16 * w + c;
-        const int uu = u < U ? u : 0;
-        const float mu = sm.MU[uu];
-        // mu = 0 (a zero channel column): z = 0 and rho = G_ii / N0
-        const bool live = fabsf(mu) >= __FLT_MIN__;
-        const float rho = live ? sm.RHO[uu] : sm.G[uu] / prm.n0;
-        const float imu = live ? __builtin_amdgcn_rcpf(mu) : 0.f;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int s = s0 + 4 * g + j;
-          const float2 xx = x[w][j];
-          float out[M_BITS];
-          llr_maxlog<M_BITS>(make_float2(xx.x * imu, xx.y * imu), rho, prm.scale, prm.inv_scale,
-                             out);
-          if (u < U && s < S) {
-            const size_t idx = ((size_t)n * U + u) * S + s;
-            float* lp = prm.llr + idx * M_BITS;
-#pragma unroll
-            for (int q = 0; q < M_BITS; ++q) lp[q] = out[q];
-            if (prm.xhat) prm.xhat[idx] = xx;
-            if (prm.mu) prm.mu[idx] = mu;
-            if (prm.sinr) prm.sinr[idx] = rho;
-          }
-        }
-      }
+      detect_inverse_chunk<W, M_BITS, METHOD>(prm, sm, n, s0, acc, lane, c, g);
     }
   }
 }
 
+// Streaming form for S <= 16: a persistent grid in which each wavefront
+// walks several subcarriers with the Gram's loads streamed (gram_stream).
+// Same arithmetic in the same order as detect_inverse_kernel.
+template <int W, typename IN, int M_BITS, int METHOD>
+__global__ __launch_bounds__(64, W == 2 ? 1 : (METHOD == kInvCholesky ? 4 : 3)) void detect_inverse_stream_kernel(DetectParams prm) {
+  using Sub = typename Storage<IN, W>::Sub;
+  using Blk = typename Storage<IN, W>::SmallBlock;
+  __shared__ InverseLds<W> sm;
+  const int lane = threadIdx.x;
+  const int c = lane & 15, g = lane >> 4;
+  const int B = prm.B, U = prm.U, S = prm.S;
+  int64_t n = blockIdx.x;
+  Sub cur;
+  Blk blk;
+  if (n < prm.n_sc) {
+    cur.init(offset_sc(IN{}, prm.H, n, B, U), offset_sc(IN{}, prm.Y, n, B, S), B, U, S, 0, c, g);
+    blk.template load<true>(cur, 0);
+  }
+  while (n < prm.n_sc) {
+    const int64_t nn = n + gridDim.x;
+    const int64_t nc = nn < prm.n_sc ? nn : n;
+    Sub nxt;
+    nxt.init(offset_sc(IN{}, prm.H, nc, B, U), offset_sc(IN{}, prm.Y, nc, B, S), B, U, S, 0, c, g);
+    if (nn >= prm.n_sc) nxt.disable();
+    GramAcc<W> acc;
+    acc.clear();
+    gram_stream<W, true>(IN{}, blk, cur, nxt, B, acc);
+    detect_inverse_chunk<W, M_BITS, METHOD>(prm, sm, n, 0, acc, lane, c, g);
+    n = nn;
+    cur = nxt;
+  }
+}
+
+// Precoding after the Gram phase: X on the first chunk, then v = X t and the
+// shared output stage for rhs s0 .. s0 + 15.
+template <int W, typename IN, int METHOD>
+__device__ __forceinline__ void precode_inverse_chunk(const PrecodeParams& prm,
+                                                      InverseLds<W>& sm, int64_t n, int s0,
+                                                      const GramAcc<W>* acc, AOperand<W>& at,
+                                                      int lane, int c, int g) {
+  constexpr int AST = InverseLds<W>::AST;
+  const int B = prm.B, U = prm.U, S = prm.S;
+  if (s0 == 0) {
+    store_gram_lds<W>(*acc, sm.A, sm.G, (float*)sm.P, AST, prm.beta, c, g);
+    wave_lds_sync();
+    build_inverse<W, METHOD>(sm, U, prm.K, lane, c, g);
+    // A operand for ||q||^2 = v^H A v - beta ||v||^2 (the padding
+    // diagonal differs from A's but meets only zero entries of v)
+    at.load(sm.A, AST, c, g);
+  }
+  float2 t[W][4], v[W][4];
+#pragma unroll
+  for (int w = 0; w < W; ++w)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int u = 16 * w + c, s = s0 + 4 * g + j;
+      t[w][j] = (u < U && s < S) ? prm.T[((size_t)n * U + u) * S + s] : make_float2(0.f, 0.f);
+    }
+  apply_inverse<W>(sm, t, c, g, v);                      // v = X t
+  precode_store<W, IN, float>(prm, n, s0, offset_sc(IN{}, prm.H, n, B, U), v, at, sm.P, sm.N,
+                              c, g);
+  wave_lds_sync();
+}
+
 template <int W, typename IN, int METHOD>
 __global__ __launch_bounds__(64) void precode_inverse_kernel(PrecodeParams prm) {
-  constexpr int AST = InverseLds<W>::AST;
   __shared__ InverseLds<W> sm;
   const int lane = threadIdx.x;
   const int c = lane & 15, g = lane >> 4;
@@ -131,29 +208,45 @@ __global__ __launch_bounds__(64) void precode_inverse_kernel(PrecodeParams prm) 
     const void* Hn = offset_sc(IN{}, prm.H, n, B, U);
     AOperand<W> at;
     for (int s0 = 0; s0 < S; s0 += 16) {
+      GramAcc<W> acc;
       if (s0 == 0) {
-        GramAcc<W> acc;
         acc.clear();
         gram_mf<W, true, false>(IN{}, Hn, nullptr, B, U, S, 0, c, g, acc);
-        store_gram_lds<W>(acc, sm.A, sm.G, (float*)sm.P, AST, prm.beta, c, g);
-        wave_lds_sync();
-        build_inverse<W, METHOD>(sm, U, prm.K, lane, c, g);
-        // A operand for ||q||^2 = v^H A v - beta ||v||^2 (the padding
-        // diagonal differs from A's but meets only zero entries of v)
-        at.load(sm.A, AST, c, g);
       }
-      float2 t[W][4], v[W][4];
-#pragma unroll
-      for (int w = 0; w < W; ++w)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int u = 16 * w + c, s = s0 + 4 * g + j;
-          t[w][j] = (u < U && s < S) ? prm.T[((size_t)n * U + u) * S + s] : make_float2(0.f, 0.f);
-        }
-      apply_inverse<W>(sm, t, c, g, v);                      // v = X t
-      precode_store<W, IN, float>(prm, n, s0, Hn, v, at, sm.P, sm.N, c, g);
-      wave_lds_sync();
+      precode_inverse_chunk<W, IN, METHOD>(prm, sm, n, s0, &acc, at, lane, c, g);
     }
+  }
+}
+
+// Streaming form for S <= 16 (see detect_inverse_stream_kernel).
+template <int W, typename IN, int METHOD>
+__global__ __launch_bounds__(64, W == 1 ? 4 : 1) void precode_inverse_stream_kernel(PrecodeParams prm) {
+  using Sub = typename Storage<IN, W>::Sub;
+  using Blk = typename Storage<IN, W>::SmallBlock;
+  __shared__ InverseLds<W> sm;
+  const int lane = threadIdx.x;
+  const int c = lane & 15, g = lane >> 4;
+  const int B = prm.B, U = prm.U, S = prm.S;
+  int64_t n = blockIdx.x;
+  Sub cur;
+  Blk blk;
+  if (n < prm.n_sc) {
+    cur.init(offset_sc(IN{}, prm.H, n, B, U), nullptr, B, U, S, 0, c, g);
+    blk.template load<false>(cur, 0);
+  }
+  while (n < prm.n_sc) {
+    const int64_t nn = n + gridDim.x;
+    const int64_t nc = nn < prm.n_sc ? nn : n;
+    Sub nxt;
+    nxt.init(offset_sc(IN{}, prm.H, nc, B, U), nullptr, B, U, S, 0, c, g);
+    if (nn >= prm.n_sc) nxt.disable();
+    GramAcc<W> acc;
+    acc.clear();
+    gram_stream<W, false>(IN{}, blk, cur, nxt, B, acc);
+    AOperand<W> at;
+    precode_inverse_chunk<W, IN, METHOD>(prm, sm, n, 0, &acc, at, lane, c, g);
+    n = nn;
+    cur = nxt;
   }
 }
 
@@ -162,14 +255,34 @@ static dim3 sc_grid(int64_t n_sc) {
   return dim3((unsigned)(blocks < 1 ? 1 : blocks));
 }
 
+// Persistent grid of the streaming forms: as many one-wave blocks per CU as
+// the LDS allows, up to 16.
+template <int W>
+static dim3 stream_grid(int64_t n_sc) {
+  constexpr int64_t kLdsPerCu = 160 * 1024;
+  constexpr int64_t fit = kLdsPerCu / (int64_t)sizeof(InverseLds<W>);
+  const int64_t cap = (int64_t)num_compute_units() * (fit < 16 ? fit : 16);
+  const int64_t blocks = n_sc < cap ? n_sc : cap;
+  return dim3((unsigned)(blocks < 1 ? 1 : blocks));
+}
+
+template <int W, typename IN, int M, int METHOD>
+static void launch_detect_form(const DetectParams& p, hipStream_t stream) {
+  if (p.S <= 16)
+    hipLaunchKernelGGL((detect_inverse_stream_kernel<W, IN, M, METHOD>), stream_grid<W>(p.n_sc),
+                       dim3(kWave), 0, stream, p);
+  else
+    hipLaunchKernelGGL((detect_inverse_kernel<W, IN, M, METHOD>), sc_grid(p.n_sc), dim3(kWave),
+                       0, stream, p);
+}
+
 template <int W, typename IN, int METHOD>
 static hipError_t launch_detect_m(const DetectParams& p, int m_bits, hipStream_t stream) {
-  const dim3 grid = sc_grid(p.n_sc), block(kWave);
   switch (m_bits) {
-    case 2: hipLaunchKernelGGL((detect_inverse_kernel<W, IN, 2, METHOD>), grid, block, 0, stream, p); break;
-    case 4: hipLaunchKernelGGL((detect_inverse_kernel<W, IN, 4, METHOD>), grid, block, 0, stream, p); break;
-    case 6: hipLaunchKernelGGL((detect_inverse_kernel<W, IN, 6, METHOD>), grid, block, 0, stream, p); break;
-    case 8: hipLaunchKernelGGL((detect_inverse_kernel<W, IN, 8, METHOD>), grid, block, 0, stream, p); break;
+    case 2: launch_detect_form<W, IN, 2, METHOD>(p, stream); break;
+    case 4: launch_detect_form<W, IN, 4, METHOD>(p, stream); break;
+    case 6: launch_detect_form<W, IN, 6, METHOD>(p, stream); break;
+    case 8: launch_detect_form<W, IN, 8, METHOD>(p, stream); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -186,13 +299,22 @@ static hipError_t launch_detect_in(const DetectParams& p, int in_dtype, int m_bi
   return hipErrorInvalidValue;
 }
 
+template <int W, typename IN, int METHOD>
+static void launch_precode_form(const PrecodeParams& p, hipStream_t stream) {
+  if (p.S <= 16)
+    hipLaunchKernelGGL((precode_inverse_stream_kernel<W, IN, METHOD>), stream_grid<W>(p.n_sc),
+                       dim3(kWave), 0, stream, p);
+  else
+    hipLaunchKernelGGL((precode_inverse_kernel<W, IN, METHOD>), sc_grid(p.n_sc), dim3(kWave), 0,
+                       stream, p);
+}
+
 template <int W, int METHOD>
 static hipError_t launch_precode_in(const PrecodeParams& p, int in_dtype, hipStream_t stream) {
-  const dim3 grid = sc_grid(p.n_sc), block(kWave);
   switch (in_dtype) {
-    case 0: hipLaunchKernelGGL((precode_inverse_kernel<W, InC32, METHOD>), grid, block, 0, stream, p); break;
-    case 1: hipLaunchKernelGGL((precode_inverse_kernel<W, InF16, METHOD>), grid, block, 0, stream, p); break;
-    case 2: hipLaunchKernelGGL((precode_inverse_kernel<W, InBF16, METHOD>), grid, block, 0, stream, p); break;
+    case 0: launch_precode_form<W, InC32, METHOD>(p, stream); break;
+    case 1: launch_precode_form<W, InF16, METHOD>(p, stream); break;
+    case 2: launch_precode_form<W, InBF16, METHOD>(p, stream); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
