@@ -39,11 +39,18 @@ struct Tracker {
   }
 };
 
-// A^T operand of the mat-vec: a[wc][t] = A[16 wc + c][4 t + g].
+// A^T operand of the mat-vec: a[wc][t] = A[16 wc + c][4 t + g].  nk = the
+// k-steps (4 users each) that reach a real user, ceil(U / 4): the vectors the
+// CG multiplies are zero on padding users (b is zero there and A keeps them
+// decoupled), so later k-steps would add exact zeros and are skipped.  A
+// caller whose vectors are not zero on padding users passes U = 16 W.
 template <int W>
 struct AOperand {
   float2 a[W][4 * W];
-  __device__ void load(const float2* __restrict__ As, int ast, int c, int g) {
+  int nk;
+  __device__ void load(const float2* __restrict__ As, int ast, int c, int g, int U) {
+    const int k = (U + 3) >> 2;
+    nk = __builtin_amdgcn_readfirstlane(k < 4 * W ? k : 4 * W);
 #pragma unroll
     for (int wc = 0; wc < W; ++wc)
 #pragma unroll
@@ -120,6 +127,7 @@ __device__ __forceinline__ void matvec_mfma(const AOperand<W>& at, const float2*
   for (int w = 0; w < W; ++w) { er[w] = zero4(); ei[w] = zero4(); }
 #pragma unroll
   for (int t = 0; t < 4 * W; ++t) {
+    if (t >= at.nk) break;                            // users >= 4 t are padding
     const float2 pk = Ps[(4 * t + g) * kPST + c];     // X[k = 4 t + g][rhs c]
 #pragma unroll
     for (int w = 0; w < W; ++w) {

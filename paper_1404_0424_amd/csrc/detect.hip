@@ -116,11 +116,11 @@ __device__ __forceinline__ void cg_llr_epilogue(const DetectParams& prm, int64_t
 // Gram tiles -> LDS A, A^T operand and diagonal d = A_ii.
 template <int W>
 __device__ __forceinline__ void gram_to_operands(const GramAcc<W>& acc, float2* As, float* Gs,
-                                                 float2* Ps, int ast, float reg, int c, int g,
-                                                 AOperand<W>& at, float (&d)[W]) {
+                                                 float2* Ps, int ast, float reg, int U, int c,
+                                                 int g, AOperand<W>& at, float (&d)[W]) {
   store_gram_lds<W>(acc, As, Gs, (float*)Ps, ast, reg, c, g);
   wave_lds_sync();
-  at.load(As, ast, c, g);
+  at.load(As, ast, c, g, U);
 #pragma unroll
   for (int w = 0; w < W; ++w) d[w] = As[(16 * w + c) * ast + 16 * w + c].x;
 }
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(256, 2) void detect_stream_kernel(DetectParams prm)
     finish_mf(IN{}, acc);
     AOperand<W> at;
     float d[W];
-    gram_to_operands<W>(acc, As, Gs, Ps, AST, prm.reg, c, g, at, d);
+    gram_to_operands<W>(acc, As, Gs, Ps, AST, prm.reg, U, c, g, at, d);
     cg_llr_epilogue<W, ST, M_BITS, kUncondMem<IN>>(prm, n, 0, acc, at, d, Gs, Ps, c, g);
     n = nn;
     cur = nxt;
@@ -220,7 +220,7 @@ __device__ __forceinline__ void detect_one(const DetectParams& prm, int64_t n, f
     acc.clear();
     if (s0 == 0) {
       gram_mf<W, true, true>(IN{}, Hn, Yn, B, U, S, s0, c, g, acc);
-      gram_to_operands<W>(acc, As, Gs, Ps, AST, prm.reg, c, g, at, d);
+      gram_to_operands<W>(acc, As, Gs, Ps, AST, prm.reg, U, c, g, at, d);
     } else {
       gram_mf<W, false, true>(IN{}, Hn, Yn, B, U, S, s0, c, g, acc);
     }

@@ -45,7 +45,7 @@ __device__ __forceinline__ void apply_inverse(InverseLds<W>& sm, const float2 (&
   stage_vec<W>(sm.P, c, g, x);
   wave_lds_sync();
   AOperand<W> xo;
-  xo.load(sm.X, InverseLds<W>::AST, c, g);
+  xo.load(sm.X, InverseLds<W>::AST, c, g, 16 * W);
   matvec_mfma<W>(xo, sm.P, c, g, e);
   wave_lds_sync();
 }
@@ -182,7 +182,7 @@ __device__ __forceinline__ void precode_inverse_chunk(const PrecodeParams& prm,
     build_inverse<W, METHOD>(sm, U, prm.K, lane, c, g);
     // A operand for ||q||^2 = v^H A v - beta ||v||^2 (the padding
     // diagonal differs from A's but meets only zero entries of v)
-    at.load(sm.A, AST, c, g);
+    at.load(sm.A, AST, c, g, 16 * W);
   }
   float2 t[W][4], v[W][4];
 #pragma unroll

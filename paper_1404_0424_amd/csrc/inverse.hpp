@@ -163,7 +163,7 @@ __device__ __forceinline__ void neumann_series(const float2* As, float2* Xs, int
                                                int lane, int c, int g) {
   constexpr int NU = 16 * W;
   AOperand<W> e;                       // e.a[wr][kt] = A(16 wr + c, 4 kt + g)
-  e.load(As, ast, c, g);
+  e.load(As, ast, c, g, 16 * W);
 #pragma unroll
   for (int wr = 0; wr < W; ++wr)
 #pragma unroll

@@ -31,7 +31,7 @@ __device__ __forceinline__ void precode_one(const PrecodeParams& prm, int64_t n,
       gram_mf<W, true, false>(IN{}, Hn, nullptr, B, U, S, 0, c, g, acc);
       store_gram_lds<W>(acc, As, Gs, (float*)Ps, AST, beta, c, g);
       wave_lds_sync();
-      at.load(As, AST, c, g);
+      at.load(As, AST, c, g, U);
     }
     // b = t
     float2 b[W][4];
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256, 2) void precode_stream_kernel(PrecodeParams pr
     store_gram_lds<W>(acc, As, Gs, (float*)Ps, AST, prm.beta, c, g);
     wave_lds_sync();
     AOperand<W> at;
-    at.load(As, AST, c, g);
+    at.load(As, AST, c, g, U);
     float2 b[W][4];                                   // b = t
 #pragma unroll
     for (int w = 0; w < W; ++w)
@@ -265,7 +265,7 @@ __global__ __launch_bounds__(256, resident_min_blocks<ST>()) void precode_reside
     store_gram_lds<1>(acc, As, Gs, (float*)Ps, AST, prm.beta, c, g);
     wave_lds_sync();
     AOperand<1> at;
-    at.load(As, AST, c, g);
+    at.load(As, AST, c, g, U);
     CGState<1, ST> st;
     cg_init<1, ST>(st, b);
     for (int k = 0; k < prm.K; ++k) {
