@@ -24,7 +24,7 @@
 namespace mimo {
 
 // H v for the 16 antennas b0 .. b0 + 15 (element j: antenna b0 + 4 g + j,
-// rhs c); vv / vs are the staged v[16 w + 4 g + t][c] and Re + Im of it.
+// rhs c); vv / vs are the staged v[16 w + 4 t + g][c] and Re + Im of it.
 template <int W, typename IN>
 __device__ __forceinline__ void h_times(IN tag, const void* Hn, int B, int U, int b0, int c,
                                         int g, const float2 (&vv)[W][4], const float (&vs)[W][4],
@@ -82,7 +82,7 @@ __device__ __forceinline__ void load_staged(const float2* Ps, int c, int g, floa
   for (int w = 0; w < W; ++w)
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      vv[w][t] = Ps[(16 * w + 4 * g + t) * kPST + c];
+      vv[w][t] = Ps[(16 * w + 4 * t + g) * kPST + c];
       vs[w][t] = vv[w][t].x + vv[w][t].y;
     }
 }

@@ -162,7 +162,7 @@ __global__ __launch_bounds__(256, 2) void precode_stream_kernel(PrecodeParams pr
 // The registers hold the Gram's k-steps (complex64: lane (c, g) holds
 // H[4 t + g][c] for k-step t; 16-bit: Re and Im of the eight antennas of
 // block 4 t + g for user c), but the output contraction needs H[16 i + c]
-// [4 g + t] in FP32, so each 16-antenna tile passes through the wave's LDS;
+// [4 t + g] in FP32, so each 16-antenna tile passes through the wave's LDS;
 // the registers a k-step leaves receive the same k-step of the wave's next
 // subcarrier, which is then in flight during the rest of the output stage.
 // Two LDS tile buffers alternate, so tile i + 1 is staged while tile i's
@@ -185,12 +185,16 @@ struct ResidentBlock<InBF16> {
 };
 
 // Output tile i (antennas 16 i .. 16 i + 15) of the resident channel to LDS
-// as Hs[antenna][user] in FP32 (row stride kPST).
+// as Hs[antenna][slot] in FP32 (row stride kPST), user u in slot
+// 4 (u % 4) + u / 4: the contraction's k-step t takes users 4 t + g, which
+// then sit in the four adjacent slots 4 g .. 4 g + 3 of a row.
+__device__ __forceinline__ int user_slot(int u) { return ((u & 3) << 2) | (u >> 2); }
 template <int NK>
 __device__ __forceinline__ void stage_h_tile(const BlockC32<1, 1> (&hb)[NK], int i,
                                              float2* __restrict__ Hs, int c, int g) {
+  const int sl = user_slot(c);
 #pragma unroll
-  for (int t = 0; t < 4; ++t) Hs[(4 * t + g) * kPST + c] = hb[4 * i + t].h[0][0];
+  for (int t = 0; t < 4; ++t) Hs[(4 * t + g) * kPST + sl] = hb[4 * i + t].h[0][0];
 }
 template <int NK, typename V8>
 __device__ __forceinline__ void stage_h_tile(const Block16<1, V8, 1> (&hb)[NK], int i,
@@ -198,9 +202,10 @@ __device__ __forceinline__ void stage_h_tile(const Block16<1, V8, 1> (&hb)[NK], 
   // k-step i / 2 holds blocks 4 (i / 2) + g; tile i is blocks 2 i and 2 i + 1
   if ((g >> 1) == (i & 1)) {
     const V8 re = hb[i >> 1].hr[0][0], im = hb[i >> 1].hi[0][0];
+    const int sl = user_slot(c);
 #pragma unroll
     for (int e = 0; e < 8; ++e)
-      Hs[(8 * (g & 1) + e) * kPST + c] = make_float2((float)re[e], (float)im[e]);
+      Hs[(8 * (g & 1) + e) * kPST + sl] = make_float2((float)re[e], (float)im[e]);
   }
 }
 
@@ -300,7 +305,7 @@ __global__ __launch_bounds__(256, resident_min_blocks<ST>()) void precode_reside
     float vs[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      vv[t] = Ps[(4 * g + t) * kPST + c];
+      vv[t] = Ps[(4 * t + g) * kPST + c];
       vs[t] = vv[t].x + vv[t].y;
     }
     const __amdgpu_buffer_rsrc_t rq = make_rsrc(prm.Q + (size_t)n * B * S, (uint32_t)B * S * 8u);
@@ -322,11 +327,12 @@ __global__ __launch_bounds__(256, resident_min_blocks<ST>()) void precode_reside
         wave_lds_sync();
         float2 hv[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) hv[t] = cur_t[c * kPST + 4 * g + t];
+        for (int t = 0; t < 4; ++t) hv[t] = cur_t[c * kPST + 4 * g + t];   // user 4 t + g
         if (i + 1 < BMAX / 16 && 16 * (i + 1) < B) stage_h_tile(hb, i + 1, nxt_t, c, g);
         f4 p1 = zero4(), p2 = zero4(), p3 = zero4();
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
+          if (4 * t >= U) break;                      // users past U: v is zero
           p1 = mfma4(hv[t].x, vv[t].x, p1);
           p2 = mfma4(hv[t].y, vv[t].y, p2);
           p3 = mfma4(hv[t].x + hv[t].y, vs[t], p3);

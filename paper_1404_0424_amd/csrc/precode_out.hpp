@@ -27,15 +27,16 @@ __device__ __forceinline__ float2 load_h(InBF16, const void* Hn, int b, int u, i
   return make_float2(bf16_to_f32(p[0]), bf16_to_f32(p[(size_t)U * 8]));
 }
 
-// A-operand rows of the output contraction: H[b][u] for u = 16 w + 4 g + t.
-// Row b0 + c of H (users 16 w + 4 g + t); rows past B read zero.
+// A-operand rows of the output contraction: H[b][u] for u = 16 w + 4 t + g
+// (k-step t covers users 16 w + 4 t .. 16 w + 4 t + 3, so k-steps past the
+// last user can be skipped).  Row b0 + c of H; rows past B read zero.
 template <int W>
 __device__ __forceinline__ void load_h_row(InC32, const void* Hn, int B, int U, int b0, int c,
                                            int w, int g, float2 (&hv)[4]) {
   const __amdgpu_buffer_rsrc_t rh = make_rsrc(Hn, (uint32_t)B * U * 8u);
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const int u = 16 * w + 4 * g + t;
+    const int u = 16 * w + 4 * t + g;
     hv[t] = bload2(rh, u < U ? (uint32_t)(c * U + u) * 8u : kOOB, (uint32_t)b0 * U * 8u);
   }
 }
@@ -45,7 +46,7 @@ __device__ __forceinline__ void load_h_row(IN tag, const void* Hn, int B, int U,
   const int brow = b0 + c;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const int u = 16 * w + 4 * g + t;
+    const int u = 16 * w + 4 * t + g;
     hv[t] = (brow < B && u < U) ? load_h(tag, Hn, brow, u, U) : make_float2(0.f, 0.f);
   }
 }
@@ -79,8 +80,9 @@ __device__ __forceinline__ void precode_store(const PrecodeParams& prm, int64_t 
     wave_lds_sync();
 
     // ---- q = H_u v (Algorithm 1 output) on MFMA: rows = antennas,
-    // columns = right-hand sides, k = users (k-group g takes users
-    // 16 w + 4 g + t, t = 0..3, so a lane reads 4 adjacent users of a row).
+    // columns = right-hand sides, k = users (k-step t of tile w takes users
+    // 16 w + 4 t + g; v is zero on padding users, so k-steps past U are
+    // skipped).
     const int s = s0 + c;
     const float nrm2 = Ns[c];
     const float scl = prm.normalize ? (nrm2 > 0.f ? __builtin_amdgcn_rsqf(nrm2) : 0.f) : 1.0f;
@@ -88,7 +90,7 @@ __device__ __forceinline__ void precode_store(const PrecodeParams& prm, int64_t 
 #pragma unroll
     for (int w = 0; w < W; ++w)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) vv[w][t] = Ps[(16 * w + 4 * g + t) * kPST + c];
+      for (int t = 0; t < 4; ++t) vv[w][t] = Ps[(16 * w + 4 * t + g) * kPST + c];
     float2 hn[W][4];                                 // next row tile, loaded ahead
 #pragma unroll
     for (int w = 0; w < W; ++w) load_h_row<W>(IN{}, Hn, B, U, 0, c, w, g, hn[w]);
@@ -113,6 +115,7 @@ __device__ __forceinline__ void precode_store(const PrecodeParams& prm, int64_t 
         const float2(&hv)[4] = hc[w];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
+          if (16 * w + 4 * t >= U) break;
           p1 = mfma4(hv[t].x, vv[w][t].x, p1);
           p2 = mfma4(hv[t].y, vv[w][t].y, p2);
           p3 = mfma4(hv[t].x + hv[t].y, vs[w][t], p3);
