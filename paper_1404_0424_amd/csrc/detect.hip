@@ -54,7 +54,7 @@ struct DetectStore {
 // are faster (the compiler's load-counter waits then cover exactly the
 // block consumed); with 16-bit storage the branchy form is faster.
 template <typename IN>
-constexpr bool kUncondMem = std::is_same<IN, InC32>::value;
+constexpr bool kUncondMem = std::is_same<IN, InC32>::value || std::is_same<IN, InC32P>::value;
 
 // K iterations of Algorithm 1 with the tracker of eq. (13), then mu (eq. (14)),
 // rho (eq. (15)), z = xhat / mu and the LLRs (eq. (4)) of right-hand sides
@@ -114,11 +114,11 @@ __device__ __forceinline__ void cg_llr_epilogue(const DetectParams& prm, int64_t
 }
 
 // Gram tiles -> LDS A, A^T operand and diagonal d = A_ii.
-template <int W>
-__device__ __forceinline__ void gram_to_operands(const GramAcc<W>& acc, float2* As, float* Gs,
-                                                 float2* Ps, int ast, float reg, int U, int c,
-                                                 int g, AOperand<W>& at, float (&d)[W]) {
-  store_gram_lds<W>(acc, As, Gs, (float*)Ps, ast, reg, c, g);
+template <int W, typename IN>
+__device__ __forceinline__ void gram_to_operands(IN tag, const GramAcc<W>& acc, float2* As,
+                                                 float* Gs, float2* Ps, int ast, float reg, int U,
+                                                 int c, int g, AOperand<W>& at, float (&d)[W]) {
+  store_gram(tag, acc, As, Gs, (float*)Ps, ast, reg, c, g);
   wave_lds_sync();
   at.load(As, ast, c, g, U);
 #pragma unroll
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(256, 2) void detect_stream_kernel(DetectParams prm)
     finish_mf(IN{}, acc);
     AOperand<W> at;
     float d[W];
-    gram_to_operands<W>(acc, As, Gs, Ps, AST, prm.reg, U, c, g, at, d);
+    gram_to_operands<W>(IN{}, acc, As, Gs, Ps, AST, prm.reg, U, c, g, at, d);
     cg_llr_epilogue<W, ST, M_BITS, kUncondMem<IN>>(prm, n, 0, acc, at, d, Gs, Ps, c, g);
     n = nn;
     cur = nxt;
@@ -220,7 +220,7 @@ __device__ __forceinline__ void detect_one(const DetectParams& prm, int64_t n, f
     acc.clear();
     if (s0 == 0) {
       gram_mf<W, true, true>(IN{}, Hn, Yn, B, U, S, s0, c, g, acc);
-      gram_to_operands<W>(acc, As, Gs, Ps, AST, prm.reg, U, c, g, at, d);
+      gram_to_operands<W>(IN{}, acc, As, Gs, Ps, AST, prm.reg, U, c, g, at, d);
     } else {
       gram_mf<W, false, true>(IN{}, Hn, Yn, B, U, S, s0, c, g, acc);
     }
@@ -264,6 +264,13 @@ __global__ __launch_bounds__(256, 2) void detect_batch_kernel(BatchArgs args) {
     const FrameArgs& F = args.f[f];
     DetectParams prm{F.H, F.Y, F.B, F.U, F.S, F.K, F.n_sc, F.reg, F.n0, F.es, F.scale,
                      F.inv_scale, (float*)F.out, (float2*)F.out2, nullptr, nullptr};
+    if constexpr (std::is_same<IN, InC32>::value) {
+      if (F.U <= 8) {               // packed form, as a single call of this frame runs
+        detect_one<1, InC32P, ST, M_BITS>(prm, gsc - F.sc_begin, A_s[wv], P_s[wv], G_s[wv], c,
+                                          g);
+        continue;
+      }
+    }
     detect_one<W, IN, ST, M_BITS>(prm, gsc - F.sc_begin, A_s[wv], P_s[wv], G_s[wv], c, g);
   }
 }
@@ -303,7 +310,10 @@ template <int W>
 static hipError_t launch_in(const DetectParams& p, int in_dtype, int f64, int m_bits,
                             const Schedule& sch, hipStream_t stream) {
   switch (in_dtype) {
-    case 0: return launch_st<W, InC32>(p, f64, m_bits, sch, stream);
+    case 0:
+      if constexpr (W == 1)
+        if (p.U <= 8) return launch_st<1, InC32P>(p, f64, m_bits, sch, stream);
+      return launch_st<W, InC32>(p, f64, m_bits, sch, stream);
     case 1: return launch_st<W, InF16>(p, f64, m_bits, sch, stream);
     case 2: return launch_st<W, InBF16>(p, f64, m_bits, sch, stream);
   }

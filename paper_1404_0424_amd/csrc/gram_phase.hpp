@@ -20,6 +20,18 @@
 //   Gram tile (wr, wc):   G[16 wr + 4 g + j][16 wc + c]
 //   matched filter w:     b[user 16 w + c][rhs s0 + 4 g + j]
 // which is the layout the CG phase works in (lane = user, 4 rhs per lane).
+//
+// Packed form (storage tag InC32P: complex64 with U <= 8): the users fill
+// only half of a 16-wide tile, so lanes c and c + 8 both load user c & 7 and
+// give the MFMA its real part (c < 8) or imaginary part (c >= 8).  One
+// product of that operand with itself is the whole real Gram,
+//   C = [Hr Hi]^T [Hr Hi],  Re G = C[0:8, 0:8] + C[8:16, 8:16],
+//                           Im G = C[0:8, 8:16] - C[8:16, 0:8],
+// and two products with Yr and Yi give the matched filter (C1 = Yr^T [Hr Hi],
+// C2 = Yi^T [Hr Hi]):  Re b^T = C1[:, 0:8] + C2[:, 8:16],
+//                      Im b^T = C2[:, 0:8] - C1[:, 8:16],
+// 3 MFMAs per k-step instead of 6.  finish_mf and store_gram fold the halves
+// back into the standard layout.
 #pragma once
 
 #include "common.hpp"
@@ -93,6 +105,7 @@ __host__ __device__ constexpr int tile_index(int wr, int wc, int W) {
 
 // Input storage tags
 struct InC32 {};
+struct InC32P {};   // complex64, U <= 8, packed form (one wavefront per subcarrier)
 struct InF16 {};
 struct InBF16 {};
 
@@ -178,6 +191,47 @@ __device__ __forceinline__ void finish_mf(InC32, GramAcc<W>& acc) {
     const f4 p1 = acc.dr[w], p2 = acc.di[w];
     acc.dr[w] = p1 + p2;
     acc.di[w] = acc.p3[w] - p1 + p2;
+  }
+}
+
+// ------------------------------------------------------ complex64, packed
+struct SubC32P : SubC32<1> {
+  __device__ void init(const void* Hn, const void* Yn, int B, int U_, int S_, int s0, int c,
+                       int g) {
+    SubC32<1>::init(Hn, Yn, B, U_, S_, s0, c, g);
+    const int u = c & 7;
+    oh[0] = u < U ? (uint32_t)(g * U + u) * 8u : kOOB;
+  }
+};
+
+template <int UNR>
+struct BlockC32P : BlockC32<1, UNR> {
+  template <bool DO_GRAM, bool DO_MF>
+  __device__ __forceinline__ void mma(GramAcc<1>& acc) const {
+    const bool re = (__lane_id() & 8) == 0;
+#pragma unroll
+    for (int t = 0; t < UNR; ++t) {
+      const float2 v = this->h[t][0];       // select by value: a select between member
+      const float a = re ? v.x : v.y;       // addresses would keep the block in scratch
+      if (DO_GRAM) acc.gr[0] = mfma4(a, a, acc.gr[0]);
+      if (DO_MF) {
+        acc.dr[0] = mfma4(this->y[t].x, a, acc.dr[0]);
+        acc.di[0] = mfma4(this->y[t].y, a, acc.di[0]);
+      }
+    }
+  }
+};
+
+// Re b = C1[s][u] + C2[s][u + 8], Im b = C2[s][u] - C1[s][u + 8] on the lanes
+// of users u < 8 (partner lane u + 8), zero on the others.
+__device__ __forceinline__ void finish_mf(InC32P, GramAcc<1>& acc) {
+  const bool lo = (__lane_id() & 8) == 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float c1 = acc.dr[0][j], c2 = acc.di[0][j];
+    const float c1h = __shfl_xor(c1, 8, 64), c2h = __shfl_xor(c2, 8, 64);
+    acc.dr[0][j] = lo ? c1 + c2h : 0.f;
+    acc.di[0][j] = lo ? c2 - c1h : 0.f;
   }
 }
 
@@ -287,6 +341,12 @@ struct Storage<InF16, W> {
   using Block = Block16<W, h8, W == 1 ? 2 : 1>;
   using SmallBlock = Block16<W, h8, 1>;
 };
+template <>
+struct Storage<InC32P, 1> {
+  using Sub = SubC32P;
+  using Block = BlockC32P<8>;
+  using SmallBlock = BlockC32P<4>;
+};
 template <int W>
 struct Storage<InBF16, W> {
   using Sub = Sub16<W>;
@@ -314,6 +374,10 @@ template <typename IN>
 __device__ __forceinline__ const void* offset_sc(IN tag, const void* base, int64_t n, int R, int C);
 template <>
 __device__ __forceinline__ const void* offset_sc(InC32, const void* base, int64_t n, int R, int C) {
+  return (const float2*)base + (size_t)n * R * C;
+}
+template <>
+__device__ __forceinline__ const void* offset_sc(InC32P, const void* base, int64_t n, int R, int C) {
   return (const float2*)base + (size_t)n * R * C;
 }
 template <>
@@ -366,6 +430,37 @@ __device__ __forceinline__ void store_gram_lds(const GramAcc<W>& acc, float2* As
         }
       }
     }
+}
+
+// store_gram_lds for any storage form: the packed form first folds
+// C = [Hr Hi]^T [Hr Hi] into Re G and M (through `scratch`), then writes A
+// as store_gram_lds does.
+template <int W, typename IN>
+__device__ __forceinline__ void store_gram(IN, const GramAcc<W>& acc, float2* As, float* Gd,
+                                           float* scratch, int ast, float reg, int c, int g) {
+  store_gram_lds<W>(acc, As, Gd, scratch, ast, reg, c, g);
+}
+__device__ __forceinline__ void store_gram(InC32P, const GramAcc<1>& acc, float2* As, float* Gd,
+                                           float* scratch, int ast, float reg, int c, int g) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) scratch[(4 * g + j) * 17 + c] = acc.gr[0][j];
+  wave_lds_sync();
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int r = 4 * g + j;
+    float re = 0.f, im = 0.f;                         // users >= 8 are padding
+    if (r < 8 && c < 8) {
+      re = acc.gr[0][j] + scratch[(r + 8) * 17 + c + 8];
+      im = scratch[r * 17 + c + 8] - scratch[(r + 8) * 17 + c];
+    }
+    if (r < c) {
+      As[r * ast + c] = make_float2(re, im);
+      As[c * ast + r] = make_float2(re, -im);
+    } else if (r == c) {
+      As[r * ast + r] = make_float2(re + reg, 0.f);
+      Gd[r] = re;
+    }
+  }
 }
 
 }  // namespace mimo

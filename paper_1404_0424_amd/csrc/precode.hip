@@ -29,7 +29,7 @@ __device__ __forceinline__ void precode_one(const PrecodeParams& prm, int64_t n,
       GramAcc<W> acc;
       acc.clear();
       gram_mf<W, true, false>(IN{}, Hn, nullptr, B, U, S, 0, c, g, acc);
-      store_gram_lds<W>(acc, As, Gs, (float*)Ps, AST, beta, c, g);
+      store_gram(IN{}, acc, As, Gs, (float*)Ps, AST, beta, c, g);
       wave_lds_sync();
       at.load(As, AST, c, g, U);
     }
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(256, 2) void precode_stream_kernel(PrecodeParams pr
       alt.template mma<true, false>(acc);
       if (!more2) break;
     }
-    store_gram_lds<W>(acc, As, Gs, (float*)Ps, AST, prm.beta, c, g);
+    store_gram(IN{}, acc, As, Gs, (float*)Ps, AST, prm.beta, c, g);
     wave_lds_sync();
     AOperand<W> at;
     at.load(As, AST, c, g, U);
@@ -176,6 +176,10 @@ struct ResidentBlock<InC32> {
   using type = BlockC32<1, 1>;    // one k-step: 4 antennas
 };
 template <>
+struct ResidentBlock<InC32P> {
+  using type = BlockC32P<1>;      // packed form (U <= 8)
+};
+template <>
 struct ResidentBlock<InF16> {
   using type = Block16<1, h8, 1>;   // one k-step: 32 antennas
 };
@@ -189,9 +193,11 @@ struct ResidentBlock<InBF16> {
 // 4 (u % 4) + u / 4: the contraction's k-step t takes users 4 t + g, which
 // then sit in the four adjacent slots 4 g .. 4 g + 3 of a row.
 __device__ __forceinline__ int user_slot(int u) { return ((u & 3) << 2) | (u >> 2); }
-template <int NK>
-__device__ __forceinline__ void stage_h_tile(const BlockC32<1, 1> (&hb)[NK], int i,
-                                             float2* __restrict__ Hs, int c, int g) {
+// (Packed form: lanes c and c + 8 hold the same user c & 7, so slots of
+// users 8..15 receive copies; the contraction never reads them for U <= 8.)
+template <typename BLK, int NK>
+__device__ __forceinline__ void stage_h_tile(const BLK (&hb)[NK], int i, float2* __restrict__ Hs,
+                                             int c, int g) {
   const int sl = user_slot(c);
 #pragma unroll
   for (int t = 0; t < 4; ++t) Hs[(4 * t + g) * kPST + sl] = hb[4 * i + t].h[0][0];
@@ -222,7 +228,7 @@ __global__ __launch_bounds__(256, resident_min_blocks<ST>()) void precode_reside
   using Sub = typename Storage<IN, 1>::Sub;
   using RB = typename ResidentBlock<IN>::type;
   constexpr int NK = BMAX / RB::ANT;            // k-steps held in registers
-  constexpr bool C32 = std::is_same<IN, InC32>::value;
+  constexpr bool C32 = std::is_same<IN, InC32>::value || std::is_same<IN, InC32P>::value;
   __shared__ __align__(16) float2 A_s[kWavesPerBlock][NU * AST];
   __shared__ __align__(16) float2 P_s[kWavesPerBlock][NU * kPST];
   __shared__ __align__(16) float2 H2_s[kWavesPerBlock][NU * kPST];
@@ -267,7 +273,7 @@ __global__ __launch_bounds__(256, resident_min_blocks<ST>()) void precode_reside
 #pragma unroll
     for (int t = 0; t < NK; ++t)
       if (t * RB::ANT < B) hb[t].template mma<true, false>(acc);
-    store_gram_lds<1>(acc, As, Gs, (float*)Ps, AST, prm.beta, c, g);
+    store_gram(IN{}, acc, As, Gs, (float*)Ps, AST, prm.beta, c, g);
     wave_lds_sync();
     AOperand<1> at;
     at.load(As, AST, c, g, U);
@@ -408,6 +414,13 @@ __global__ __launch_bounds__(256, 2) void precode_batch_kernel(BatchArgs args) {
     const FrameArgs& F = args.f[f];
     PrecodeParams prm{F.H, (const float2*)F.Y, F.B, F.U, F.S, F.K, F.n_sc, F.beta,
                       F.normalize, (float2*)F.out, (float*)F.out2};
+    if constexpr (std::is_same<IN, InC32>::value) {
+      if (F.U <= 8) {               // packed form, as a single call of this frame runs
+        precode_one<1, InC32P, ST>(prm, gsc - F.sc_begin, A_s[wv], P_s[wv], G_s[wv], N_s[wv], c,
+                                   g);
+        continue;
+      }
+    }
     precode_one<W, IN, ST>(prm, gsc - F.sc_begin, A_s[wv], P_s[wv], G_s[wv], N_s[wv], c, g);
   }
 }
@@ -442,7 +455,10 @@ template <int W>
 static hipError_t launch_in(const PrecodeParams& p, int in_dtype, int f64, const Schedule& sch,
                             hipStream_t stream) {
   switch (in_dtype) {
-    case 0: return launch_st<W, InC32>(p, f64, sch, stream);
+    case 0:
+      if constexpr (W == 1)
+        if (p.U <= 8) return launch_st<1, InC32P>(p, f64, sch, stream);
+      return launch_st<W, InC32>(p, f64, sch, stream);
     case 1: return launch_st<W, InF16>(p, f64, sch, stream);
     case 2: return launch_st<W, InBF16>(p, f64, sch, stream);
   }

@@ -40,6 +40,11 @@ __device__ __forceinline__ void load_h_row(InC32, const void* Hn, int B, int U, 
     hv[t] = bload2(rh, u < U ? (uint32_t)(c * U + u) * 8u : kOOB, (uint32_t)b0 * U * 8u);
   }
 }
+template <int W>
+__device__ __forceinline__ void load_h_row(InC32P, const void* Hn, int B, int U, int b0, int c,
+                                           int w, int g, float2 (&hv)[4]) {
+  load_h_row<W>(InC32{}, Hn, B, U, b0, c, w, g, hv);
+}
 template <int W, typename IN>
 __device__ __forceinline__ void load_h_row(IN tag, const void* Hn, int B, int U, int b0, int c,
                                            int w, int g, float2 (&hv)[4]) {
