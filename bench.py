@@ -41,12 +41,14 @@ DETECT_SOURCES = ["detect.hip", "cg_core.hpp", "gram_phase.hpp", "llr.hpp", "ker
 PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
 
 
-def recorded_traffic(kernel, workload, n_sc):
+def recorded_traffic(kernel, workload, n_sc, persistent=False):
     """HBM bytes per launch of ``kernel`` from the committed counter summary
     profiles/<kernel>_<workload>_c32.md (FETCH_SIZE + WRITE_SIZE passes,
-    scaled by a plain copy of known size).  The summary records the source
-    digest of the kernel's files and the subcarriers per launch; a figure
-    taken from other sources or another launch size is not reported."""
+    scaled by a plain copy of known size), for a grid of one wavefront per
+    subcarrier or, with ``persistent``, a capped (persistent) grid.  The
+    summary records the source digest of the kernel's files and the
+    subcarriers per launch; a figure taken from other sources or another
+    launch size is not reported."""
     path = os.path.join(PROFILES, f"{kernel}_{workload}_c32.md")
     if not os.path.exists(path):
         return None
@@ -61,7 +63,8 @@ def recorded_traffic(kernel, workload, n_sc):
         if (rec.get("source_digest") != source_digest(DETECT_SOURCES)
                 or int(rec["subcarriers_per_launch"]) != n_sc):
             return None
-        return {"bytes_per_launch": float(rec["hbm_bytes_per_launch"]),
+        key = "hbm_bytes_per_launch_persistent" if persistent else "hbm_bytes_per_launch"
+        return {"bytes_per_launch": float(rec[key]),
                 "file": os.path.relpath(path, os.path.dirname(PROFILES))}
     except (KeyError, ValueError):
         return None
@@ -248,8 +251,9 @@ def main():
     det_bytes = detect_bytes_per_sc(wl.B, wl.U, wl.S, wl.m) * n
     pre_bytes = precode_bytes_per_sc(wl.B, wl.U, wl.S) * n
     achieved = det_bytes / det_s / 1e9
-    det_kernel = DETECT_KERNEL[autotune.variants("detect")[autotune.get_schedule("detect", wl.U, 0)[0]]]
-    traffic = recorded_traffic(det_kernel, wl.name, n)
+    det_v, det_bpc = autotune.get_schedule("detect", wl.U, 0)
+    det_kernel = DETECT_KERNEL[autotune.variants("detect")[det_v]]
+    traffic = recorded_traffic(det_kernel, wl.name, n, persistent=det_bpc > 0)
     # reference: a plain device copy moving the same number of bytes (half
     # read, half written), timed the same way
     src = torch.empty(det_bytes // 8, dtype=torch.float32, device=dev).fill_(1.0)
@@ -463,18 +467,26 @@ def oracle_errors(samples, O):
 def mfma_count(B, U, S, K, op):
     """v_mfma_f32_16x16x4_f32 instructions per subcarrier issued by the
     complex64 kernels: Gram tiles (3 per k-step on a diagonal tile, 4 off
-    it), the three-product matched filter / q = H v, and 16 W^2 per CG
-    mat-vec; k-steps of 4 antennas (users for q = H v)."""
+    it), the three-product matched filter, 4 W per k-step of 4 users in a
+    CG mat-vec and 3 per k-step in q = H v (k-steps past the last user are
+    skipped); k-steps of 4 antennas for the Gram and matched filter.  The
+    detectors and precoders run the packed form at U <= 8 (one product per
+    k-step for the Gram, two for the matched filter); the standalone Gram
+    kernel does not."""
     W = 1 if U <= 16 else 2
     ksteps = -(-B // 4)
     chunks = -(-S // 16)
-    gram = ksteps * (3 * W + 4 * (W * (W - 1) // 2))
+    nk = min(4 * W, -(-U // 4))
     if op == "gram_mf":
-        return gram + chunks * ksteps * 3 * W
+        return ksteps * (3 * W + 4 * (W * (W - 1) // 2)) + chunks * ksteps * 3 * W
+    packed = U <= 8
+    gram = ksteps * (1 if packed else 3 * W + 4 * (W * (W - 1) // 2))
+    mf = ksteps * (2 if packed else 3 * W)
+    matvec = 4 * W * nk
     if op == "detect":
-        return gram + chunks * (ksteps * 3 * W + K * 16 * W * W)
+        return gram + chunks * (mf + K * matvec)
     # precode: Gram, K mat-vecs + one for ||q||^2, q = H v per 16-antenna tile
-    return gram + chunks * ((K + 1) * 16 * W * W + (-(-B // 16)) * 12 * W)
+    return gram + chunks * ((K + 1) * matvec + (-(-B // 16)) * 3 * nk)
 
 
 def configs_leg(api, autotune, kernel_time, dev, samples):

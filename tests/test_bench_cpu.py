@@ -28,12 +28,20 @@ def test_mfma_counts_match_the_instruction_counters():
     # U = 32: four 16x16 tiles, three in the upper triangle
     g = bench.mfma_count(256, 32, 14, 6, "gram_mf")
     assert g == 64 * (2 * 3 + 4) + 64 * 3 * 2
+    # U = 8: packed Gram (1 per k-step) and matched filter (2), mat-vec over
+    # the 2 k-steps of real users (4 each), q = H v 3 per k-step and tile
+    assert bench.mfma_count(128, 8, 14, 3, "detect") == 32 * 1 + 32 * 2 + 3 * 8
+    assert bench.mfma_count(128, 8, 14, 3, "precode") == 32 * 1 + 4 * 8 + 8 * 3 * 2
+    assert bench.mfma_count(128, 8, 14, 3, "gram_mf") == 32 * 3 + 32 * 3
+    # U = 20: the second user tile holds one k-step of real users
+    assert bench.mfma_count(64, 20, 14, 2, "detect") == 16 * 10 + 16 * 6 + 2 * 4 * 2 * 5
 
 
 def test_recorded_traffic_only_for_matching_launch():
-    rec = bench.recorded_traffic("detect_stream_kernel", "mixed_128x16", 19200)
-    if rec is not None:                     # present while the kernel sources are unchanged
-        assert rec["bytes_per_launch"] > bench.detect_bytes_per_sc(128, 16, 14, 6) * 19200 * 0.99
+    for persistent in (False, True):
+        rec = bench.recorded_traffic("detect_stream_kernel", "mixed_128x16", 19200, persistent)
+        if rec is not None:                 # present while the kernel sources are unchanged
+            assert rec["bytes_per_launch"] > bench.detect_bytes_per_sc(128, 16, 14, 6) * 19200 * 0.99
     assert bench.recorded_traffic("detect_stream_kernel", "mixed_128x16", 1200) is None
     assert bench.recorded_traffic("no_such_kernel", "mixed_128x16", 19200) is None
 
