@@ -396,12 +396,22 @@ def test_schedules_give_identical_results(case):
             assert np.array_equal(a, b)
 
 
-def test_batched_calls_equal_single_calls():
+BATCH_SHAPES = {
+    # largest U = 32: two-tile batched kernel, frames of U <= 8 in the packed form
+    "two_tiles": [(64, 8, 30, 14, 4), (128, 16, 21, 14, 3), (32, 5, 17, 3, 2),
+                  (256, 32, 9, 14, 5), (128, 12, 13, 20, 4)],
+    # largest U = 16: one-tile batched kernel, packed (U <= 8) and standard frames mixed
+    "one_tile": [(32, 8, 19, 14, 3), (128, 16, 11, 14, 4), (24, 3, 23, 5, 2), (96, 12, 7, 17, 3),
+                 (40, 1, 5, 2, 1)],
+}
+
+
+@pytest.mark.parametrize("which", list(BATCH_SHAPES))
+def test_batched_calls_equal_single_calls(which):
     """Frames of different shapes in one batched launch give bitwise the
     same outputs as separate single-frame calls (and match the oracle)."""
     rng = np.random.default_rng(99)
-    shapes = [(64, 8, 30, 14, 4), (128, 16, 21, 14, 3), (32, 5, 17, 3, 2), (256, 32, 9, 14, 5),
-              (128, 12, 13, 20, 4)]
+    shapes = BATCH_SHAPES[which]
     ups, dns = [], []
     for B, U, n, S, K in shapes:
         f = W.uplink_frame(rng, n, B, U, S, 6, 12.0)
