@@ -23,6 +23,7 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
+FP32_VECTOR_TFLOPS = 157.3      # MI355X FP32 vector peak
 METRIC = "MMSE-CG subcarrier-solves/s + LLR Gbit/s at B=128,U=16; p50/p99 frame latency"
 CFG_INDEX = {"small_32x8": 1, "plain_128x8": 2, "mixed_128x16": 3, "mixed_128x32": 3,
              "corr_256x32": 5}
@@ -333,6 +334,22 @@ def main():
                             "precode_kernel_ms": p2 * 1e3,
                             "storage": f"{dt} H and Y, FP32 accumulate and CG"}
             del H16, Y16
+        # exact in-loop SINR (parity mode, Sec. III-C-1): U x U x U complex
+        # products per iteration and right-hand side on VALU, timed on 2 frames
+        n_ex = min(n, 2 * wl.n_sc)
+        ex_s = kernel_time(lambda: api.detect_cg(H[:n_ex], Y[:n_ex], n0, es, K, m, "exact",
+                                                 scalar), reps=3)
+        ex_flops = 8.0 * wl.U ** 3 * (K + 2) * wl.S * n_ex
+        variants["exact_sinr"] = {
+            "subcarriers": n_ex, "detect_kernel_ms": ex_s * 1e3,
+            "uplink_solves_per_s": n_ex * wl.S / ex_s,
+            "roofline": {"bound": "alu", "achieved": ex_flops / ex_s / 1e12,
+                         "peak": FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                         "frac": ex_flops / ex_s / 1e12 / FP32_VECTOR_TFLOPS},
+            "what": "exact SINR tracker: E = A P each iteration, then B = L_K G and "
+                    "C = B L_K^H, 8 U^3 flops each per right-hand side (complex FMA on VALU)"}
+        log(f"exact-SINR detection ({n_ex} subcarriers): {ex_s * 1e3:.3f} ms, "
+            f"{ex_flops / ex_s / 1e12:.1f} TFLOP/s of the tracker's products")
         result["variants"] = variants
 
     if not args.no_latency:
