@@ -335,20 +335,20 @@ def main():
                             "storage": f"{dt} H and Y, FP32 accumulate and CG"}
             del H16, Y16
         # exact in-loop SINR (parity mode, Sec. III-C-1): one U x U x U complex
-        # product per iteration and right-hand side plus B = L_K G, timed on 2 frames
-        n_ex = min(n, 2 * wl.n_sc)
-        ex_s = kernel_time(lambda: api.detect_cg(H[:n_ex], Y[:n_ex], n0, es, K, m, "exact",
-                                                 scalar), reps=3)
-        ex_flops = 8.0 * wl.U ** 3 * (K + 1) * wl.S * n_ex
+        # product per iteration and right-hand side plus B = L_K G, on MFMA for
+        # U <= 16 (FP32 matrix peak) and VALU for two user tiles (vector peak)
+        ex_s = kernel_time(lambda: api.detect_cg(H, Y, n0, es, K, m, "exact", scalar), reps=3)
+        ex_flops = 8.0 * wl.U ** 3 * (K + 1) * wl.S * n
+        ex_peak = MFMA_PEAK_FP32 / 1e12 if wl.U <= 16 else FP32_VECTOR_TFLOPS
         variants["exact_sinr"] = {
-            "subcarriers": n_ex, "detect_kernel_ms": ex_s * 1e3,
-            "uplink_solves_per_s": n_ex * wl.S / ex_s,
-            "roofline": {"bound": "alu", "achieved": ex_flops / ex_s / 1e12,
-                         "peak": FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                         "frac": ex_flops / ex_s / 1e12 / FP32_VECTOR_TFLOPS},
+            "subcarriers": n, "detect_kernel_ms": ex_s * 1e3,
+            "uplink_solves_per_s": n * wl.S / ex_s,
+            "roofline": {"bound": "mfma" if wl.U <= 16 else "alu",
+                         "achieved": ex_flops / ex_s / 1e12, "peak": ex_peak, "unit": "TFLOP/s",
+                         "frac": ex_flops / ex_s / 1e12 / ex_peak},
             "what": "exact SINR tracker: E = A P each iteration, then B = L_K G (and the "
                     "diagonal of B L_K^H), 8 U^3 flops per product and right-hand side"}
-        log(f"exact-SINR detection ({n_ex} subcarriers): {ex_s * 1e3:.3f} ms, "
+        log(f"exact-SINR detection ({n} subcarriers): {ex_s * 1e3:.3f} ms, "
             f"{ex_flops / ex_s / 1e12:.1f} TFLOP/s of the tracker's products")
         result["variants"] = variants
 

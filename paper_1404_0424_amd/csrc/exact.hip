@@ -9,7 +9,9 @@
 //
 // This costs a U x U x U complex product per iteration and right-hand side
 // (the paper notes its high complexity); one wavefront handles one subcarrier
-// and walks its right-hand sides in turn, with the matrices in LDS.
+// and walks its right-hand sides in turn.  With one user tile (U <= 16) the
+// products run on MFMA with V, R, P in registers; two tiles use VALU FMAs
+// over LDS.
 #include "cg_core.hpp"
 #include "gram_phase.hpp"
 #include "launch.hpp"
@@ -25,7 +27,9 @@ __global__ __launch_bounds__(64) void detect_exact_kernel(DetectParams prm) {
   __shared__ __align__(16) float2 As[NU * AST];
   __shared__ float Gs[NU];
   __shared__ __align__(16) float2 Bs[16 * AST];   // matched filter of the current chunk [rhs][user]
-  __shared__ __align__(16) float2 Vm[NU * MST], Rm[NU * MST], Pm[NU * MST], Em[NU * MST];
+  // (one tile keeps R in registers and needs 16 entries of Em for the row terms)
+  __shared__ __align__(16) float2 Vm[NU * MST], Pm[NU * MST];
+  __shared__ __align__(16) float2 Rm[W == 1 ? 1 : NU * MST], Em[W == 1 ? 16 : NU * MST];
   __shared__ __align__(16) float2 pv[NU];
   const int t = threadIdx.x;
   const int c = t & 15, g = t >> 4;
@@ -60,78 +64,177 @@ __global__ __launch_bounds__(64) void detect_exact_kernel(DetectParams prm) {
         const float2 bu = own ? Bs[sl * AST + t] : make_float2(0.f, 0.f);
         float2 v = make_float2(0.f, 0.f), r = bu, p = bu;
         ST rr = wave_sum<ST>((ST)bu.x * (ST)bu.x + (ST)bu.y * (ST)bu.y);
-        for (int idx = t; idx < UU; idx += kWave) {
-          const int i = idx / U, j = idx % U;
-          const float2 id = make_float2(i == j ? 1.f : 0.f, 0.f);
-          Vm[i * MST + j] = make_float2(0.f, 0.f);
-          Rm[i * MST + j] = id;
-          Pm[i * MST + j] = id;
-        }
-        __syncthreads();
-        for (int k = 0; k < prm.K; ++k) {
-          if (own) pv[t] = p;
+        float mu = 0.f, nu2 = 0.f;     // mu_t = Re B_tt and nu_t^2 of the own user t
+        if constexpr (W == 1) {
+          // Matrices on MFMA (16x16x4, four real products per complex one),
+          // held in the D layout: lane (c, g) keeps entries (4 g + jj, c).
+          float2 Vr[4], Rr[4], Pr[4];
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) {
+            const int i = 4 * g + jj;
+            const float2 id = make_float2(i == c && i < U ? 1.f : 0.f, 0.f);
+            Vr[jj] = make_float2(0.f, 0.f);
+            Rr[jj] = id;
+            Pr[jj] = id;
+          }
+          for (int k = 0; k < prm.K; ++k) {
+            if (own) pv[t] = p;
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) Pm[(4 * g + jj) * MST + c] = Pr[jj];
+            __syncthreads();
+            float2 e = make_float2(0.f, 0.f);
+            if (own)
+              for (int l = 0; l < U; ++l) cfma(e, As[t * AST + l], pv[l]);
+            f4 er = zero4(), ei = zero4();                    // E = A P
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt) {
+              const float2 a = As[c * AST + 4 * tt + g];      // A[c][4 tt + g]
+              const float2 b = Pm[(4 * tt + g) * MST + c];    // P[4 tt + g][c]
+              er = mfma4(a.x, b.x, er);
+              er = mfma4(-a.y, b.y, er);
+              ei = mfma4(a.x, b.y, ei);
+              ei = mfma4(a.y, b.x, ei);
+            }
+            const ST pe = wave_sum<ST>((ST)p.x * (ST)e.x + (ST)p.y * (ST)e.y);
+            const bool live = rr > ST(0) && pe > ST(0);
+            const ST alpha = live ? rr / pe : ST(0);
+            const float af = (float)alpha;
+            v.x = __builtin_fmaf(af, p.x, v.x);
+            v.y = __builtin_fmaf(af, p.y, v.y);
+            r.x = __builtin_fmaf(-af, e.x, r.x);
+            r.y = __builtin_fmaf(-af, e.y, r.y);
+            const ST rr_new = wave_sum<ST>((ST)r.x * (ST)r.x + (ST)r.y * (ST)r.y);
+            const ST beta = live ? rr_new / rr : ST(0);
+            const float bf = (float)beta;
+            if (live) {
+              p.x = __builtin_fmaf(bf, p.x, r.x);
+              p.y = __builtin_fmaf(bf, p.y, r.y);
+              rr = rr_new;
+            }
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+              const float2 P0 = Pr[jj];
+              Vr[jj].x = __builtin_fmaf(af, P0.x, Vr[jj].x);
+              Vr[jj].y = __builtin_fmaf(af, P0.y, Vr[jj].y);
+              Rr[jj].x = __builtin_fmaf(-af, er[jj], Rr[jj].x);
+              Rr[jj].y = __builtin_fmaf(-af, ei[jj], Rr[jj].y);
+              Pr[jj] = make_float2(__builtin_fmaf(bf, P0.x, Rr[jj].x),
+                                   __builtin_fmaf(bf, P0.y, Rr[jj].y));
+            }
+            __syncthreads();
+          }
+          // B = L_K G (G = A - reg I off the diagonal; diagonal G_ii)
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) Vm[(4 * g + jj) * MST + c] = Vr[jj];
           __syncthreads();
-          float2 e = make_float2(0.f, 0.f);
-          if (own)
-            for (int l = 0; l < U; ++l) cfma(e, As[t * AST + l], pv[l]);
-          for (int idx = t; idx < UU; idx += kWave) {          // E = A P
+          f4 br = zero4(), bi = zero4();
+#pragma unroll
+          for (int tt = 0; tt < 4; ++tt) {
+            const int l = 4 * tt + g;
+            const float2 a = Vm[c * MST + l];                  // V[c][l]
+            const float2 b = l == c ? make_float2(Gs[c], 0.f) : As[l * AST + c];   // G[l][c]
+            br = mfma4(a.x, b.x, br);
+            br = mfma4(-a.y, b.y, br);
+            bi = mfma4(a.x, b.y, bi);
+            bi = mfma4(a.y, b.x, bi);
+          }
+          // row i = 4 g + jj: mu_i = Re B_ii, sum_{j != i} |B_ij|^2 and
+          // C_ii = sum_j Re(B_ij conj(L_ij)), reduced over the row's 16 lanes
+          float2* X = (float2*)Em;
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) {
+            const int i = 4 * g + jj;
+            const float2 b = make_float2(br[jj], bi[jj]);
+            float off = (c != i && c < U) ? cabs2(b) : 0.f;
+            float cii = b.x * Vr[jj].x + b.y * Vr[jj].y;
+            float mui = c == i ? b.x : 0.f;
+            off = row_sum16(off);
+            cii = row_sum16(cii);
+            mui = row_sum16(mui);
+            if (c == 0) X[i] = make_float2(mui, off * prm.es + cii * prm.n0);
+          }
+          __syncthreads();
+          if (own) {
+            mu = X[t].x;
+            nu2 = X[t].y;
+          }
+        } else {
+          for (int idx = t; idx < UU; idx += kWave) {
+            const int i = idx / U, j = idx % U;
+            const float2 id = make_float2(i == j ? 1.f : 0.f, 0.f);
+            Vm[i * MST + j] = make_float2(0.f, 0.f);
+            Rm[i * MST + j] = id;
+            Pm[i * MST + j] = id;
+          }
+          __syncthreads();
+          for (int k = 0; k < prm.K; ++k) {
+            if (own) pv[t] = p;
+            __syncthreads();
+            float2 e = make_float2(0.f, 0.f);
+            if (own)
+              for (int l = 0; l < U; ++l) cfma(e, As[t * AST + l], pv[l]);
+            for (int idx = t; idx < UU; idx += kWave) {          // E = A P
+              const int i = idx / U, j = idx % U;
+              float2 x = make_float2(0.f, 0.f);
+              for (int l = 0; l < U; ++l) cfma(x, As[i * AST + l], Pm[l * MST + j]);
+              Em[i * MST + j] = x;
+            }
+            const ST pe = wave_sum<ST>((ST)p.x * (ST)e.x + (ST)p.y * (ST)e.y);
+            const bool live = rr > ST(0) && pe > ST(0);
+            const ST alpha = live ? rr / pe : ST(0);
+            const float af = (float)alpha;
+            v.x = __builtin_fmaf(af, p.x, v.x);
+            v.y = __builtin_fmaf(af, p.y, v.y);
+            r.x = __builtin_fmaf(-af, e.x, r.x);
+            r.y = __builtin_fmaf(-af, e.y, r.y);
+            const ST rr_new = wave_sum<ST>((ST)r.x * (ST)r.x + (ST)r.y * (ST)r.y);
+            const ST beta = live ? rr_new / rr : ST(0);
+            const float bf = (float)beta;
+            if (live) {
+              p.x = __builtin_fmaf(bf, p.x, r.x);
+              p.y = __builtin_fmaf(bf, p.y, r.y);
+              rr = rr_new;
+            }
+            __syncthreads();
+            for (int idx = t; idx < UU; idx += kWave) {
+              const int i = idx / U, j = idx % U, o = i * MST + j;
+              const float2 P0 = Pm[o], E0 = Em[o];
+              float2 Vn = Vm[o], Rn = Rm[o];
+              Vn.x = __builtin_fmaf(af, P0.x, Vn.x);
+              Vn.y = __builtin_fmaf(af, P0.y, Vn.y);
+              Rn.x = __builtin_fmaf(-af, E0.x, Rn.x);
+              Rn.y = __builtin_fmaf(-af, E0.y, Rn.y);
+              Vm[o] = Vn;
+              Rm[o] = Rn;
+              Pm[o] = make_float2(__builtin_fmaf(bf, P0.x, Rn.x), __builtin_fmaf(bf, P0.y, Rn.y));
+            }
+            __syncthreads();
+          }
+          // ---- B = L_K G (G = A - reg I off the diagonal; diagonal G_ii)
+          for (int idx = t; idx < UU; idx += kWave) {
             const int i = idx / U, j = idx % U;
             float2 x = make_float2(0.f, 0.f);
-            for (int l = 0; l < U; ++l) cfma(x, As[i * AST + l], Pm[l * MST + j]);
+            for (int l = 0; l < U; ++l) {
+              const float2 gl = (l == j) ? make_float2(Gs[j], 0.f) : As[l * AST + j];
+              cfma(x, Vm[i * MST + l], gl);
+            }
             Em[i * MST + j] = x;
           }
-          const ST pe = wave_sum<ST>((ST)p.x * (ST)e.x + (ST)p.y * (ST)e.y);
-          const bool live = rr > ST(0) && pe > ST(0);
-          const ST alpha = live ? rr / pe : ST(0);
-          const float af = (float)alpha;
-          v.x = __builtin_fmaf(af, p.x, v.x);
-          v.y = __builtin_fmaf(af, p.y, v.y);
-          r.x = __builtin_fmaf(-af, e.x, r.x);
-          r.y = __builtin_fmaf(-af, e.y, r.y);
-          const ST rr_new = wave_sum<ST>((ST)r.x * (ST)r.x + (ST)r.y * (ST)r.y);
-          const ST beta = live ? rr_new / rr : ST(0);
-          const float bf = (float)beta;
-          if (live) {
-            p.x = __builtin_fmaf(bf, p.x, r.x);
-            p.y = __builtin_fmaf(bf, p.y, r.y);
-            rr = rr_new;
-          }
           __syncthreads();
-          for (int idx = t; idx < UU; idx += kWave) {
-            const int i = idx / U, j = idx % U, o = i * MST + j;
-            const float2 P0 = Pm[o], E0 = Em[o];
-            float2 Vn = Vm[o], Rn = Rm[o];
-            Vn.x = __builtin_fmaf(af, P0.x, Vn.x);
-            Vn.y = __builtin_fmaf(af, P0.y, Vn.y);
-            Rn.x = __builtin_fmaf(-af, E0.x, Rn.x);
-            Rn.y = __builtin_fmaf(-af, E0.y, Rn.y);
-            Vm[o] = Vn;
-            Rm[o] = Rn;
-            Pm[o] = make_float2(__builtin_fmaf(bf, P0.x, Rn.x), __builtin_fmaf(bf, P0.y, Rn.y));
+          if (own) {
+            const int i = t;
+            mu = Em[i * MST + i].x;
+            float off = 0.f, cii = 0.f;
+            for (int j = 0; j < U; ++j) {
+              const float2 bij = Em[i * MST + j], lij = Vm[i * MST + j];
+              if (j != i) off += cabs2(bij);
+              cii += bij.x * lij.x + bij.y * lij.y;       // Re(B_ij conj(L_ij))
+            }
+            nu2 = off * prm.es + cii * prm.n0;
           }
-          __syncthreads();
         }
-        // ---- B = L_K G (G = A - reg I off the diagonal; diagonal G_ii)
-        for (int idx = t; idx < UU; idx += kWave) {
-          const int i = idx / U, j = idx % U;
-          float2 x = make_float2(0.f, 0.f);
-          for (int l = 0; l < U; ++l) {
-            const float2 gl = (l == j) ? make_float2(Gs[j], 0.f) : As[l * AST + j];
-            cfma(x, Vm[i * MST + l], gl);
-          }
-          Em[i * MST + j] = x;
-        }
-        __syncthreads();
         if (own) {
           const int i = t;
-          const float mu = Em[i * MST + i].x;
-          float off = 0.f, cii = 0.f;
-          for (int j = 0; j < U; ++j) {
-            const float2 bij = Em[i * MST + j], lij = Vm[i * MST + j];
-            if (j != i) off += cabs2(bij);
-            cii += bij.x * lij.x + bij.y * lij.y;       // Re(B_ij conj(L_ij))
-          }
-          const float nu2 = off * prm.es + cii * prm.n0;
           float rho = (mu * mu) / nu2;
           float2 z;
           if (mu != 0.f) {
