@@ -143,7 +143,7 @@ def main():
     scalar = "f64" if wl.scalar_f64 else "f32"
     n0, es, beta, K, m = up.n0, up.es, dn.beta, wl.K, wl.m
 
-    def run_steps(Hx, Yx, steps, record=True):
+    def run_steps(Hx, Yx, steps):
         evs = []
         for _ in range(steps):
             e0 = torch.cuda.Event(enable_timing=True)
