@@ -40,6 +40,8 @@ def test_library_exports_every_declared_symbol():
 def test_header_constants_match_binding():
     src = open(HEADER).read()
     assert f"#define MIMO_MAX_USERS {L.MIMO_MAX_USERS}" in src
+    assert f"#define MIMO_MAX_ANTENNAS {L.MIMO_MAX_ANTENNAS}" in src
+    assert f"#define MIMO_MAX_BATCH {L.MIMO_MAX_BATCH}" in src
     for name in ("MIMO_C32", "MIMO_C16", "MIMO_CBF16", "MIMO_SINR_APPROX", "MIMO_SINR_EXACT",
                  "MIMO_SCALAR_F32", "MIMO_SCALAR_F64", "MIMO_OK", "MIMO_EINVAL",
                  "MIMO_EUNSUPPORTED", "MIMO_EWORKSPACE", "MIMO_EHIP"):
