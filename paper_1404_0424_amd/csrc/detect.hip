@@ -27,6 +27,14 @@ struct DetectStore {
     sinr = make_rsrc(p.sinr ? (const void*)(p.sinr + (size_t)n * per) : p.llr,
                      p.sinr ? per * 4u : 0u);
   }
+  // xhat, mu, sinr of entry e = u * S + s (or -1 for a masked lane)
+  __device__ void store_aux(int e, float2 x, float m, float rho) const {
+    const bool ok = e >= 0;
+    bstore2(xhat, ok ? (uint32_t)e * 8u : kOOB, x.x, x.y);
+    const uint32_t o4 = ok ? (uint32_t)e * 4u : kOOB;
+    bstore1(mu, o4, m);
+    bstore1(sinr, o4, rho);
+  }
   // entry e = u * S + s, or -1 for a masked lane
   __device__ void store(int e, const float (&out)[M_BITS], float2 x, float m, float rho) const {
     const bool ok = e >= 0;
@@ -60,11 +68,18 @@ constexpr bool kUncondMem = std::is_same<IN, InC32>::value || std::is_same<IN, I
 // rho (eq. (15)), z = xhat / mu and the LLRs (eq. (4)) of right-hand sides
 // s0 + 4 g + j of subcarrier n.  A^T, d and G_ii come from the Gram phase.
 // BUF: stores through buffer descriptors (no branches) or plain stores.
-template <int W, typename ST, int M_BITS, bool BUF>
+// STAGE (with BUF, all right-hand sides in this chunk): the subcarrier's LLR
+// tile, U x S x M_BITS floats contiguous in memory, is assembled in `stg`
+// (wave-private LDS, free once the CG is done) and written with one
+// contiguous 16-byte (or 8-byte) piece per lane, so every store instruction
+// covers whole cache lines; scattered 12-byte pieces let partly written lines
+// leave L2 under load and reach HBM more than once.
+template <int W, typename ST, int M_BITS, bool BUF, bool STAGE = false>
 __device__ __forceinline__ void cg_llr_epilogue(const DetectParams& prm, int64_t n, int s0,
                                                 const GramAcc<W>& acc, const AOperand<W>& at,
                                                 const float (&d)[W], const float* Gs,
-                                                float2* Ps, int c, int g) {
+                                                float2* Ps, int c, int g,
+                                                float* __restrict__ stg = nullptr) {
   const int U = prm.U, S = prm.S;
   float2 b[W][4];
 #pragma unroll
@@ -98,7 +113,14 @@ __device__ __forceinline__ void cg_llr_epilogue(const DetectParams& prm, int64_t
       const float2 z = make_float2(x.x * imu, x.y * imu);
       float out[M_BITS];
       llr_maxlog<M_BITS>(z, rho, prm.scale, prm.inv_scale, out);
-      if (BUF) {
+      if (STAGE) {
+        if (u < U && s < S) {
+          float* sp = stg + (u * S + s) * M_BITS;
+#pragma unroll
+          for (int q = 0; q < M_BITS; ++q) sp[q] = out[q];
+        }
+        os.store_aux((u < U && s < S) ? u * S + s : -1, x, mu, rho);
+      } else if (BUF) {
         os.store((u < U && s < S) ? u * S + s : -1, out, x, mu, rho);
       } else if (u < U && s < S) {
         const size_t idx = ((size_t)n * U + u) * S + s;
@@ -110,6 +132,25 @@ __device__ __forceinline__ void cg_llr_epilogue(const DetectParams& prm, int64_t
         if (prm.sinr) prm.sinr[idx] = rho;
       }
     }
+  }
+  if (STAGE) {
+    wave_lds_sync();
+    const int lane = 16 * g + c;
+    const int total = U * S * M_BITS;             // floats, even (M_BITS is even)
+    if ((total & 3) == 0) {                       // 16-byte aligned tile
+      const float4* src = (const float4*)stg;
+      for (int o = lane; o < total / 4; o += kWave) {
+        const float4 v = src[o];
+        bstore4(os.llr, (uint32_t)o * 16u, v.x, v.y, v.z, v.w);
+      }
+    } else {
+      const float2* src = (const float2*)stg;
+      for (int o = lane; o < total / 2; o += kWave) {
+        const float2 v = src[o];
+        bstore2(os.llr, (uint32_t)o * 8u, v.x, v.y);
+      }
+    }
+    wave_lds_sync();                              // stg is A / P of the next subcarrier
   }
 }
 
@@ -137,14 +178,16 @@ __global__ __launch_bounds__(256, 2) void detect_stream_kernel(DetectParams prm)
   using Sub = typename Storage<IN, W>::Sub;
   using Blk = typename std::conditional<SMALL, typename Storage<IN, W>::SmallBlock,
                                         typename Storage<IN, W>::Block>::type;
-  __shared__ __align__(16) float2 A_s[kWavesPerBlock][NU * AST];
-  __shared__ __align__(16) float2 P_s[kWavesPerBlock][NU * kPST];
+  // per wave: A then P (float2), reused as the LLR staging tile (complex64)
+  constexpr int AP = 2 * (NU * AST + NU * kPST);                     // floats
+  constexpr int STG = kUncondMem<IN> ? NU * 16 * M_BITS : 0;
+  __shared__ __align__(16) float W_s[kWavesPerBlock][AP > STG ? AP : STG];
   __shared__ float G_s[kWavesPerBlock][NU];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const int c = lane & 15, g = lane >> 4;
-  float2* As = A_s[wv];
-  float2* Ps = P_s[wv];
+  float2* As = (float2*)W_s[wv];
+  float2* Ps = As + NU * AST;
   float* Gs = G_s[wv];
   const int B = prm.B, U = prm.U, S = prm.S;
   const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
@@ -198,7 +241,8 @@ __global__ __launch_bounds__(256, 2) void detect_stream_kernel(DetectParams prm)
     AOperand<W> at;
     float d[W];
     gram_to_operands<W>(IN{}, acc, As, Gs, Ps, AST, prm.reg, U, c, g, at, d);
-    cg_llr_epilogue<W, ST, M_BITS, kUncondMem<IN>>(prm, n, 0, acc, at, d, Gs, Ps, c, g);
+    cg_llr_epilogue<W, ST, M_BITS, kUncondMem<IN>, kUncondMem<IN>>(prm, n, 0, acc, at, d, Gs,
+                                                                  Ps, c, g, W_s[wv]);
     n = nn;
     cur = nxt;
   }
