@@ -68,7 +68,7 @@ constexpr bool kUncondMem = std::is_same<IN, InC32>::value || std::is_same<IN, I
 // rho (eq. (15)), z = xhat / mu and the LLRs (eq. (4)) of right-hand sides
 // s0 + 4 g + j of subcarrier n.  A^T, d and G_ii come from the Gram phase.
 // BUF: stores through buffer descriptors (no branches) or plain stores.
-// STAGE (with BUF, all right-hand sides in this chunk): the subcarrier's LLR
+// STAGE (all right-hand sides in this chunk): the subcarrier's LLR
 // tile, U x S x M_BITS floats contiguous in memory, is assembled in `stg`
 // (wave-private LDS, free once the CG is done) and written with one
 // contiguous 16-byte (or 8-byte) piece per lane, so every store instruction
@@ -96,7 +96,7 @@ __device__ __forceinline__ void cg_llr_epilogue(const DetectParams& prm, int64_t
     tracker_step<W, ST>(tk, d, al, be);
   }
   DetectStore<M_BITS> os;
-  if (BUF) os.init(prm, n);
+  if (BUF || STAGE) os.init(prm, n);
 #pragma unroll
   for (int w = 0; w < W; ++w) {
     const int u = 16 * w + c;
@@ -178,9 +178,9 @@ __global__ __launch_bounds__(256, 2) void detect_stream_kernel(DetectParams prm)
   using Sub = typename Storage<IN, W>::Sub;
   using Blk = typename std::conditional<SMALL, typename Storage<IN, W>::SmallBlock,
                                         typename Storage<IN, W>::Block>::type;
-  // per wave: A then P (float2), reused as the LLR staging tile (complex64)
+  // per wave: A then P (float2), reused as the LLR staging tile
   constexpr int AP = 2 * (NU * AST + NU * kPST);                     // floats
-  constexpr int STG = kUncondMem<IN> ? NU * 16 * M_BITS : 0;
+  constexpr int STG = NU * 16 * M_BITS;
   __shared__ __align__(16) float W_s[kWavesPerBlock][AP > STG ? AP : STG];
   __shared__ float G_s[kWavesPerBlock][NU];
   const int lane = threadIdx.x & 63;
@@ -241,8 +241,8 @@ __global__ __launch_bounds__(256, 2) void detect_stream_kernel(DetectParams prm)
     AOperand<W> at;
     float d[W];
     gram_to_operands<W>(IN{}, acc, As, Gs, Ps, AST, prm.reg, U, c, g, at, d);
-    cg_llr_epilogue<W, ST, M_BITS, kUncondMem<IN>, kUncondMem<IN>>(prm, n, 0, acc, at, d, Gs,
-                                                                  Ps, c, g, W_s[wv]);
+    cg_llr_epilogue<W, ST, M_BITS, kUncondMem<IN>, true>(prm, n, 0, acc, at, d, Gs, Ps, c, g,
+                                                         W_s[wv]);
     n = nn;
     cur = nxt;
   }
