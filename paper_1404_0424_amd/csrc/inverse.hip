@@ -53,12 +53,19 @@ __device__ __forceinline__ void apply_inverse(InverseLds<W>& sm, const float2 (&
 // After the Gram phase of chunk s0 (acc: Gram tiles on the first chunk, the
 // matched filter b of rhs s0 .. s0 + 15): on the first chunk build X and the
 // per-user gain and SINR, then xhat = X b and the LLRs of the chunk.
-template <int W, int M_BITS, int METHOD>
+// STAGE (streaming form, one chunk): the subcarrier's LLR tile is assembled in
+// A, X and P (contiguous, dead once xhat is formed) and written in contiguous
+// pieces, as the CG detectors do, when it fits there.
+template <int W, int M_BITS, int METHOD, bool STAGE = false>
 __device__ __forceinline__ void detect_inverse_chunk(const DetectParams& prm, InverseLds<W>& sm,
                                                      int64_t n, int s0, const GramAcc<W>& acc,
                                                      int lane, int c, int g) {
   constexpr int AST = InverseLds<W>::AST;
+  constexpr int kStageFloats = 2 * (2 * InverseLds<W>::NU * AST + InverseLds<W>::NU * kPST);
   const int U = prm.U, S = prm.S;
+  const int total = U * S * M_BITS;                  // floats of the subcarrier's LLR tile
+  const bool stage = STAGE && total <= kStageFloats;
+  float* stg = (float*)sm.A;
   if (s0 == 0) {
     store_gram_lds<W>(acc, sm.A, sm.G, (float*)sm.P, AST, prm.reg, c, g);
     wave_lds_sync();
@@ -101,7 +108,7 @@ __device__ __forceinline__ void detect_inverse_chunk(const DetectParams& prm, In
                          out);
       if (u < U && s < S) {
         const size_t idx = ((size_t)n * U + u) * S + s;
-        float* lp = prm.llr + idx * M_BITS;
+        float* lp = stage ? stg + (u * S + s) * M_BITS : prm.llr + idx * M_BITS;
 #pragma unroll
         for (int q = 0; q < M_BITS; ++q) lp[q] = out[q];
         if (prm.xhat) prm.xhat[idx] = xx;
@@ -109,6 +116,24 @@ __device__ __forceinline__ void detect_inverse_chunk(const DetectParams& prm, In
         if (prm.sinr) prm.sinr[idx] = rho;
       }
     }
+  }
+  if (stage) {
+    wave_lds_sync();
+    const __amdgpu_buffer_rsrc_t rl = make_rsrc(prm.llr + (size_t)n * total, (uint32_t)total * 4u);
+    if ((total & 3) == 0) {
+      const float4* src = (const float4*)stg;
+      for (int o = lane; o < total / 4; o += kWave) {
+        const float4 v = src[o];
+        bstore4(rl, (uint32_t)o * 16u, v.x, v.y, v.z, v.w);
+      }
+    } else {
+      const float2* src = (const float2*)stg;
+      for (int o = lane; o < total / 2; o += kWave) {
+        const float2 v = src[o];
+        bstore2(rl, (uint32_t)o * 8u, v.x, v.y);
+      }
+    }
+    wave_lds_sync();
   }
 }
 
@@ -161,7 +186,10 @@ __global__ __launch_bounds__(64, W == 2 ? 1 : (METHOD == kInvCholesky ? 4 : 3)) 
     GramAcc<W> acc;
     acc.clear();
     gram_stream<W, true>(IN{}, blk, cur, nxt, B, acc);
-    detect_inverse_chunk<W, M_BITS, METHOD>(prm, sm, n, 0, acc, lane, c, g);
+    // staged LLR stores where they measured faster (Neumann); at 4 waves per
+    // SIMD they make the Cholesky kernel spill
+    detect_inverse_chunk<W, M_BITS, METHOD, METHOD == kInvNeumann>(prm, sm, n, 0, acc, lane, c,
+                                                                    g);
     n = nn;
     cur = nxt;
   }
