@@ -41,6 +41,8 @@ CASES = [
     ("ragged_80x20", 13, 80, 20, 3, 4, 5, 12.0, "iid"),
     ("single_user", 9, 6, 1, 2, 8, 1, 10.0, "iid"),
     ("square_16x16", 11, 16, 16, 5, 4, 2, 15.0, "iid"),
+    # U S m = 90, not a multiple of 4: the staged LLR tile is written in 8-byte pieces
+    ("odd_tile_40x5_S3", 29, 40, 5, 3, 6, 3, 12.0, "iid"),
 ]
 
 

@@ -50,6 +50,11 @@ DETECT_CASES = [
     ("square_16x16", 11, 16, 16, 5, 4, 4, 15.0, "iid"),
     # converges to round-off before K: exercises the zero-residual guard
     ("converged_16x16_0dB", 11, 16, 16, 5, 4, 16, 0.0, "iid"),
+    # U S m not a multiple of 4 (90 and 26 floats): the streaming kernels write the
+    # staged LLR tile in 8-byte pieces; one tile and two tiles
+    ("odd_tile_40x5_S3", 29, 40, 5, 3, 6, 4, 12.0, "iid"),
+    ("odd_tile_64x13_S1", 23, 64, 13, 1, 2, 3, 8.0, "iid"),
+    ("odd_tile_96x17_S3", 7, 96, 17, 3, 6, 4, 12.0, "iid"),
 ]
 
 
@@ -363,8 +368,10 @@ def test_bench_batches_sampled(wl, frames, dsched, psched):
 
 
 @pytest.mark.parametrize("case", [DETECT_CASES[4], DETECT_CASES[5], DETECT_CASES[7],
-                                  ("ragged_100x12_S9", 29, 100, 12, 9, 4, 4, 10.0, "iid")],
-                         ids=["mixed_128x16", "mixed_128x32", "ragged_30x5_S17", "ragged_100x12_S9"])
+                                  ("ragged_100x12_S9", 29, 100, 12, 9, 4, 4, 10.0, "iid"),
+                                  ("odd_tile_40x5_S3", 29, 40, 5, 3, 6, 4, 12.0, "iid")],
+                         ids=["mixed_128x16", "mixed_128x32", "ragged_30x5_S17", "ragged_100x12_S9",
+                              "odd_tile_40x5_S3"])
 def test_schedules_give_identical_results(case):
     """Every kernel variant and grid size computes the same per-system
     arithmetic in the same order: outputs are bitwise equal."""
