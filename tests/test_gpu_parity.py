@@ -88,6 +88,9 @@ EXACT_CASES = [
     ("u20_S17", 5, 40, 20, 17, 2, 6, 8.0, "iid"),
     ("u32_corr", 4, 128, 32, 3, 8, 6, 25.0, "kronecker"),
     ("square_16x16_KU", 6, 16, 16, 3, 4, 16, 15.0, "iid"),
+    # users short of the 16-wide MFMA tile (padding rows and columns), two rhs chunks
+    ("u5_S17", 9, 24, 5, 17, 4, 3, 10.0, "iid"),
+    ("u13_K5", 6, 48, 13, 4, 6, 5, 12.0, "iid"),
 ]
 
 
