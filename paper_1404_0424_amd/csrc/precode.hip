@@ -148,7 +148,7 @@ __global__ __launch_bounds__(256, 2) void precode_stream_kernel(PrecodeParams pr
       ST al[4], be[4];
       cg_step<W, ST>(st, at, Ps, c, g, al, be);
     }
-    precode_store<W, IN, ST>(prm, n, 0, Hn, st.v, at, Ps, Ns, c, g);
+    precode_store<W, IN, ST>(prm, n, 0, Hn, st.v, at, Ps, Ns, c, g, As);
     wave_lds_sync();
     n = nn;
     cur = nxt;

@@ -57,12 +57,15 @@ __device__ __forceinline__ void load_h_row(IN tag, const void* Hn, int B, int U,
 }
 
 // Q[n][:, s0 .. s0+15] and qnorm from v (lane layout, ST-precision norms).
-// `at` is the A^T operand of A = G + beta I.
+// `at` is the A^T operand of A = G + beta I.  With `Qs` (wave-private LDS of
+// at least 16 x 16 complex, free during the output stage) and S <= 16, each
+// 16-antenna output tile, contiguous in memory, is staged there and written
+// with contiguous 8-byte pieces, whole cache lines per store instruction.
 template <int W, typename IN, typename ST>
 __device__ __forceinline__ void precode_store(const PrecodeParams& prm, int64_t n, int s0,
                                               const void* Hn, const float2 (&vsol)[W][4],
                                               const AOperand<W>& at, float2* Ps, float* Ns,
-                                              int c, int g) {
+                                              int c, int g, float2* Qs = nullptr) {
   const int B = prm.B, U = prm.U, S = prm.S;
   const float beta = prm.beta;
     // ---- ||q||^2 = v^H G v ; V stays staged in Ps for the output contraction
@@ -89,6 +92,7 @@ __device__ __forceinline__ void precode_store(const PrecodeParams& prm, int64_t 
     // 16 w + 4 t + g; v is zero on padding users, so k-steps past U are
     // skipped).
     const int s = s0 + c;
+    const bool stage = Qs != nullptr && S <= 16;
     const float nrm2 = Ns[c];
     const float scl = prm.normalize ? (nrm2 > 0.f ? __builtin_amdgcn_rsqf(nrm2) : 0.f) : 1.0f;
     float2 vv[W][4];
@@ -128,7 +132,23 @@ __device__ __forceinline__ void precode_store(const PrecodeParams& prm, int64_t 
       }
       const f4 qr = p1 - p2;
       const f4 qi = p3 - p1 - p2;
-      if (s < S) {
+      if (stage) {
+        if (s < S) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) Qs[(4 * g + j) * S + s] = make_float2(qr[j] * scl, qi[j] * scl);
+        }
+        wave_lds_sync();
+        const int rows = B - b0 < 16 ? B - b0 : 16;
+        const __amdgpu_buffer_rsrc_t rq =
+            make_rsrc(prm.Q + ((size_t)n * B + b0) * S, (uint32_t)(rows * S) * 8u);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int e = 64 * r + 16 * g + c;
+          const float2 q = Qs[e < 16 * S ? e : 0];
+          bstore2(rq, e < rows * S ? (uint32_t)e * 8u : kOOB, q.x, q.y);
+        }
+        wave_lds_sync();
+      } else if (s < S) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int bb = b0 + 4 * g + j;
