@@ -251,8 +251,10 @@ __global__ __launch_bounds__(256, 2) void detect_stream_kernel(DetectParams prm)
 // All right-hand sides of subcarrier n, in chunks of 16; the Gram is
 // computed with the first chunk and kept in LDS.
 template <int W, typename IN, typename ST, int M_BITS>
+// With all right-hand sides in one chunk (S <= 16) the LLR tile is staged in
+// `stg` (A and P of the wave, contiguous, at least 16 W x 16 x M_BITS floats).
 __device__ __forceinline__ void detect_one(const DetectParams& prm, int64_t n, float2* As,
-                                           float2* Ps, float* Gs, int c, int g) {
+                                           float2* Ps, float* Gs, int c, int g, float* stg) {
   constexpr int AST = 16 * W + 2;
   const int B = prm.B, U = prm.U, S = prm.S;
   const void* Hn = offset_sc(IN{}, prm.H, n, B, U);
@@ -268,7 +270,11 @@ __device__ __forceinline__ void detect_one(const DetectParams& prm, int64_t n, f
     } else {
       gram_mf<W, false, true>(IN{}, Hn, Yn, B, U, S, s0, c, g, acc);
     }
-    cg_llr_epilogue<W, ST, M_BITS, kUncondMem<IN>>(prm, n, s0, acc, at, d, Gs, Ps, c, g);
+    if (S <= 16)
+      cg_llr_epilogue<W, ST, M_BITS, kUncondMem<IN>, true>(prm, n, s0, acc, at, d, Gs, Ps, c, g,
+                                                           stg);
+    else
+      cg_llr_epilogue<W, ST, M_BITS, kUncondMem<IN>>(prm, n, s0, acc, at, d, Gs, Ps, c, g);
   }
 }
 
@@ -277,15 +283,19 @@ template <int W, typename IN, typename ST, int M_BITS>
 __global__ __launch_bounds__(256, 2) void detect_approx_kernel(DetectParams prm) {
   constexpr int NU = 16 * W;
   constexpr int AST = NU + 2;   // LDS row stride (complex) of A
-  __shared__ __align__(16) float2 A_s[kWavesPerBlock][NU * AST];
-  __shared__ __align__(16) float2 P_s[kWavesPerBlock][NU * kPST];
+  // per wave: A then P (float2), reused as the LLR staging tile
+  constexpr int AP = 2 * (NU * AST + NU * kPST);                     // floats
+  constexpr int STG = NU * 16 * M_BITS;
+  __shared__ __align__(16) float W_s[kWavesPerBlock][AP > STG ? AP : STG];
   __shared__ float G_s[kWavesPerBlock][NU];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const int c = lane & 15, g = lane >> 4;
+  float2* As = (float2*)W_s[wv];
+  float2* Ps = As + NU * AST;
   for (int64_t n = (int64_t)blockIdx.x * kWavesPerBlock + wv; n < prm.n_sc;
        n += (int64_t)gridDim.x * kWavesPerBlock)
-    detect_one<W, IN, ST, M_BITS>(prm, n, A_s[wv], P_s[wv], G_s[wv], c, g);
+    detect_one<W, IN, ST, M_BITS>(prm, n, As, Ps, G_s[wv], c, g, W_s[wv]);
 }
 
 // Batched kernel: frames of different shapes (same user class, QAM order,
@@ -296,12 +306,16 @@ template <int W, typename IN, typename ST, int M_BITS>
 __global__ __launch_bounds__(256, 2) void detect_batch_kernel(BatchArgs args) {
   constexpr int NU = 16 * W;
   constexpr int AST = NU + 2;
-  __shared__ __align__(16) float2 A_s[kWavesPerBlock][NU * AST];
-  __shared__ __align__(16) float2 P_s[kWavesPerBlock][NU * kPST];
+  // per wave: A then P (float2), reused as the LLR staging tile
+  constexpr int AP = 2 * (NU * AST + NU * kPST);                     // floats
+  constexpr int STG = NU * 16 * M_BITS;
+  __shared__ __align__(16) float W_s[kWavesPerBlock][AP > STG ? AP : STG];
   __shared__ float G_s[kWavesPerBlock][NU];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const int c = lane & 15, g = lane >> 4;
+  float2* As = (float2*)W_s[wv];
+  float2* Ps = As + NU * AST;
   for (int64_t gsc = (int64_t)blockIdx.x * kWavesPerBlock + wv; gsc < args.total;
        gsc += (int64_t)gridDim.x * kWavesPerBlock) {
     const int f = find_frame(args, gsc);
@@ -310,12 +324,12 @@ __global__ __launch_bounds__(256, 2) void detect_batch_kernel(BatchArgs args) {
                      F.inv_scale, (float*)F.out, (float2*)F.out2, nullptr, nullptr};
     if constexpr (std::is_same<IN, InC32>::value) {
       if (F.U <= 8) {               // packed form, as a single call of this frame runs
-        detect_one<1, InC32P, ST, M_BITS>(prm, gsc - F.sc_begin, A_s[wv], P_s[wv], G_s[wv], c,
-                                          g);
+        detect_one<1, InC32P, ST, M_BITS>(prm, gsc - F.sc_begin, As, Ps, G_s[wv], c, g,
+                                          W_s[wv]);
         continue;
       }
     }
-    detect_one<W, IN, ST, M_BITS>(prm, gsc - F.sc_begin, A_s[wv], P_s[wv], G_s[wv], c, g);
+    detect_one<W, IN, ST, M_BITS>(prm, gsc - F.sc_begin, As, Ps, G_s[wv], c, g, W_s[wv]);
   }
 }
 
