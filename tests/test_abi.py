@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -194,3 +195,33 @@ def test_batch_validation():
     assert lib.mimo_detect_cg_batch(ctypes.addressof(fr), 0, 0, 4, 0, None) == L.MIMO_OK
     fr[0] = L.MimoFrame(4, 32, 8, 2, 3, P, P, P2, None, 0.0, 0.0, -1.0, 1)   # bad beta
     assert lib.mimo_precode_cg_batch(ctypes.addressof(fr), 1, 0, 0, None) == L.MIMO_EINVAL
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built library every entry point raises; nothing falls back
+    to a CPU computation."""
+    from paper_1404_0424_amd import api
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "absent.so"))
+    monkeypatch.setattr(L, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        api.workspace_bytes(128, 16, 14, 4, 1200)
+    with pytest.raises(RuntimeError, match="missing"):
+        L.lib()
+
+
+def test_product_package_does_not_import_the_oracle():
+    """The oracle is test infrastructure: no module of the package imports it,
+    and importing the package loads no oracle module."""
+    pkg = os.path.join(ROOT, "paper_1404_0424_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith(".py"):
+                src = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(from|import)\s+oracle\b", src, re.M), f
+    code = ("import sys, paper_1404_0424_amd, paper_1404_0424_amd.api, "
+            "paper_1404_0424_amd.serving, paper_1404_0424_amd.autotune; "
+            "print(any(m == 'oracle' or m.startswith('oracle.') for m in sys.modules))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         timeout=120)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "False"
