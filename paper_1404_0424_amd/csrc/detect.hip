@@ -30,10 +30,10 @@ struct DetectStore {
   // xhat, mu, sinr of entry e = u * S + s (or -1 for a masked lane)
   __device__ void store_aux(int e, float2 x, float m, float rho) const {
     const bool ok = e >= 0;
-    bstore2(xhat, ok ? (uint32_t)e * 8u : kOOB, x.x, x.y);
+    bstore2<0>(xhat, ok ? (uint32_t)e * 8u : kOOB, x.x, x.y);
     const uint32_t o4 = ok ? (uint32_t)e * 4u : kOOB;
-    bstore1(mu, o4, m);
-    bstore1(sinr, o4, rho);
+    bstore1<0>(mu, o4, m);
+    bstore1<0>(sinr, o4, rho);
   }
   // entry e = u * S + s, or -1 for a masked lane
   __device__ void store(int e, const float (&out)[M_BITS], float2 x, float m, float rho) const {
@@ -50,10 +50,10 @@ struct DetectStore {
       bstore4(llr, ol, out[0], out[1], out[2], out[3]);
       bstore4(llr, ol + 16u, out[4], out[5], out[6], out[7]);
     }
-    bstore2(xhat, ok ? (uint32_t)e * 8u : kOOB, x.x, x.y);
+    bstore2<0>(xhat, ok ? (uint32_t)e * 8u : kOOB, x.x, x.y);
     const uint32_t o4 = ok ? (uint32_t)e * 4u : kOOB;
-    bstore1(mu, o4, m);
-    bstore1(sinr, o4, rho);
+    bstore1<0>(mu, o4, m);
+    bstore1<0>(sinr, o4, rho);
   }
 };
 

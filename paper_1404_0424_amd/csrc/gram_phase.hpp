@@ -65,13 +65,17 @@ __device__ __forceinline__ uint4 bload4(__amdgpu_buffer_rsrc_t r, uint32_t voff,
 typedef unsigned int u2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u3 __attribute__((ext_vector_type(3)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+// (CPOL 0, the default policy, suits outputs written in scattered 4- or 8-byte
+// pieces: there L2 merges the pieces into whole lines before they leave.)
+template <int CPOL = kStreamCPol>
 __device__ __forceinline__ void bstore1(__amdgpu_buffer_rsrc_t r, uint32_t voff, float a) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, a), r, voff, 0, kStreamCPol);
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, a), r, voff, 0, CPOL);
 }
+template <int CPOL = kStreamCPol>
 __device__ __forceinline__ void bstore2(__amdgpu_buffer_rsrc_t r, uint32_t voff, float a,
                                         float b) {
   const u2 v = {__builtin_bit_cast(unsigned int, a), __builtin_bit_cast(unsigned int, b)};
-  __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, 0, kStreamCPol);
+  __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, 0, CPOL);
 }
 // ... with a wave-uniform part of the offset in soffset (range-checked too)
 __device__ __forceinline__ void bstore2s(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
