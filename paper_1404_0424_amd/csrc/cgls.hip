@@ -15,6 +15,9 @@
 // k-steps of a tile run over j), so antenna-length vectors never move
 // between lanes; they live in lane-private LDS slots.  Per-rhs step sizes
 // cross between the layouts through a 16-entry LDS array.
+// H is read twice per launch here (or once per iteration): keep its lines in
+// the caches (default policy for every buffer access).
+#define MIMO_CACHE_STREAMING 0
 #include "cg_core.hpp"
 #include "gram_phase.hpp"
 #include "launch.hpp"

@@ -44,13 +44,20 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint3
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
                                            0x00020000);
 }
-// Cache policy of every buffer load and store below: non-temporal (the nt
-// bit, value 2 of the builtins' aux operand on gfx950).  Each byte of H, Y, T
-// and of the outputs crosses the memory system once per launch, so marking the
-// lines as streaming keeps them from displacing each other in L2 and the
-// Infinity Cache; it changes no value (detection measured 147-149 us -> 136-138
-// us per launch on the 128x16 batch of 19,200 subcarriers).
-constexpr int kStreamCPol = 2;
+// Cache policy of the buffer loads and stores below.  Where a kernel reads
+// each byte of H, Y (and writes each output byte) once per launch, the
+// non-temporal policy (the nt bit, value 2 of the builtins' aux operand on
+// gfx950) marks the lines as streaming so they stop displacing one another in
+// L2 and the Infinity Cache; it changes no value (detection measured 147-149 us
+// -> 136-138 us per launch on the 128x16 batch of 19,200 subcarriers).  Kernels
+// that read H a second time (the streaming precoders, the inverse-based and
+// CGLS methods) want those lines kept: their translation units define
+// MIMO_CACHE_STREAMING 0 before including this header and get the default
+// policy (each unit is compiled to its own device code object).
+#ifndef MIMO_CACHE_STREAMING
+#define MIMO_CACHE_STREAMING 1
+#endif
+constexpr int kStreamCPol = MIMO_CACHE_STREAMING ? 2 : 0;
 
 __device__ __forceinline__ float2 bload2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
   return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, kStreamCPol));

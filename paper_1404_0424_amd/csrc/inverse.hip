@@ -5,6 +5,9 @@
 // and matched filter on MFMA as in CG-D, the explicit (approximate) inverse
 // X of A in LDS, then xhat = X b on MFMA with the soft output of the linear
 // detector W = X H^H (eqs. (2)-(4)), or v = X t and q = H_u v (eq. (5)).
+// H is read twice per launch here (or once per iteration): keep its lines in
+// the caches (default policy for every buffer access).
+#define MIMO_CACHE_STREAMING 0
 #include "gram_stream.hpp"
 #include "inverse.hpp"
 #include "launch.hpp"

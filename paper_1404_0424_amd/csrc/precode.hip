@@ -8,6 +8,9 @@
 // once, already scaled.
 #include <type_traits>
 
+// H is read twice per launch here (or once per iteration): keep its lines in
+// the caches (default policy for every buffer access).
+#define MIMO_CACHE_STREAMING 0
 #include "launch.hpp"
 #include "precode_out.hpp"
 
