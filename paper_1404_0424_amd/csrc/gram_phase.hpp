@@ -53,17 +53,20 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint3
 // that read H a second time (the streaming precoders, the inverse-based and
 // CGLS methods) want those lines kept: their translation units define
 // MIMO_CACHE_STREAMING 0 before including this header and get the default
-// policy (each unit is compiled to its own device code object).
+// policy (each unit is compiled to its own device code object); a kernel there
+// that reads H once passes the policy to the block loads explicitly.
 #ifndef MIMO_CACHE_STREAMING
 #define MIMO_CACHE_STREAMING 1
 #endif
 constexpr int kStreamCPol = MIMO_CACHE_STREAMING ? 2 : 0;
 
+template <int CPOL = kStreamCPol>
 __device__ __forceinline__ float2 bload2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, kStreamCPol));
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, CPOL));
 }
+template <int CPOL = kStreamCPol>
 __device__ __forceinline__ uint4 bload4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, kStreamCPol));
+  return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, CPOL));
 }
 
 // Buffer stores: an offset outside the descriptor's range (kOOB, or any
@@ -163,14 +166,14 @@ struct BlockC32 {
   static constexpr int ANT = 4 * UNR;  // antennas per block
   float2 h[UNR][W];
   float2 y[UNR];
-  template <bool DO_MF>
+  template <bool DO_MF, int CPOL = kStreamCPol>
   __device__ __forceinline__ void load(const SubC32<W>& sb, int b0) {
 #pragma unroll
     for (int t = 0; t < UNR; ++t) {
       const int b = b0 + 4 * t;
 #pragma unroll
-      for (int w = 0; w < W; ++w) h[t][w] = bload2(sb.rh, sb.oh[w], (uint32_t)b * sb.U * 8u);
-      if (DO_MF) y[t] = bload2(sb.ry, sb.oy, (uint32_t)b * sb.S * 8u);
+      for (int w = 0; w < W; ++w) h[t][w] = bload2<CPOL>(sb.rh, sb.oh[w], (uint32_t)b * sb.U * 8u);
+      if (DO_MF) y[t] = bload2<CPOL>(sb.ry, sb.oy, (uint32_t)b * sb.S * 8u);
     }
   }
   template <bool DO_GRAM, bool DO_MF>
@@ -295,19 +298,19 @@ template <int W, typename V8, int UNR = 2>
 struct Block16 {
   static constexpr int ANT = 32 * UNR;
   V8 hr[UNR][W], hi[UNR][W], yr[UNR], yi[UNR];
-  template <bool DO_MF>
+  template <bool DO_MF, int CPOL = kStreamCPol>
   __device__ __forceinline__ void load(const Sub16<W>& sb, int b0) {
 #pragma unroll
     for (int t = 0; t < UNR; ++t) {
       const uint32_t kb = (uint32_t)((b0 >> 3) + 4 * t);     // first 8-antenna block of the step
 #pragma unroll
       for (int w = 0; w < W; ++w) {
-        hr[t][w] = __builtin_bit_cast(V8, bload4(sb.rh, sb.oh[w], kb * 2u * sb.U * 16u));
-        hi[t][w] = __builtin_bit_cast(V8, bload4(sb.rh, sb.oh[w], (kb * 2u + 1u) * sb.U * 16u));
+        hr[t][w] = __builtin_bit_cast(V8, bload4<CPOL>(sb.rh, sb.oh[w], kb * 2u * sb.U * 16u));
+        hi[t][w] = __builtin_bit_cast(V8, bload4<CPOL>(sb.rh, sb.oh[w], (kb * 2u + 1u) * sb.U * 16u));
       }
       if (DO_MF) {
-        yr[t] = __builtin_bit_cast(V8, bload4(sb.ry, sb.oy, kb * 2u * sb.S * 16u));
-        yi[t] = __builtin_bit_cast(V8, bload4(sb.ry, sb.oy, (kb * 2u + 1u) * sb.S * 16u));
+        yr[t] = __builtin_bit_cast(V8, bload4<CPOL>(sb.ry, sb.oy, kb * 2u * sb.S * 16u));
+        yi[t] = __builtin_bit_cast(V8, bload4<CPOL>(sb.ry, sb.oy, (kb * 2u + 1u) * sb.S * 16u));
       }
     }
   }

@@ -218,6 +218,11 @@ __device__ __forceinline__ void stage_h_tile(const Block16<1, V8, 1> (&hb)[NK], 
   }
 }
 
+// The resident kernel reads each byte of H once per launch (it keeps the
+// subcarrier's channel in registers for q = H v): its loads of H take the
+// non-temporal policy (nt) that the streaming precoders of this unit do not.
+constexpr int kOnceCPol = 2;
+
 // Occupancy the register budget is sized for: 3 waves per SIMD (H takes 64
 // VGPRs at B = 128 in complex64, 32 in 16-bit storage, where 4 waves would
 // spill), 2 with FP64 scalars.
@@ -260,7 +265,7 @@ __global__ __launch_bounds__(256, resident_min_blocks<ST>()) void precode_reside
     Sub cur;
     cur.init(offset_sc(IN{}, prm.H, n, B, U), nullptr, B, U, S, 0, c, g);
 #pragma unroll
-    for (int t = 0; t < NK; ++t) hb[t].template load<false>(cur, t * RB::ANT);
+    for (int t = 0; t < NK; ++t) hb[t].template load<false, kOnceCPol>(cur, t * RB::ANT);
   }
   while (n < prm.n_sc) {
     const int64_t nn = n + stride;
@@ -326,7 +331,7 @@ __global__ __launch_bounds__(256, resident_min_blocks<ST>()) void precode_reside
     stage_h_tile(hb, 0, H2, c, g);
     if (C32) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t) hb[t].template load<false>(nxt, t * RB::ANT);
+      for (int t = 0; t < 4; ++t) hb[t].template load<false, kOnceCPol>(nxt, t * RB::ANT);
     }
 #pragma unroll
     for (int i = 0; i < BMAX / 16; ++i) {
@@ -372,10 +377,10 @@ __global__ __launch_bounds__(256, resident_min_blocks<ST>()) void precode_reside
         if (i + 1 < BMAX / 16) {
 #pragma unroll
           for (int t = 4 * (i + 1); t < 4 * (i + 1) + 4; ++t)
-            hb[t].template load<false>(nxt, t * RB::ANT);
+            hb[t].template load<false, kOnceCPol>(nxt, t * RB::ANT);
         }
       } else if (i & 1) {
-        hb[i >> 1].template load<false>(nxt, (i >> 1) * RB::ANT);
+        hb[i >> 1].template load<false, kOnceCPol>(nxt, (i >> 1) * RB::ANT);
       }
     }
     {
