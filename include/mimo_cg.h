@@ -48,11 +48,16 @@ extern "C" {
 
 #define MIMO_MAX_USERS 32   /* largest U supported */
 #define MIMO_MAX_ANTENNAS 4096
+/* Bound on one subcarrier's arrays: S * 8 * max(B, 4 U) bytes must be below
+ * this (2^31), i.e. Y and Q (8 B S bytes) and the LLRs (up to 32 U S bytes)
+ * of a subcarrier; larger S returns MIMO_EUNSUPPORTED. */
+#define MIMO_MAX_SPAN_BYTES 2147483648LL
 
 typedef struct mimo_shape {
   int32_t B;     /* base-station antennas, U <= B <= MIMO_MAX_ANTENNAS */
   int32_t U;     /* single-antenna users, 1 <= U <= MIMO_MAX_USERS */
-  int32_t S;     /* right-hand sides per subcarrier (OFDM symbols), >= 1 */
+  int32_t S;     /* right-hand sides per subcarrier (OFDM symbols), >= 1,
+                    S * 8 * max(B, 4 U) < MIMO_MAX_SPAN_BYTES */
   int32_t K;     /* CG iterations (Algorithm 1), 1 <= K <= 1024 */
   int64_t n_sc;  /* independent subcarrier systems, >= 0 (0 = no-op) */
 } mimo_shape;

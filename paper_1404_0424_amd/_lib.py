@@ -18,6 +18,7 @@ MIMO_OP_GRAM_MF, MIMO_OP_DETECT, MIMO_OP_PRECODE = 0, 1, 2
 MIMO_OK, MIMO_EINVAL, MIMO_EUNSUPPORTED, MIMO_EWORKSPACE, MIMO_EHIP = 0, -1, -2, -3, -4
 MIMO_MAX_USERS = 32
 MIMO_MAX_ANTENNAS = 4096
+MIMO_MAX_SPAN_BYTES = 1 << 31
 
 
 class MimoShape(ctypes.Structure):

@@ -39,6 +39,15 @@ int check_shape(const mimo_shape* s, bool need_k) {
   if (s->B > MIMO_MAX_ANTENNAS)
     return fail(MIMO_EUNSUPPORTED, "B=%d > %d", s->B, MIMO_MAX_ANTENNAS);
   if (s->S < 1) return fail(MIMO_EINVAL, "S=%d < 1", s->S);
+  // Kernels address one subcarrier's arrays through buffer descriptors with
+  // 32-bit byte offsets, and mark masked lanes with the offset 2^31: every
+  // per-subcarrier byte range (Y and Q: 8 B S, LLRs up to 32 U S) must stay
+  // below 2^31.
+  const int64_t per_rhs = 8 * (int64_t)(s->B > 4 * s->U ? s->B : 4 * s->U);
+  if ((int64_t)s->S * per_rhs >= MIMO_MAX_SPAN_BYTES)
+    return fail(MIMO_EUNSUPPORTED, "S=%d too large for B=%d, U=%d (per-subcarrier arrays of "
+                "%lld bytes; the limit is %lld)", s->S, s->B, s->U,
+                (long long)((int64_t)s->S * per_rhs), (long long)MIMO_MAX_SPAN_BYTES);
   if (s->n_sc < 0) return fail(MIMO_EINVAL, "n_sc=%lld < 0", (long long)s->n_sc);
   if (need_k && (s->K < 1 || s->K > 1024)) return fail(MIMO_EINVAL, "K=%d outside [1, 1024]", s->K);
   return MIMO_OK;

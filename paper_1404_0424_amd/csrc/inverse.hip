@@ -211,8 +211,8 @@ __device__ __forceinline__ void precode_inverse_chunk(const PrecodeParams& prm,
     store_gram_lds<W>(*acc, sm.A, sm.G, (float*)sm.P, AST, prm.beta, c, g);
     wave_lds_sync();
     build_inverse<W, METHOD>(sm, U, prm.K, lane, c, g);
-    // A operand for ||q||^2 = v^H A v - beta ||v||^2 (the padding
-    // diagonal differs from A's but meets only zero entries of v)
+    // A operand for ||q||^2 = v^H G v (the output stage puts the raw
+    // diagonal sm.G in place of A's)
     at.load(sm.A, AST, c, g, 16 * W);
   }
   float2 t[W][4], v[W][4];
@@ -224,8 +224,8 @@ __device__ __forceinline__ void precode_inverse_chunk(const PrecodeParams& prm,
       t[w][j] = (u < U && s < S) ? prm.T[((size_t)n * U + u) * S + s] : make_float2(0.f, 0.f);
     }
   apply_inverse<W>(sm, t, c, g, v);                      // v = X t
-  precode_store<W, IN, float>(prm, n, s0, offset_sc(IN{}, prm.H, n, B, U), v, at, sm.P, sm.N,
-                              c, g);
+  precode_store<W, IN, float>(prm, n, s0, offset_sc(IN{}, prm.H, n, B, U), v, at, sm.G, sm.P,
+                              sm.N, c, g);
   wave_lds_sync();
 }
 

@@ -4,8 +4,7 @@
 // subcarrier.
 //
 // ||q||^2 = v^H H^H H v = v^H G v is formed in the CG layout from one more
-// mat-vec with A (v^H A v - beta ||v||^2), so each output tile is written
-// once, already scaled.
+// mat-vec (with G), so each output tile is written once, already scaled.
 #include <type_traits>
 
 // H is read twice per launch here (or once per iteration): keep its lines in
@@ -53,7 +52,7 @@ __device__ __forceinline__ void precode_one(const PrecodeParams& prm, int64_t n,
       cg_step<W, ST>(st, at, Ps, c, g, al, be);
     }
 
-    precode_store<W, IN, ST>(prm, n, s0, Hn, st.v, at, Ps, Ns, c, g);
+    precode_store<W, IN, ST>(prm, n, s0, Hn, st.v, at, Gs, Ps, Ns, c, g);
     wave_lds_sync();
   }
 }
@@ -151,7 +150,7 @@ __global__ __launch_bounds__(256, 2) void precode_stream_kernel(PrecodeParams pr
       ST al[4], be[4];
       cg_step<W, ST>(st, at, Ps, c, g, al, be);
     }
-    precode_store<W, IN, ST>(prm, n, 0, Hn, st.v, at, Ps, Ns, c, g, As);
+    precode_store<W, IN, ST>(prm, n, 0, Hn, st.v, at, Gs, Ps, Ns, c, g, As);
     wave_lds_sync();
     n = nn;
     cur = nxt;
@@ -292,23 +291,10 @@ __global__ __launch_bounds__(256, resident_min_blocks<ST>()) void precode_reside
       cg_step<1, ST>(st, at, Ps, c, g, al, be);
     }
 
-    // ---- ||q||^2 = v^H G v = v^H A v - beta ||v||^2 (V stays staged in Ps)
-    const float beta = prm.beta;
+    // ---- ||q||^2 = v^H G v (V stays staged in Ps)
     stage_vec<1>(Ps, c, g, st.v);
     wave_lds_sync();
-    {
-      float2 e[1][4];
-      matvec_mfma<1>(at, Ps, c, g, e);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const float2 v = st.v[0][j];
-        ST part = ST(0);
-        part += (ST)v.x * (ST)e[0][j].x + (ST)v.y * (ST)e[0][j].y -
-                (ST)beta * ((ST)v.x * (ST)v.x + (ST)v.y * (ST)v.y);
-        const ST qq = row_sum16(part);
-        if (c == 0) Ns[4 * g + j] = (float)(qq > ST(0) ? qq : ST(0));
-      }
-    }
+    qnorm2_lds<1, ST>(at, Gs, st.v, Ps, Ns, c, g);
     wave_lds_sync();
 
     // ---- q = H_u v on MFMA with H from registers: P1 = Hr Vr, P2 = Hi Vi,

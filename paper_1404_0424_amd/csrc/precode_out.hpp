@@ -1,8 +1,8 @@
 // Output stage of the precoders (Sec. III-D, Algorithm 1 output): given
 // the solution v of (H_d H_d^H + beta I) v = t in the CG lane layout, form
-// ||q||^2 = v^H G v = v^H A v - beta ||v||^2 from one mat-vec with A, then
-// q = H_d^H v = H_u v on MFMA with the optional power normalization
-// s = q / ||q|| (Sec. II-B), each output tile written once, already scaled.
+// ||q||^2 = v^H G v from one mat-vec with G, then q = H_d^H v = H_u v on
+// MFMA with the optional power normalization s = q / ||q|| (Sec. II-B), each
+// output tile written once, already scaled.
 #pragma once
 
 #include "cg_core.hpp"
@@ -57,34 +57,54 @@ __device__ __forceinline__ void load_h_row(IN tag, const void* Hn, int B, int U,
 }
 
 // Q[n][:, s0 .. s0+15] and qnorm from v (lane layout, ST-precision norms).
-// `at` is the A^T operand of A = G + beta I.  With `Qs` (wave-private LDS of
+// `at` is the A^T operand of A = G + beta I, Gd the raw diagonal G_uu.  With `Qs` (wave-private LDS of
 // at least 16 x 16 complex, free during the output stage) and S <= 16, each
 // 16-antenna output tile, contiguous in memory, is staged there and written
 // with contiguous 8-byte pieces, whole cache lines per store instruction.
+// ||q_s||^2 = v_s^H G v_s for the lane layout's 16 right-hand sides into
+// Ns[0..15] (V staged in Ps).  The mat-vec runs on the A^T operand with its
+// diagonal entries A_uu = G_uu + beta replaced by the raw G_uu (Gd), so beta
+// never enters the sum: v^H A v - beta ||v||^2 would cancel as beta grows
+// (at low SNR), leaving the FP32 rounding of A v at magnitude beta |v|.
+template <int W, typename ST>
+__device__ __forceinline__ void qnorm2_lds(const AOperand<W>& at, const float* Gd,
+                                           const float2 (&vsol)[W][4],
+                                           const float2* __restrict__ Ps, float* Ns, int c,
+                                           int g) {
+  AOperand<W> gt = at;
+#pragma unroll
+  for (int wc = 0; wc < W; ++wc) {
+    const float gd = Gd[16 * wc + c];
+#pragma unroll
+    for (int t = 0; t < 4 * W; ++t)
+      if (16 * wc + c == 4 * t + g) gt.a[wc][t] = make_float2(gd, 0.f);
+  }
+  float2 e[W][4];
+  matvec_mfma<W>(gt, Ps, c, g, e);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    ST part = ST(0);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const float2 v = vsol[w][j];
+      part += (ST)v.x * (ST)e[w][j].x + (ST)v.y * (ST)e[w][j].y;
+    }
+    const ST qq = row_sum16(part);
+    if (c == 0) Ns[4 * g + j] = (float)(qq > ST(0) ? qq : ST(0));
+  }
+}
+
 template <int W, typename IN, typename ST>
 __device__ __forceinline__ void precode_store(const PrecodeParams& prm, int64_t n, int s0,
                                               const void* Hn, const float2 (&vsol)[W][4],
-                                              const AOperand<W>& at, float2* Ps, float* Ns,
-                                              int c, int g, float2* Qs = nullptr) {
+                                              const AOperand<W>& at, const float* Gd,
+                                              float2* Ps, float* Ns, int c, int g,
+                                              float2* Qs = nullptr) {
   const int B = prm.B, U = prm.U, S = prm.S;
-  const float beta = prm.beta;
     // ---- ||q||^2 = v^H G v ; V stays staged in Ps for the output contraction
     stage_vec<W>(Ps, c, g, vsol);
     wave_lds_sync();
-    float2 e[W][4];
-    matvec_mfma<W>(at, Ps, c, g, e);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      ST part = ST(0);
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        const float2 v = vsol[w][j];
-        part += (ST)v.x * (ST)e[w][j].x + (ST)v.y * (ST)e[w][j].y -
-                (ST)beta * ((ST)v.x * (ST)v.x + (ST)v.y * (ST)v.y);
-      }
-      const ST qq = row_sum16(part);
-      if (c == 0) Ns[4 * g + j] = (float)(qq > ST(0) ? qq : ST(0));
-    }
+    qnorm2_lds<W, ST>(at, Gd, vsol, Ps, Ns, c, g);
     wave_lds_sync();
 
     // ---- q = H_u v (Algorithm 1 output) on MFMA: rows = antennas,

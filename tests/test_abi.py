@@ -43,6 +43,8 @@ def test_header_constants_match_binding():
     assert f"#define MIMO_MAX_USERS {L.MIMO_MAX_USERS}" in src
     assert f"#define MIMO_MAX_ANTENNAS {L.MIMO_MAX_ANTENNAS}" in src
     assert f"#define MIMO_MAX_BATCH {L.MIMO_MAX_BATCH}" in src
+    m = re.search(r"#define MIMO_MAX_SPAN_BYTES (\d+)LL", src)
+    assert m and int(m.group(1)) == L.MIMO_MAX_SPAN_BYTES
     for name in ("MIMO_C32", "MIMO_C16", "MIMO_CBF16", "MIMO_SINR_APPROX", "MIMO_SINR_EXACT",
                  "MIMO_SCALAR_F32", "MIMO_SCALAR_F64", "MIMO_OK", "MIMO_EINVAL",
                  "MIMO_EUNSUPPORTED", "MIMO_EWORKSPACE", "MIMO_EHIP"):
@@ -89,6 +91,38 @@ def test_detect_rejects_invalid_arguments(shape, kw, status):
     st = _detect(L.shape(*shape), **kw)
     assert st == status
     assert L.lib().mimo_last_error()
+
+
+def _max_s(B, U):
+    """Largest S whose per-subcarrier arrays stay below MIMO_MAX_SPAN_BYTES."""
+    return (L.MIMO_MAX_SPAN_BYTES - 1) // (8 * max(B, 4 * U))
+
+
+@pytest.mark.parametrize("B,U", [(4096, 32), (128, 16), (32, 8), (64, 32)])
+def test_rhs_count_bounded_by_32bit_offsets(B, U):
+    """Per-subcarrier arrays are addressed with 32-bit byte offsets (2^31 marks
+    a masked lane): an S whose Y / Q (8 B S bytes) or LLR (32 U S bytes) range
+    reaches 2^31 is rejected before anything is enqueued, on every entry point
+    that takes a shape; the largest S below the bound passes validation (with
+    n_sc = 0, so nothing runs)."""
+    lib = L.lib()
+    s_ok, s_bad = _max_s(B, U), _max_s(B, U) + 1
+    assert 8 * max(B, 4 * U) * s_bad >= L.MIMO_MAX_SPAN_BYTES
+    for S, n_sc, want in ((s_bad, 4, L.MIMO_EUNSUPPORTED), (s_bad, 0, L.MIMO_EUNSUPPORTED),
+                          (s_ok, 0, L.MIMO_OK)):
+        sh = L.shape(B, U, S, 3, n_sc)
+        assert _detect(sh, m=8) == want
+        assert lib.mimo_precode_cg(sh, P, P, 0, 0.1, 0, 0, P2, None, None, 0, None) == want
+        assert lib.mimo_gram_mf(sh, P, P, 0, 0.5, P2, P2, None) == want
+        assert lib.mimo_detect_cholesky(sh, P, P, 0, 0.5, 1.0, 4, P2, None, None, None,
+                                        None) == want
+        assert lib.mimo_precode_cgls(sh, P, P, 0, 0.1, 0, 0, P2, None, None) == want
+        if want != L.MIMO_OK:
+            assert b"too large" in lib.mimo_last_error()
+    fr = (L.MimoFrame * 1)()
+    fr[0] = L.MimoFrame(4, B, U, s_bad, 3, P, P, P2, None, 0.5, 1.0, 0.0, 0)
+    assert lib.mimo_detect_cg_batch(ctypes.addressof(fr), 1, 0, 4, 0,
+                                    None) == L.MIMO_EUNSUPPORTED
 
 
 def test_zero_subcarriers_is_a_noop():

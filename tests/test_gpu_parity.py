@@ -34,9 +34,9 @@ def api():
 # (name, n_sc, B, U, S, m, K, snr_db, channel)
 DETECT_CASES = [
     ("small_32x8", 64, 32, 8, 1, 4, 3, 10.0, "iid"),
-    ("plain_128x8_0dB", 48, 128, 8, 14, 6, 3, 0.0, "iid"),
-    ("plain_128x8_10dB", 48, 128, 8, 14, 6, 3, 10.0, "iid"),
-    ("plain_128x8_20dB", 48, 128, 8, 14, 6, 3, 20.0, "iid"),
+    # the 128x8 workload's whole SNR sweep, 0-20 dB in 2 dB steps
+    *[(f"plain_128x8_{snr}dB", 48, 128, 8, 14, 6, 3, float(snr), "iid")
+      for snr in range(0, 21, 2)],
     ("mixed_128x16", 64, 128, 16, 14, 6, 4, 15.0, "iid"),
     ("mixed_128x32", 40, 128, 32, 14, 6, 4, 15.0, "iid"),
     ("corr_256x32", 24, 256, 32, 14, 8, 6, 25.0, "kronecker"),
@@ -56,6 +56,10 @@ DETECT_CASES = [
     ("odd_tile_64x13_S1", 23, 64, 13, 1, 2, 3, 8.0, "iid"),
     ("odd_tile_96x17_S3", 7, 96, 17, 3, 6, 4, 12.0, "iid"),
 ]
+
+
+def _case(name):
+    return next(c for c in DETECT_CASES if c[0] == name)
 
 
 def _uplink(case, seed=0):
@@ -137,7 +141,7 @@ def test_detect_zero_receive_vectors():
 
 
 def test_detect_is_deterministic():
-    f = _uplink(DETECT_CASES[4])
+    f = _uplink(_case("mixed_128x16"))
     H, Y = dev(f.H), dev(f.Y)
     a = host(api().detect_cg(H, Y, f.n0, f.es, 4, 6)["llr"])
     b = host(api().detect_cg(H, Y, f.n0, f.es, 4, 6)["llr"])
@@ -148,7 +152,8 @@ def test_detect_is_deterministic():
 
 PRECODE_CASES = [
     ("small_32x8", 64, 32, 8, 1, 3, 10.0),
-    ("plain_128x8", 48, 128, 8, 14, 3, 10.0),
+    # the 128x8 workload's whole SNR sweep, 0-20 dB in 2 dB steps
+    *[(f"plain_128x8_{snr}dB", 48, 128, 8, 14, 3, float(snr)) for snr in range(0, 21, 2)],
     ("mixed_128x16", 48, 128, 16, 14, 4, 15.0),
     ("mixed_128x32", 24, 128, 32, 14, 4, 15.0),
     ("corr_256x32", 16, 256, 32, 14, 6, 25.0),
@@ -254,7 +259,7 @@ def test_convert_is_bit_exact_rne(dt):
 
 
 @pytest.mark.parametrize("dt", ["f16", "bf16"])
-@pytest.mark.parametrize("case", [DETECT_CASES[0], DETECT_CASES[4], DETECT_CASES[5]],
+@pytest.mark.parametrize("case", [_case("small_32x8"), _case("mixed_128x16"), _case("mixed_128x32")],
                          ids=["small_32x8", "mixed_128x16", "mixed_128x32"])
 def test_detect_16bit_matches_oracle_on_quantized_inputs(dt, case):
     name, n, B, U, S, m, K, snr, ch = case
@@ -370,7 +375,7 @@ def test_bench_batches_sampled(wl, frames, dsched, psched):
     assert np.all(np.isfinite(dets[0][0])) and np.all(np.isfinite(pres[0][0]))
 
 
-@pytest.mark.parametrize("case", [DETECT_CASES[4], DETECT_CASES[5], DETECT_CASES[7],
+@pytest.mark.parametrize("case", [_case("mixed_128x16"), _case("mixed_128x32"), _case("ragged_30x5_S17"),
                                   ("ragged_100x12_S9", 29, 100, 12, 9, 4, 4, 10.0, "iid"),
                                   ("odd_tile_40x5_S3", 29, 40, 5, 3, 6, 4, 12.0, "iid")],
                          ids=["mixed_128x16", "mixed_128x32", "ragged_30x5_S17", "ragged_100x12_S9",
@@ -450,7 +455,7 @@ def test_graph_replay_matches_eager():
     """Captured detection + precoding replayed several times, with eager work
     and synchronizations in between: every replay equals the eager result."""
     from paper_1404_0424_amd.graphs import StepGraph
-    f = _uplink(DETECT_CASES[4])
+    f = _uplink(_case("mixed_128x16"))
     d = W.downlink_frame(np.random.default_rng(8), f.H.shape[0], 128, 16, 14, 6, 15.0, H=f.H)
     A = api()
     H, Y, T = dev(f.H), dev(f.Y), dev(d.T)
@@ -477,8 +482,8 @@ def test_graph_replay_matches_eager():
         assert torch.isfinite(other["llr"]).all()
 
 
-@pytest.mark.parametrize("case", [DETECT_CASES[0], DETECT_CASES[4], DETECT_CASES[5],
-                                  DETECT_CASES[7]],
+@pytest.mark.parametrize("case", [_case("small_32x8"), _case("mixed_128x16"), _case("mixed_128x32"),
+                                  _case("ragged_30x5_S17")],
                          ids=["small_32x8", "mixed_128x16", "mixed_128x32", "ragged_30x5_S17"])
 def test_plain_baseline_variant_parity(case):
     """The plain VALU per-system baseline computes the same method."""
