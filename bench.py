@@ -247,7 +247,11 @@ def main():
                  "what": "plain FP32 per-system detection: VALU Gram/matched filter/CG, "
                          "one right-hand side at a time, complex64 storage"}
         log(f"plain FP32 per-system detection: {plain_s * 1e3:.3f} ms")
-    solves = 2 * n * wl.S                      # uplink + downlink CG solves per step
+    # a solve is one (subcarrier, OFDM symbol) system; a step solves each of
+    # the batch's n x S systems twice, once by uplink detection and once by
+    # downlink precoding, and `value` counts both (uplink.solves_per_s is the
+    # detection-only rate over the detection kernel's time)
+    solves = 2 * n * wl.S
     llr_bits = n * wl.S * wl.U * wl.m
     det_bytes = detect_bytes_per_sc(wl.B, wl.U, wl.S, wl.m) * n
     pre_bytes = precode_bytes_per_sc(wl.B, wl.U, wl.S) * n
@@ -267,7 +271,7 @@ def main():
     result = {
         "metric": METRIC,
         "value": solves / wall,
-        "unit": "subcarrier-solves/s",
+        "unit": "subcarrier-solves/s (uplink detections + downlink precodings)",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -513,7 +517,8 @@ def configs_leg(api, autotune, kernel_time, dev, samples):
     matched-filter kernel's MFMA utilisation (the Gram stage) at U = 32."""
     import torch
     from paper_1404_0424_amd import workload as W
-    plan = [("small_32x8", 1024, (10.0,)), ("plain_128x8", 16, (0.0, 10.0, 20.0)),
+    plan = [("small_32x8", 1024, (10.0,)),
+            ("plain_128x8", 16, tuple(float(x) for x in range(0, 21, 2))),
             ("mixed_128x32", 8, (15.0,)), ("corr_256x32", 1, (25.0,))]
     out = {}
     for name, F, snrs in plan:
@@ -614,11 +619,24 @@ def comparison_leg(api, autotune, H, Y, T, llr, Q, up, dn, wl, n, kernel_time):
     ks = np.array(sorted(det["cg"]))
     ts = np.array([det["cg"][K]["ms"] for K in ks]) * 1e-3
     slope = float(np.polyfit(ks, ts, 1)[0])
-    cg_stage = {"ms_per_iteration": slope * 1e3, "stage_ms_at_K": slope * wl.K * 1e3,
-                "frame_bytes_per_stage_time_gbs": det_b / (slope * wl.K) / 1e9,
-                "frac": det_b / (slope * wl.K) / 1e9 / HBM_PEAK_GBS,
-                "what": "CG stage time = slope of detection time over K times K; frame "
-                        "bytes (H, Y, LLR) over that time"}
+    # one CG iteration's MFMA work per subcarrier: the mat-vec E = A P of all
+    # right-hand sides (4 W products per k-step of 4 users); its floor is that
+    # work at the FP32 MFMA peak.  The CG moves no HBM bytes (A, P and the
+    # vectors stay in LDS and registers), so it has no HBM roofline: what it
+    # costs is the launch time it adds per iteration.
+    W_ = 1 if wl.U <= 16 else 2
+    it_flops = 4 * W_ * min(4 * W_, -(-wl.U // 4)) * MFMA_FLOPS * -(-wl.S // 16) * n
+    floor_s = it_flops / MFMA_PEAK_FP32
+    at_k = det["cg"][wl.K]["ms"] * 1e-3
+    cg_stage = {"ms_per_iteration": slope * 1e3,
+                "mfma_floor_ms_per_iteration": floor_s * 1e3,
+                "slope_over_floor": slope / floor_s,
+                "stage_ms_at_K": slope * wl.K * 1e3,
+                "stage_share_of_launch_at_K": slope * wl.K / at_k,
+                "what": "least-squares slope of the detection launch time over K = 1..16 "
+                        "(the Gram, matched-filter and LLR work does not depend on K); the "
+                        "floor is one iteration's mat-vec MFMAs at the FP32 MFMA peak; the "
+                        "CG stage reads and writes no HBM"}
     pre = {
         "cg_K%d" % wl.K: rec(kernel_time(lambda: api.precode_cg(
             H, T, beta, wl.K, True, qnorm=False, out=Q), reps=5), pre_b),
@@ -744,10 +762,80 @@ def serving_leg(n_frames, skip):
     return out
 
 
+def _oracle_chunk(args):
+    """One chunk of the CPU baseline in a worker process: the FP64 oracle's
+    detection and precoding of a few subcarriers, one BLAS thread."""
+    H, Y, T, n0, es, beta, K, m = args
+    from threadpoolctl import threadpool_limits
+
+    from oracle import mimo_oracle as O
+    with threadpool_limits(1):
+        O.detect_cg(H, Y, n0, es, K, m, "approx")
+        O.precode_cg(H, T, beta, K, normalize=True)
+    return H.shape[0]
+
+
+def _worker_init(root):
+    sys.path.insert(0, root)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def host_workers():
+    """Worker processes for the all-cores oracle run: the CPUs this process
+    may run on, at most 16 (one GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_all_cores(up, dn, wl, seconds, workers):
+    """The oracle over random chunks of the same batch on `workers` processes
+    (spawned children, one BLAS thread each), for about `seconds` of wall
+    time after the pool has started.  Returns (subcarriers, seconds)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    root = os.path.dirname(os.path.abspath(__file__))
+    chunk = 16
+    rng = np.random.default_rng(1)
+
+    def task():
+        idx = np.sort(rng.choice(up.H.shape[0], chunk, replace=False))
+        return (up.H[idx], up.Y[idx], dn.T[idx], up.n0, up.es, dn.beta, wl.K, wl.m)
+
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"),
+                                initializer=_worker_init, initargs=(root,)) as pool:
+        list(pool.map(_oracle_chunk, [task() for _ in range(workers)]))    # start every worker
+        done = 0
+        t0 = time.perf_counter()
+        pending = {pool.submit(_oracle_chunk, task()) for _ in range(2 * workers)}
+        while pending:
+            fin, pending = cf.wait(pending, return_when=cf.FIRST_COMPLETED)
+            for f in fin:
+                done += f.result()
+                if time.perf_counter() - t0 < seconds:
+                    pending.add(pool.submit(_oracle_chunk, task()))
+        return done, time.perf_counter() - t0
+
+
 def cpu_baseline(up, dn, wl, llr_gpu, Q_gpu, seconds, samples=()):
-    """The FP64 oracle on the host, single-threaded, on a bounded sample of the
-    same workload; also reports the GPU's error against it on that sample and
-    on the sampled results of every other leg (storage types, configurations)."""
+    """The FP64 oracle on the host on a bounded sample of the same workload:
+    single-threaded, and on all the host cores this run may use (worker
+    processes over subcarriers); also reports the GPU's error against it on
+    that sample and on the sampled results of every other leg (storage
+    types, configurations)."""
     sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
     from oracle import mimo_oracle as O
     from threadpoolctl import threadpool_limits
@@ -771,15 +859,24 @@ def cpu_baseline(up, dn, wl, llr_gpu, Q_gpu, seconds, samples=()):
                 eq = float(np.max(np.linalg.norm(Q_h - p["Q"], axis=1)
                                   / np.linalg.norm(p["Q"], axis=1)))
         el_s = time.perf_counter() - t0
-    solves = 2 * done * wl.S
-    log(f"cpu oracle: {done} subcarriers in {el_s:.1f}s")
+    one = 2 * done * wl.S / el_s
+    log(f"cpu oracle, 1 thread: {done} subcarriers in {el_s:.1f}s")
+    workers = host_workers()
+    done_all, el_all = cpu_all_cores(up, dn, wl, seconds, workers)
+    allc = 2 * done_all * wl.S / el_all
+    log(f"cpu oracle, {workers} processes: {done_all} subcarriers in {el_all:.1f}s")
     errors = oracle_errors(samples, O)
     for k, v in errors.items():
         log(f"error vs oracle {k}: " + ", ".join(f"{a}={b:.2e}" for a, b in v.items()
                                                 if a != "subcarriers"))
-    return {"value": solves / el_s, "unit": "subcarrier-solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} random subcarriers of the timed batch ({wl.S} symbols each), "
-                      f"uplink detection + downlink precoding, numpy FP64, 1 thread",
+    return {"value": allc, "unit": "subcarrier-solves/s (uplink detections + downlink "
+                                   "precodings)", "cores": workers, "kind": "oracle",
+            "sample": f"{done_all} random subcarriers of the timed batch ({wl.S} symbols each), "
+                      f"uplink detection + downlink precoding, numpy FP64, {workers} worker "
+                      f"processes of one thread each, {el_all:.1f} s",
+            "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(),
+            "single_thread": {"value": one, "cores": 1,
+                              "sample": f"{done} random subcarriers, {el_s:.1f} s"},
             "gpu_error_vs_oracle_on_sample": {"eps_llr": el, "eps_q": eq},
             "gpu_error_vs_oracle_by_result": errors}
 

@@ -13,6 +13,12 @@ Latency is arrival to completion of the request's last kernel: completion
 times come from HIP events measured against a reference event whose host
 time was taken when the server started.
 
+The HBM budget covers the channel cache and the device buffers of admitted
+requests until their kernels complete.  Outputs handed back to the caller
+(through the request's future) are the caller's from then on and sit outside
+the budget: the server keeps no reference to them, only the timing and work
+counts of completed requests for :meth:`Server.stats`.
+
 The scheduling logic is independent of the GPU: an *executor* object does
 the device work (``GpuExecutor`` here), so the admission and ordering rules
 can be exercised with any executor that implements the same methods.
@@ -66,6 +72,15 @@ class Result:
         return self.t_done - self.t_submit
 
 
+@dataclasses.dataclass
+class _Done:
+    """What the server keeps of a completed request (no device buffers)."""
+    t_submit: float
+    t_done: float
+    solves: int
+    llr_bits: int
+
+
 class AdmissionError(RuntimeError):
     """A request can never fit the HBM budget."""
 
@@ -101,7 +116,7 @@ class Server:
         self._free_slots = list(range(n_slots))
         self._reserved = 0                 # bytes of admitted requests
         self._channels: dict = {}          # ch_id -> bytes
-        self._done: list[Result] = []
+        self._done: list[_Done] = []
         self._running = True
         self._paused = bool(start_paused)  # queue requests without admitting them
         self._t_resume = None              # when a paused server was released
@@ -297,7 +312,8 @@ class Server:
                 results = [Result(o, p.t_submit, t_admit, t_done, solves, bits)
                            for p, (o, t_done, solves, bits) in zip(group, per)]
                 with self._lock:
-                    self._done.extend(results)
+                    self._done.extend(_Done(r.t_submit, r.t_done, r.solves, r.llr_bits)
+                                      for r in results)
                 for p, r in zip(group, results):
                     p.fut.set_result(r)
             except Exception as e:          # noqa: BLE001

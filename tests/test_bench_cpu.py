@@ -105,3 +105,17 @@ def test_oracle_errors_16bit_against_rounded_inputs():
     assert e["d"]["eps_llr_vs_rounded_inputs"] == 0.0
     assert e["p"]["eps_q_vs_rounded_inputs"] == 0.0
     assert 1e-4 < e["d"]["eps_x"] < 3e-2 and 1e-4 < e["p"]["eps_q"] < 3e-2
+
+
+def test_cpu_all_cores_oracle_run():
+    """The all-cores oracle leg: spawned worker processes (one BLAS thread
+    each) run the oracle over chunks of the workload for the given time."""
+    from paper_1404_0424_amd import workload as W
+    wl = W.WORKLOADS["small_32x8"]
+    rng = np.random.default_rng(0)
+    up = W.uplink_frame(rng, 64, wl.B, wl.U, wl.S, wl.m, 10.0)
+    dn = W.downlink_frame(rng, 64, wl.B, wl.U, wl.S, wl.m, 10.0, H=up.H)
+    done, secs = bench.cpu_all_cores(up, dn, wl, 0.5, 2)
+    assert done > 0 and done % 16 == 0 and secs >= 0.5
+    assert 1 <= bench.host_workers() <= 16
+    assert bench.cpu_model()

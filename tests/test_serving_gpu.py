@@ -100,3 +100,43 @@ def test_small_budget_waits_and_16bit_channels(setup):
     Yq = O.dequantize_f16(O.quantize_f16(Y))
     ref = O.detect_cg(deq, Yq, req.n0, 1.0, 3, 6)
     assert llr_err(out, ref["llr"]) <= TOL_L
+
+
+def test_device_memory_stays_within_budget(setup):
+    """Many frames served under a small budget, the caller dropping each
+    result after reading it: device memory allocated during the run stays
+    within the budget plus a fixed slack (the server keeps no outputs of
+    completed requests)."""
+    SV, rng, chans = setup
+    import gc
+    ex = SV.GpuExecutor(n_slots=4)
+    H = chans[1]
+    reqs = [_uplink(SV, rng, H, "c")[0] for _ in range(4)] + \
+           [_downlink(SV, rng, H, "c")[0] for _ in range(4)]
+    torch.cuda.synchronize()
+    gc.collect()
+    base = torch.cuda.memory_allocated()
+    srv = SV.Server(ex, hbm_budget=1 << 30, n_slots=4)
+    srv.register_channel("c", H, "c32")
+    need = max(ex.request_bytes(r) for r in reqs)
+    cache = srv.cache_bytes
+    srv.close()
+    budget = cache + 3 * need
+    srv = SV.Server(ex, hbm_budget=budget, n_slots=4)
+    srv.register_channel("c", H, "c32")
+    peak = 0
+    for k in range(300):
+        f = srv.submit(reqs[k % len(reqs)])
+        if k % 8 == 7:
+            f.result(timeout=60)
+            peak = max(peak, torch.cuda.memory_allocated() - base)
+        del f
+    srv.drain(timeout=60)
+    gc.collect()
+    peak = max(peak, torch.cuda.memory_allocated() - base)
+    st = srv.stats()
+    srv.close()
+    assert st["frames"] == 300
+    slack = 4 << 20                  # allocator rounding, event/stream objects
+    print(f"budget {budget} B, peak allocated above baseline {peak} B")
+    assert peak <= budget + slack
