@@ -149,6 +149,7 @@ const char* mimo_tune_variant_name(int op, int variant) {
       case mimo::kDetectStream: return "stream";
       case mimo::kDetectStreamSmall: return "stream-small";
       case mimo::kDetectPlain: return "plain";
+      case mimo::kDetectRing: return "ring";
     }
   } else if (op == MIMO_OP_PRECODE) {
     switch (variant) {

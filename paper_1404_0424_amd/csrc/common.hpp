@@ -17,13 +17,26 @@ constexpr int kWavesPerBlock = 4;
 
 // ---------------------------------------------------------------- ordering
 // One wavefront owns each LDS region, so cross-lane exchange through LDS
-// needs no s_barrier: LDS instructions of one wave complete in order.  The
-// fence keeps the compiler from moving LDS accesses across the exchange
-// point and waits for the wave's own outstanding LDS operations.
+// needs no s_barrier: LDS instructions of one wave execute in order.  The
+// asm statement is a compiler barrier for memory operations (its memory
+// clobber) and waits for the wave's own outstanding LDS operations; it
+// waits for nothing else.  (A workgroup-scope memory fence would also do,
+// but while loads into LDS are in flight it waits for every outstanding
+// vector-memory operation, which would drain a kernel's prefetch.)
 __device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Wait until at most N of the wave's vector-memory operations (loads,
+// stores, loads into LDS) are outstanding; they complete in issue order.
+// Loads into LDS are invisible to the compiler's own counter waits, so
+// kernels that issue them wait explicitly; the memory clobber keeps LDS
+// reads of the landed data below the wait.
+template <int N>
+__device__ __forceinline__ void vm_wait() {
+  static_assert(N >= 0 && N <= 63, "vmcnt is a 6-bit counter");
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
 }
 
 // ---------------------------------------------------------------- DPP

@@ -90,14 +90,12 @@ __global__ __launch_bounds__(256, W == 1 ? 3 : 2) void gram_mf_stream_kernel(Gra
     GramAcc<W> acc;
     acc.clear();
     Blk alt;
+    // pairs of blocks; an odd count's last partner lies past B and reads
+    // zero, adding exact zeros (one loop exit, so nothing after the Gram
+    // waits for the next subcarrier's block in flight)
     for (int b0 = 0;; b0 += 2 * Blk::ANT) {
-      const bool more1 = b0 + Blk::ANT < B;
-      alt.template load<HAS_Y>(more1 ? cur : nxt, more1 ? b0 + Blk::ANT : 0);
+      alt.template load<HAS_Y>(cur, b0 + Blk::ANT);
       blk.template mma<true, HAS_Y>(acc);
-      if (!more1) {
-        blk = alt;
-        break;
-      }
       const bool more2 = b0 + 2 * Blk::ANT < B;
       blk.template load<HAS_Y>(more2 ? cur : nxt, more2 ? b0 + 2 * Blk::ANT : 0);
       alt.template mma<true, HAS_Y>(acc);

@@ -18,14 +18,12 @@ template <int W, bool DO_MF, typename IN, typename Sub, typename Blk>
 __device__ __forceinline__ void gram_stream(IN tag, Blk& blk, const Sub& cur, const Sub& nxt,
                                             int B, GramAcc<W>& acc) {
   Blk alt;
+  // pairs of blocks; an odd count's last partner lies past B and reads
+  // zero, adding exact zeros (one loop exit, so nothing after the Gram
+  // waits for the next subcarrier's block in flight)
   for (int b0 = 0;; b0 += 2 * Blk::ANT) {
-    const bool more1 = b0 + Blk::ANT < B;
-    alt.template load<DO_MF>(more1 ? cur : nxt, more1 ? b0 + Blk::ANT : 0);
+    alt.template load<DO_MF>(cur, b0 + Blk::ANT);
     blk.template mma<true, DO_MF>(acc);
-    if (!more1) {
-      blk = alt;
-      break;
-    }
     const bool more2 = b0 + 2 * Blk::ANT < B;
     blk.template load<DO_MF>(more2 ? cur : nxt, more2 ? b0 + 2 * Blk::ANT : 0);
     alt.template mma<true, DO_MF>(acc);

@@ -88,7 +88,7 @@ struct Schedule {
   int blocks_per_cu;
 };
 enum { kDetectGeneric = 0, kDetectStream = 1, kDetectStreamSmall = 2, kDetectPlain = 3,
-       kDetectVariants = 4 };
+       kDetectRing = 4, kDetectVariants = 5 };
 enum { kPrecodeGeneric = 0, kPrecodeStream = 1, kPrecodeStreamSmall = 2, kPrecodeResident = 3,
        kPrecodeVariants = 4 };
 

@@ -13,6 +13,12 @@ hipError_t launch_detect_exact(const DetectParams& p, int in_dtype, int scalar_f
                                hipStream_t stream);
 hipError_t launch_precode(const PrecodeParams& p, int in_dtype, int scalar_f64,
                           const Schedule& sch, hipStream_t stream);
+// LDS-ring detection (complex64, U <= 16, S <= 16, at least 3 chunks of 16 antennas,
+// 16-byte aligned per-subcarrier arrays, LLRs only); other calls take
+// stream-small.
+bool detect_ring_eligible(const DetectParams& p, int in_dtype);
+hipError_t launch_detect_ring(const DetectParams& p, int scalar_f64, int m_bits,
+                              const Schedule& sch, hipStream_t stream);
 hipError_t launch_detect_plain(const DetectParams& p, int scalar_f64, int m_bits,
                                const Schedule& sch, hipStream_t stream);
 hipError_t launch_detect_batch(const BatchArgs& a, int max_u, int in_dtype, int scalar_f64,

@@ -119,14 +119,12 @@ __global__ __launch_bounds__(256, 2) void precode_stream_kernel(PrecodeParams pr
     GramAcc<W> acc;
     acc.clear();
     Blk alt;
+    // pairs of blocks; an odd count's last partner lies past B and reads
+    // zero, adding exact zeros (one loop exit, so nothing after the Gram
+    // waits for the next subcarrier's block in flight)
     for (int b0 = 0;; b0 += 2 * Blk::ANT) {
-      const bool more1 = b0 + Blk::ANT < B;
-      alt.template load<false>(more1 ? cur : nxt, more1 ? b0 + Blk::ANT : 0);
+      alt.template load<false>(cur, b0 + Blk::ANT);
       blk.template mma<true, false>(acc);
-      if (!more1) {
-        blk = alt;
-        break;
-      }
       const bool more2 = b0 + 2 * Blk::ANT < B;
       blk.template load<false>(more2 ? cur : nxt, more2 ? b0 + 2 * Blk::ANT : 0);
       alt.template mma<true, false>(acc);
