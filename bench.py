@@ -35,10 +35,11 @@ def log(msg):
 
 # kernel symbol that each detection schedule variant launches
 DETECT_KERNEL = {"generic": "detect_approx_kernel", "stream": "detect_stream_kernel",
-                 "stream-small": "detect_stream_kernel", "plain": "detect_plain_kernel"}
+                 "stream-small": "detect_stream_kernel", "plain": "detect_plain_kernel",
+                 "ring": "detect_ring_kernel"}
 # translation units the complex64 approximate-SINR detection kernels are built from
-DETECT_SOURCES = ["detect.hip", "cg_core.hpp", "gram_phase.hpp", "llr.hpp", "kernels.hpp",
-                  "common.hpp"]
+DETECT_SOURCES = ["detect.hip", "detect_core.hpp", "detect_ring.hip", "cg_core.hpp",
+                  "gram_phase.hpp", "llr.hpp", "kernels.hpp", "common.hpp"]
 PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
 
 
@@ -385,6 +386,9 @@ def main():
 
     if not args.no_serving:
         result["serving"] = serving_leg(args.serving_frames, args.serving_skip)
+        nat = serving_leg(args.serving_frames, args.serving_skip, native=True)
+        nat["saturation_vs_batched_step"] = nat["saturation"]["solves_per_s"] / result["value"]
+        result["serving"]["native"] = nat
 
     if args.copy_calibration:
         nbytes = 512 << 20
@@ -661,16 +665,21 @@ def comparison_leg(api, autotune, H, Y, T, llr, Q, up, dn, wl, n, kernel_time):
                     "bytes (H, Y in, LLR out / H, T in, Q out) per launch time"}
 
 
-def serving_leg(n_frames, skip):
+def serving_leg(n_frames, skip, native=False):
     """Mixed-shape uplink/downlink frames through the continuous-batching
     server: saturation throughput (all frames queued, then released at once), then Poisson
     arrivals at 50%, 80% and 95% of it, and 80% under a small HBM budget that
     makes requests wait for memory; p50/p99 arrival-to-completion latency
-    over all but the first ``skip`` frames of each run."""
+    over all but the first ``skip`` frames of each run.  ``native``: the C++
+    scheduler of include/mimo_serve.h (NativeServer) instead of the Python
+    one (Server)."""
     import torch
 
+    from paper_1404_0424_amd import native_serving as NS
     from paper_1404_0424_amd import serving as SV
     from paper_1404_0424_amd import workload as W
+
+    tag = "native " if native else ""
 
     rng = W.rng_for(4, 0)
     chans, _ = W.serving_stream(rng, 16, 0, 0.0)
@@ -695,10 +704,16 @@ def serving_leg(n_frames, skip):
 
     def run(rate, frames_n, dtype="c32", budget=16 << 30):
         frames = W.serving_frames(W.rng_for(4, 1 + int(rate)), 16, frames_n, rate)
-        srv = SV.Server(ex, hbm_budget=budget, n_slots=4)
+        # the native server's consumer reads no outputs (they return to the
+        # pool at completion) and submits pre-marshalled requests without
+        # futures; statistics come from the server's completion records
+        srv = (NS.NativeServer(hbm_budget=budget, n_slots=4, input_events=False,
+                               keep_outputs=False) if native
+               else SV.Server(ex, hbm_budget=budget, n_slots=4))
         for c in chans:
             srv.register_channel(c.ch_id, c.H, dtype)
-        reqs = [request(f) for f in frames]
+        reqs = [srv.prepare(request(f)) if native else request(f) for f in frames]
+        submit = (lambda r: srv.submit(r, future=False)) if native else srv.submit
         # warm up every shape class once
         for f in {(by_id[f.ch_id].B, by_id[f.ch_id].U, f.uplink, f.m): f for f in frames}.values():
             srv.submit(request(f)).result(timeout=60)
@@ -714,40 +729,90 @@ def serving_leg(n_frames, skip):
                 if d <= 0:
                     break
                 time.sleep(d - 1e-4 if d > 2e-4 else 0)
-            srv.submit(r)
+            submit(r)
         srv.resume()
         srv.drain(timeout=120)
         st = srv.stats(skip=min(skip, len(frames) // 2))
-        st["mean_batch"] = float(np.mean(srv.batch_sizes[-len(frames):])) if srv.batch_sizes else 0
+        if not native:
+            st["mean_batch"] = (float(np.mean(srv.batch_sizes[-len(frames):]))
+                                if srv.batch_sizes else 0)
         st["budget_bytes"] = budget
         st["budget_waits"] = srv.budget_waits
         srv.close()
         return st
 
+    def device_rate(frames_n):
+        """Solves/s of the same stream's frames in ideal batches: grouped by
+        kernel class, 32 frames per batched launch, back to back on one
+        stream, no scheduler (the device rate a server can approach)."""
+        frames = W.serving_frames(W.rng_for(4, 1), 16, frames_n, 0.0)
+        groups = {}
+        for f in frames:
+            c = by_id[f.ch_id]
+            groups.setdefault((f.uplink, c.U <= 16, f.m if f.uplink else 0), []).append(f)
+        Hd = {c.ch_id: torch.from_numpy(c.H.astype(np.complex64)).to(dev) for c in chans}
+        launches = []
+        for (up, _, m), fs in groups.items():
+            for i in range(0, len(fs), 32):
+                chunk = fs[i:i + 32]
+                if up:
+                    fr = [(Hd[f.ch_id], data[f.ch_id][0],
+                           W.n0_from_snr_db(f.snr_db, by_id[f.ch_id].U, by_id[f.ch_id].B), 1.0)
+                          for f in chunk]
+                    launches.append(lambda fr=fr, m=m: api.detect_cg_batch(fr, 3, m))
+                else:
+                    fr = [(Hd[f.ch_id], data[f.ch_id][1],
+                           W.n0_from_snr_db(f.snr_db, by_id[f.ch_id].U, by_id[f.ch_id].B), True)
+                          for f in chunk]
+                    launches.append(lambda fr=fr: api.precode_cg_batch(fr, 3))
+        solves = sum(by_id[f.ch_id].n_sc * 14 for f in frames)
+        best = None
+        for _ in range(3):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for fn in launches:
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        return {"solves_per_s": solves / (best * 1e-3), "frames_per_s": frames_n / (best * 1e-3),
+                "launches": len(launches), "ms": best}
+
+    from paper_1404_0424_amd import api
+    ideal = device_rate(n_frames)
+    log(f"serving stream in ideal batches (no scheduler): {ideal['frames_per_s']:.0f} frames/s, "
+        f"{ideal['solves_per_s']:.3g} solves/s")
+
     old_switch = sys.getswitchinterval()
     sys.setswitchinterval(2e-5)              # submitter and scheduler threads share the GIL
 
     sat = run(0.0, n_frames)
-    log(f"serving saturation: {sat['frames_per_s']:.0f} frames/s, p50 {sat['p50_ms']:.3f} ms, "
-        f"p99 {sat['p99_ms']:.3f} ms")
+    sat["vs_ideal_batches"] = sat["solves_per_s"] / ideal["solves_per_s"]
+    log(f"{tag}serving saturation: {sat['frames_per_s']:.0f} frames/s, "
+        f"{sat['solves_per_s']:.3g} solves/s, p50 {sat['p50_ms']:.3f} ms, p99 {sat['p99_ms']:.3f} ms")
     out = {"workload": "Poisson uplink/downlink frames, B in {64,128,256}, U in {8,16,32}, "
                        "300-1200 subcarriers x 14 symbols, 16/64/256-QAM, 5-25 dB, K=3, "
                        "16 device-resident channels, 4 stream slots, 16 GiB budget",
+           "scheduler": ("C++ scheduler thread (include/mimo_serve.h), device pool of the budget"
+                         if native else "Python scheduler thread (serving.Server)"),
            "frames_per_run": n_frames, "frames_left_out": min(skip, n_frames // 2),
-           "saturation": sat}
+           "ideal_batches": ideal, "saturation": sat}
     for load in (0.5, 0.8, 0.95):
         st = run(load * sat["frames_per_s"], n_frames)
-        log(f"serving load {load}: offered {load * sat['frames_per_s']:.0f}/s, achieved "
+        log(f"{tag}serving load {load}: offered {load * sat['frames_per_s']:.0f}/s, achieved "
             f"{st['frames_per_s']:.0f}/s, p50 {st['p50_ms']:.3f} ms, p99 {st['p99_ms']:.3f} ms")
         out[f"load_{load}"] = st
     # small budget: the channel cache plus room for two of the largest
     # requests, so that admission waits for memory
-    need = max(ex.request_bytes(r) for c in chans for r in (
-        SV.UplinkRequest(c.ch_id, data[c.ch_id][0], 1.0, 1.0, 8, 3),
-        SV.DownlinkRequest(c.ch_id, data[c.ch_id][1], 1.0, 3, True)))
-    cache = sum(ex.channel_bytes(c.H, "c32") for c in chans)
-    st = run(0.8 * sat["frames_per_s"], n_frames, budget=cache + 2 * need)
-    log(f"serving load 0.8, budget {(cache + 2 * need) / 2**20:.0f} MiB: achieved "
+    # (uplink: LLRs of 256-QAM; downlink: Q and the norms; complex64 channels)
+    need = max(max(4 * c.n_sc * c.U * 14 * 8, 8 * c.n_sc * c.B * 14 + 4 * c.n_sc * 14)
+               for c in chans)
+    cache = sum(8 * c.n_sc * c.B * c.U for c in chans)
+    small = cache + 2 * need + 4096          # + pool rounding of the native server
+    st = run(0.8 * sat["frames_per_s"], n_frames, budget=small)
+    log(f"{tag}serving load 0.8, budget {small / 2**20:.0f} MiB: achieved "
         f"{st['frames_per_s']:.0f}/s, p50 {st['p50_ms']:.3f} ms, p99 {st['p99_ms']:.3f} ms, "
         f"{st['budget_waits']} budget waits")
     out["load_0.8_small_budget"] = st
@@ -755,7 +820,7 @@ def serving_leg(n_frames, skip):
     # filter on 16-bit MFMA, FP32 accumulate and CG); uplink Y is rounded to
     # BF16 on the slot stream per frame
     sat16 = run(0.0, n_frames, "bf16")
-    log(f"serving saturation, BF16 channel storage: {sat16['frames_per_s']:.0f} frames/s, "
+    log(f"{tag}serving saturation, BF16 channel storage: {sat16['frames_per_s']:.0f} frames/s, "
         f"{sat16['solves_per_s']:.3g} solves/s")
     out["saturation_bf16"] = sat16
     sys.setswitchinterval(old_switch)

@@ -37,6 +37,46 @@ class MimoFrame(ctypes.Structure):
                 ("normalize", ctypes.c_int32)]
 
 
+class MimoServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_int64), ("n_slots", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("lookahead", ctypes.c_int32),
+                ("paused", ctypes.c_int32), ("keep_outputs", ctypes.c_int32)]
+
+
+class MimoUplinkReq(ctypes.Structure):
+    _fields_ = [("ch_id", ctypes.c_int64), ("Y", ctypes.c_void_p), ("S", ctypes.c_int32),
+                ("qam_bits", ctypes.c_int32), ("K", ctypes.c_int32), ("sinr_mode", ctypes.c_int32),
+                ("scalar_prec", ctypes.c_int32), ("want_xhat", ctypes.c_int32),
+                ("n0", ctypes.c_float), ("es", ctypes.c_float)]
+
+
+class MimoDownlinkReq(ctypes.Structure):
+    _fields_ = [("ch_id", ctypes.c_int64), ("T", ctypes.c_void_p), ("S", ctypes.c_int32),
+                ("K", ctypes.c_int32), ("normalize", ctypes.c_int32),
+                ("scalar_prec", ctypes.c_int32), ("beta", ctypes.c_float)]
+
+
+class MimoCompletion(ctypes.Structure):
+    _fields_ = [("req_id", ctypes.c_int64), ("status", ctypes.c_int32), ("kind", ctypes.c_int32),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("out", ctypes.c_void_p), ("out2", ctypes.c_void_p),
+                ("n_sc", ctypes.c_int64), ("B", ctypes.c_int32), ("U", ctypes.c_int32),
+                ("S", ctypes.c_int32), ("qam_bits", ctypes.c_int32), ("solves", ctypes.c_int64),
+                ("llr_bits", ctypes.c_int64)]
+
+
+class MimoServerStats(ctypes.Structure):
+    _fields_ = [("frames", ctypes.c_int64), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("frames_per_s", ctypes.c_double), ("solves_per_s", ctypes.c_double),
+                ("llr_gbit_s", ctypes.c_double), ("peak_bytes", ctypes.c_int64),
+                ("budget_waits", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("mean_batch", ctypes.c_double)]
+
+
+MIMO_SERVE_MAX_SLOTS = 16
+
+
 class MimoError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"[{status}] {message}")
@@ -72,6 +112,25 @@ _SIGNATURES = {
     "mimo_tune_get": (_i, [_i, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "mimo_tune_variant_count": (_i, [_i]),
     "mimo_tune_variant_name": (ctypes.c_char_p, [_i, _i]),
+    # native serving runtime (include/mimo_serve.h)
+    "mimo_server_create": (_i, [ctypes.POINTER(MimoServerConfig), _i, ctypes.POINTER(_vp)]),
+    "mimo_server_destroy": (_i, [_vp]),
+    "mimo_server_register_channel": (_i, [_vp, ctypes.c_int64, _vp, _i, ctypes.c_int64,
+                                          ctypes.c_int32, ctypes.c_int32]),
+    "mimo_server_unregister_channel": (_i, [_vp, ctypes.c_int64]),
+    "mimo_server_submit_uplink": (_i, [_vp, ctypes.POINTER(MimoUplinkReq), _vp,
+                                       ctypes.POINTER(ctypes.c_int64)]),
+    "mimo_server_submit_downlink": (_i, [_vp, ctypes.POINTER(MimoDownlinkReq), _vp,
+                                         ctypes.POINTER(ctypes.c_int64)]),
+    "mimo_server_poll": (_i, [_vp, ctypes.POINTER(MimoCompletion), _i, ctypes.c_int64]),
+    "mimo_server_release": (_i, [_vp, ctypes.c_int64]),
+    "mimo_server_dlpack": (_i, [_vp, ctypes.c_int64, _i, ctypes.POINTER(_vp)]),
+    "mimo_server_pause": (_i, [_vp]),
+    "mimo_server_resume": (_i, [_vp]),
+    "mimo_server_drain": (_i, [_vp, ctypes.c_int64]),
+    "mimo_server_stats_get": (_i, [_vp, ctypes.c_int64, _i, ctypes.POINTER(MimoServerStats)]),
+    "mimo_server_memory": (_i, [_vp, ctypes.POINTER(ctypes.c_int64),
+                                ctypes.POINTER(ctypes.c_int64)]),
 }
 
 

@@ -123,6 +123,8 @@ float qam_scale(float es, int qam_bits) {
 }  // namespace
 
 namespace mimo {
+void set_last_error(const char* msg) { std::snprintf(g_last_error, sizeof(g_last_error), "%s", msg); }
+
 int num_compute_units() {
   static std::atomic<int> cache[64];
   int dev = 0;

@@ -45,6 +45,9 @@ hipError_t launch_gram_mf(const GramParams& p, int in_dtype, const Schedule& sch
 hipError_t launch_convert(const float2* src, uint16_t* dst, int dst_dtype, int64_t n, int R,
                           int C, hipStream_t stream);
 
+// Sets the calling thread's mimo_last_error() message (abi.hip).
+void set_last_error(const char* msg);
+
 // Grid for one-wavefront-per-subcarrier kernels (4 waves per block); the
 // kernels loop over subcarriers with a grid stride, so any n_sc is covered.
 inline unsigned int wave_grid(int64_t n_sc) {

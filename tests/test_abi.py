@@ -1,6 +1,6 @@
 """The C ABI on the CPU: the library loads, exports every entry point that
-include/mimo_cg.h declares, and rejects invalid arguments synchronously
-(before any HIP call).  No kernel runs here."""
+include/*.h declares (mimo_cg.h, mimo_serve.h), and rejects invalid
+arguments synchronously (before any HIP call).  No kernel runs here."""
 import ctypes
 import os
 import re
@@ -13,12 +13,16 @@ from paper_1404_0424_amd import _lib as L
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "mimo_cg.h")
+HEADERS = sorted(os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+                 if f.endswith(".h"))
 
 
 def _declared():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(mimo_[a-z0-9_]+)\s*\(", src)))
+    names = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(mimo_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
@@ -259,3 +263,47 @@ def test_product_package_does_not_import_the_oracle():
                          timeout=120)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip() == "False"
+
+
+def test_server_validation_without_a_gpu():
+    """The native server's entry points reject bad configurations and NULL
+    handles before any HIP call."""
+    import ctypes
+    lib = L.lib()
+    out = ctypes.c_void_p()
+    for cfg in [L.MimoServerConfig(0, 4, 32, 128, 0, 1), L.MimoServerConfig(1 << 20, 0, 32, 128, 0, 1),
+                L.MimoServerConfig(1 << 20, L.MIMO_SERVE_MAX_SLOTS + 1, 32, 128, 0, 1),
+                L.MimoServerConfig(1 << 20, 4, 0, 128, 0, 1),
+                L.MimoServerConfig(1 << 20, 4, L.MIMO_MAX_BATCH + 1, 128, 0, 1),
+                L.MimoServerConfig(1 << 20, 4, 32, 0, 0, 1)]:
+        assert lib.mimo_server_create(ctypes.byref(cfg), 0, ctypes.byref(out)) == L.MIMO_EINVAL
+        assert lib.mimo_last_error()
+    assert lib.mimo_server_create(None, 0, ctypes.byref(out)) == L.MIMO_EINVAL
+    rid = ctypes.c_int64()
+    up = L.MimoUplinkReq()
+    dn = L.MimoDownlinkReq()
+    assert lib.mimo_server_destroy(None) == L.MIMO_EINVAL
+    assert lib.mimo_server_register_channel(None, 1, P, 0, 1, 8, 4) == L.MIMO_EINVAL
+    assert lib.mimo_server_unregister_channel(None, 1) == L.MIMO_EINVAL
+    assert lib.mimo_server_submit_uplink(None, ctypes.byref(up), None, ctypes.byref(rid)) == L.MIMO_EINVAL
+    assert lib.mimo_server_submit_downlink(None, ctypes.byref(dn), None, ctypes.byref(rid)) == L.MIMO_EINVAL
+    assert lib.mimo_server_poll(None, None, 0, 0) == L.MIMO_EINVAL
+    assert lib.mimo_server_release(None, 1) == L.MIMO_EINVAL
+    assert lib.mimo_server_dlpack(None, 1, 0, ctypes.byref(out)) == L.MIMO_EINVAL
+    assert lib.mimo_server_pause(None) == L.MIMO_EINVAL
+    assert lib.mimo_server_resume(None) == L.MIMO_EINVAL
+    assert lib.mimo_server_drain(None, 0) == L.MIMO_EINVAL
+    st = L.MimoServerStats()
+    assert lib.mimo_server_stats_get(None, 0, 0, ctypes.byref(st)) == L.MIMO_EINVAL
+    assert lib.mimo_server_memory(None, None, None) == L.MIMO_EINVAL
+
+
+def test_serve_header_constants_match_binding():
+    src = open(os.path.join(ROOT, "include", "mimo_serve.h")).read()
+    assert f"#define MIMO_SERVE_MAX_SLOTS {L.MIMO_SERVE_MAX_SLOTS}" in src
+    # struct layouts the binding relies on (sizes of the C structs)
+    import ctypes
+    assert ctypes.sizeof(L.MimoServerConfig) == 32
+    assert ctypes.sizeof(L.MimoUplinkReq) == 48
+    assert ctypes.sizeof(L.MimoDownlinkReq) == 40
+    assert ctypes.sizeof(L.MimoCompletion) == 96
