@@ -36,9 +36,9 @@ def log(msg):
 # kernel symbol that each detection schedule variant launches
 DETECT_KERNEL = {"generic": "detect_approx_kernel", "stream": "detect_stream_kernel",
                  "stream-small": "detect_stream_kernel", "plain": "detect_plain_kernel",
-                 "ring": "detect_ring_kernel"}
+                 "ring": "detect_ring_kernel", "split": "detect_split_kernel"}
 # translation units the complex64 approximate-SINR detection kernels are built from
-DETECT_SOURCES = ["detect.hip", "detect_core.hpp", "detect_ring.hip", "cg_core.hpp",
+DETECT_SOURCES = ["detect.hip", "detect_core.hpp", "detect_ring.hip", "split.hip", "cg_core.hpp",
                   "gram_phase.hpp", "llr.hpp", "kernels.hpp", "common.hpp"]
 PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
 

@@ -152,6 +152,7 @@ const char* mimo_tune_variant_name(int op, int variant) {
       case mimo::kDetectStreamSmall: return "stream-small";
       case mimo::kDetectPlain: return "plain";
       case mimo::kDetectRing: return "ring";
+      case mimo::kDetectSplit: return "split";
     }
   } else if (op == MIMO_OP_PRECODE) {
     switch (variant) {
@@ -159,6 +160,7 @@ const char* mimo_tune_variant_name(int op, int variant) {
       case mimo::kPrecodeStream: return "stream";
       case mimo::kPrecodeStreamSmall: return "stream-small";
       case mimo::kPrecodeResident: return "resident";
+      case mimo::kPrecodeSplit: return "split";
     }
   } else if (op == MIMO_OP_GRAM_MF) {
     switch (variant) {

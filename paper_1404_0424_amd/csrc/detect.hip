@@ -259,6 +259,12 @@ hipError_t launch_detect_approx(const DetectParams& p, int in_dtype, int scalar_
                                 const Schedule& sch, hipStream_t stream) {
   if (sch.variant == kDetectPlain && in_dtype == 0)
     return launch_detect_plain(p, scalar_f64, m_bits, sch, stream);
+  if (sch.variant == kDetectSplit) {
+    if (split_eligible(in_dtype, p.U, p.S, p.B, false))
+      return launch_detect_split(p, scalar_f64, m_bits, sch, stream);
+    return launch_detect_approx(p, in_dtype, scalar_f64, m_bits,
+                                Schedule{kDetectStreamSmall, sch.blocks_per_cu}, stream);
+  }
   if (sch.variant == kDetectRing) {
     if (detect_ring_eligible(p, in_dtype))
       return launch_detect_ring(p, scalar_f64, m_bits, sch, stream);

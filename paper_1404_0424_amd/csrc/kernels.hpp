@@ -88,9 +88,9 @@ struct Schedule {
   int blocks_per_cu;
 };
 enum { kDetectGeneric = 0, kDetectStream = 1, kDetectStreamSmall = 2, kDetectPlain = 3,
-       kDetectRing = 4, kDetectVariants = 5 };
+       kDetectRing = 4, kDetectSplit = 5, kDetectVariants = 6 };
 enum { kPrecodeGeneric = 0, kPrecodeStream = 1, kPrecodeStreamSmall = 2, kPrecodeResident = 3,
-       kPrecodeVariants = 4 };
+       kPrecodeSplit = 4, kPrecodeVariants = 5 };
 
 int num_compute_units();   // of the current device (cached per device)
 

@@ -19,6 +19,14 @@ hipError_t launch_precode(const PrecodeParams& p, int in_dtype, int scalar_f64,
 bool detect_ring_eligible(const DetectParams& p, int in_dtype);
 hipError_t launch_detect_ring(const DetectParams& p, int scalar_f64, int m_bits,
                               const Schedule& sch, hipStream_t stream);
+// Split forms: four wavefronts per subcarrier, antenna quarters (complex64,
+// U <= 32, S <= 16; precoding also B <= 256); other calls take the
+// register-streaming kernels.
+bool split_eligible(int in_dtype, int U, int S, int B, bool precode);
+hipError_t launch_detect_split(const DetectParams& p, int scalar_f64, int m_bits,
+                               const Schedule& sch, hipStream_t stream);
+hipError_t launch_precode_split(const PrecodeParams& p, int scalar_f64, const Schedule& sch,
+                                hipStream_t stream);
 hipError_t launch_detect_plain(const DetectParams& p, int scalar_f64, int m_bits,
                                const Schedule& sch, hipStream_t stream);
 hipError_t launch_detect_batch(const BatchArgs& a, int max_u, int in_dtype, int scalar_f64,

@@ -487,6 +487,12 @@ hipError_t launch_precode_batch(const BatchArgs& a, int max_u, int in_dtype, int
 
 hipError_t launch_precode(const PrecodeParams& p, int in_dtype, int scalar_f64,
                           const Schedule& sch, hipStream_t stream) {
+  if (sch.variant == kPrecodeSplit) {
+    if (split_eligible(in_dtype, p.U, p.S, p.B, true))
+      return launch_precode_split(p, scalar_f64, sch, stream);
+    return launch_precode(p, in_dtype, scalar_f64,
+                          Schedule{kPrecodeStreamSmall, sch.blocks_per_cu}, stream);
+  }
   if (p.U <= 16) return launch_in<1>(p, in_dtype, scalar_f64, sch, stream);
   return launch_in<2>(p, in_dtype, scalar_f64, sch, stream);
 }

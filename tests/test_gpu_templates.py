@@ -60,12 +60,14 @@ def test_every_variant_of_every_instantiation(dt, U, scalar):
     saved = [autotune.get_schedule(op, U, code) for op in ("detect", "precode")]
     try:
         for v, name in enumerate(autotune.variants("detect")):
-            if name in autotune.BASELINE_VARIANTS:
+            if name in autotune.BASELINE_VARIANTS | autotune.ROUNDING_VARIANTS:
                 continue
             autotune.set_schedule("detect", U, code, v, 0)
             o = A.detect_cg(H, Y, f.n0, f.es, K, m, "approx", scalar, xhat=True)
             dets[name] = (host(o["llr"]), host(o["xhat"]))
         for v, name in enumerate(autotune.variants("precode")):
+            if name in autotune.ROUNDING_VARIANTS:
+                continue
             autotune.set_schedule("precode", U, code, v, 2)
             q, qn = A.precode_cg(H, T, d.beta, K, True, scalar)
             pres[name] = (host(q), host(qn))
