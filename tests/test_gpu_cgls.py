@@ -40,6 +40,8 @@ CASES = [
     ("corr_256x32", 24, 256, 32, 14, 8, 6, 25.0, "kronecker"),
     ("ragged_30x5_S17", 37, 30, 5, 17, 2, 5, 5.0, "iid"),
     ("ragged_20x20", 13, 20, 20, 3, 4, 7, 12.0, "iid"),
+    # U = 16 with B <= 128 stages H in LDS: a partial antenna tile and two rhs chunks
+    ("ragged_40x16_S17", 21, 40, 16, 17, 4, 4, 10.0, "iid"),
     ("single_user", 9, 6, 1, 2, 8, 1, 10.0, "iid"),
     # square channel, kappa(A) ~ 9: K = 8 stops well before convergence (past
     # convergence the recomputed s = Hbar^H r sits at the rounding floor of
