@@ -36,7 +36,8 @@ def log(msg):
 # kernel symbol that each detection schedule variant launches
 DETECT_KERNEL = {"generic": "detect_approx_kernel", "stream": "detect_stream_kernel",
                  "stream-small": "detect_stream_kernel", "plain": "detect_plain_kernel",
-                 "ring": "detect_ring_kernel", "split": "detect_split_kernel"}
+                 "ring": "detect_ring_kernel", "split": "detect_split_kernel",
+                 "stream-valu": "detect_stream_kernel"}
 # translation units the complex64 approximate-SINR detection kernels are built from
 DETECT_SOURCES = ["detect.hip", "detect_core.hpp", "detect_ring.hip", "split.hip", "cg_core.hpp",
                   "gram_phase.hpp", "llr.hpp", "kernels.hpp", "common.hpp"]
@@ -98,6 +99,10 @@ def main():
     ap.add_argument("--schedules", help="load a schedule table saved by --save-schedules "
                     "(or the autotuner) instead of tuning")
     ap.add_argument("--save-schedules", help="write the tuned schedule table to this file")
+    ap.add_argument("--detect-schedule", metavar="VARIANT:BLOCKS_PER_CU",
+                    help="run detection under this schedule instead of tuning (e.g. stream-valu:0)")
+    ap.add_argument("--precode-schedule", metavar="VARIANT:BLOCKS_PER_CU",
+                    help="run precoding under this schedule instead of tuning (e.g. split:2)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-stream leg")
     ap.add_argument("--serving-frames", type=int, default=2000)
     ap.add_argument("--serving-skip", type=int, default=200,
@@ -193,6 +198,14 @@ def main():
             tuned[op] = {"variant": autotune.variants(op)[v], "blocks_per_cu": b,
                          "from": os.path.basename(args.schedules)}
         log(f"loaded schedules: {tuned}")
+    elif args.detect_schedule or args.precode_schedule:
+        for op, spec in (("detect", args.detect_schedule), ("precode", args.precode_schedule)):
+            if spec:
+                name, bpc = spec.split(":")
+                autotune.set_schedule(op, wl.U, 0, autotune.variants(op).index(name), int(bpc))
+            v, b = autotune.get_schedule(op, wl.U, 0)
+            tuned[op] = {"variant": autotune.variants(op)[v], "blocks_per_cu": b, "from": "command line"}
+        log(f"schedules: {tuned}")
     elif not args.no_tune:
         # schedules picked by the autotuner on these inputs (not timed)
         e1 = autotune.tune("detect", wl.U, 0, lambda: api.detect_cg(

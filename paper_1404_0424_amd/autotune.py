@@ -23,9 +23,9 @@ from . import _lib as L
 
 BLOCKS_PER_CU = (0, 1, 2, 3, 4, 5, 6, 8)
 BASELINE_VARIANTS = {"plain"}      # reference mappings, never chosen
-# variants that sum the Gram in another order (antenna quarters): equal to the
-# others to rounding, not bit for bit
-ROUNDING_VARIANTS = {"split"}
+# variants that sum in another order (the Gram over antenna quarters; the CG
+# mat-vec on VALU FMAs): equal to the others to rounding, not bit for bit
+ROUNDING_VARIANTS = {"split", "stream-valu"}
 OPS = {"detect": L.MIMO_OP_DETECT, "precode": L.MIMO_OP_PRECODE,
        "gram_mf": L.MIMO_OP_GRAM_MF}
 

@@ -153,6 +153,7 @@ const char* mimo_tune_variant_name(int op, int variant) {
       case mimo::kDetectPlain: return "plain";
       case mimo::kDetectRing: return "ring";
       case mimo::kDetectSplit: return "split";
+      case mimo::kDetectValu: return "stream-valu";
     }
   } else if (op == MIMO_OP_PRECODE) {
     switch (variant) {

@@ -48,7 +48,12 @@ template <int W>
 struct AOperand {
   float2 a[W][4 * W];
   int nk;
-  __device__ void load(const float2* __restrict__ As, int ast, int c, int g, int U) {
+  const float2* rows;   // the wave's LDS copy of A (row stride ast), for matvec_valu
+  int ast, U;
+  __device__ void load(const float2* __restrict__ As, int ast_, int c, int g, int U_) {
+    rows = As;
+    ast = ast_;
+    U = U_;
     const int k = (U + 3) >> 2;
     nk = __builtin_amdgcn_readfirstlane(k < 4 * W ? k : 4 * W);
 #pragma unroll
@@ -144,19 +149,53 @@ __device__ __forceinline__ void matvec_mfma(const AOperand<W>& at, const float2*
     for (int j = 0; j < 4; ++j) e[w][j] = make_float2(er[w][j], ei[w][j]);
 }
 
+// e = A x with VALU FMAs instead of MFMA (a measured alternative, schedule
+// variant "stream-valu"): lane (c, g) forms e[16 w + c][4 g + j] as
+// sum_k A[16 w + c][k] X[k][4 g + j] over the users k < U, with A from the
+// wave's LDS copy and X[k][.] from the staged vectors (the 16 lanes of a DPP
+// row read the same address: a broadcast).  Terms k >= U are exact zeros
+// and are skipped.  Sums in another order than the MFMA form.
+template <int W>
+__device__ __forceinline__ void matvec_valu(const AOperand<W>& at, const float2* __restrict__ Ps,
+                                            int c, int g, float2 (&e)[W][4]) {
+#pragma unroll
+  for (int w = 0; w < W; ++w)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) e[w][j] = make_float2(0.f, 0.f);
+  for (int k = 0; k < at.U; ++k) {
+    const float4 x01 = *(const float4*)&Ps[k * kPST + 4 * g];
+    const float4 x23 = *(const float4*)&Ps[k * kPST + 4 * g + 2];
+    const float2 x[4] = {make_float2(x01.x, x01.y), make_float2(x01.z, x01.w),
+                         make_float2(x23.x, x23.y), make_float2(x23.z, x23.w)};
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const float2 a = at.rows[(16 * w + c) * at.ast + k];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        e[w][j].x = __builtin_fmaf(a.x, x[j].x, e[w][j].x);
+        e[w][j].x = __builtin_fmaf(-a.y, x[j].y, e[w][j].x);
+        e[w][j].y = __builtin_fmaf(a.x, x[j].y, e[w][j].y);
+        e[w][j].y = __builtin_fmaf(a.y, x[j].x, e[w][j].y);
+      }
+    }
+  }
+}
+
 // One iteration of Algorithm 1 (loop body) for the lane's 4 right-hand
 // sides.  alpha/beta are returned for the trackers.  A right-hand side whose
 // residual norm is zero (converged or b = 0) freezes: alpha = beta = 0.
 // Branch-free (selects), with the four right-hand sides' reductions
 // interleaved.
-template <int W, typename ST>
+// VALU: the mat-vec on VALU FMAs (matvec_valu) instead of MFMA.
+template <int W, typename ST, bool VALU = false>
 __device__ __forceinline__ void cg_step(CGState<W, ST>& st, const AOperand<W>& at,
                                         float2* __restrict__ Ps, int c, int g, ST (&alpha)[4],
                                         ST (&beta)[4]) {
   stage_vec<W>(Ps, c, g, st.p);
   wave_lds_sync();
   float2 e[W][4];
-  matvec_mfma<W>(at, Ps, c, g, e);                 // e_{k-1} = A p_{k-1}
+  if constexpr (VALU) matvec_valu<W>(at, Ps, c, g, e);   // e_{k-1} = A p_{k-1}
+  else matvec_mfma<W>(at, Ps, c, g, e);
   wave_lds_sync();
   ST pe[4];
 #pragma unroll

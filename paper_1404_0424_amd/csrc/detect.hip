@@ -13,7 +13,8 @@ namespace mimo {
 // current block run, and issues the first block of its next subcarrier
 // before the CG / LLR phase of the current one, so HBM latency overlaps
 // compute within the wave as well as across waves.
-template <int W, typename IN, typename ST, int M_BITS, bool SMALL>
+// VALU: CG mat-vec on VALU FMAs (schedule variant "stream-valu").
+template <int W, typename IN, typename ST, int M_BITS, bool SMALL, bool VALU = false>
 __global__ __launch_bounds__(256, 2) void detect_stream_kernel(DetectParams prm) {
   constexpr int NU = 16 * W;
   constexpr int AST = NU + 2;   // LDS row stride (complex) of A
@@ -80,8 +81,8 @@ __global__ __launch_bounds__(256, 2) void detect_stream_kernel(DetectParams prm)
     AOperand<W> at;
     float d[W];
     gram_to_operands<W>(IN{}, acc, As, Gs, Ps, AST, prm.reg, U, c, g, at, d);
-    cg_llr_epilogue<W, ST, M_BITS, kUncondMem<IN>, true>(prm, n, 0, acc, at, d, Gs, Ps, c, g,
-                                                         W_s[wv]);
+    cg_llr_epilogue<W, ST, M_BITS, kUncondMem<IN>, true, false, VALU>(prm, n, 0, acc, at, d, Gs,
+                                                                       Ps, c, g, W_s[wv]);
     n = nn;
     cur = nxt;
   }
@@ -179,6 +180,13 @@ static void launch_one(const DetectParams& p, const Schedule& sch, hipStream_t s
     hipLaunchKernelGGL((detect_approx_kernel<W, IN, ST, M>), grid, block, 0, stream, p);
   else if (sch.variant == kDetectStreamSmall)
     hipLaunchKernelGGL((detect_stream_kernel<W, IN, ST, M, true>), grid, block, 0, stream, p);
+  else if (sch.variant == kDetectValu) {
+    if constexpr (std::is_same<IN, InC32>::value || std::is_same<IN, InC32P>::value)
+      hipLaunchKernelGGL((detect_stream_kernel<W, IN, ST, M, true, true>), grid, block, 0, stream,
+                         p);
+    else
+      hipLaunchKernelGGL((detect_stream_kernel<W, IN, ST, M, true>), grid, block, 0, stream, p);
+  }
   else
     hipLaunchKernelGGL((detect_stream_kernel<W, IN, ST, M, false>), grid, block, 0, stream, p);
 }

@@ -87,7 +87,8 @@ constexpr int kStagedStores = (16 * W * 16 * M_BITS / 2 + kWave - 1) / kWave;
 // xhat, mu and SINR outputs are not written, so a caller that counts
 // outstanding memory operations knows that this call adds exactly
 // kStagedStores<W, M_BITS> of them.
-template <int W, typename ST, int M_BITS, bool BUF, bool STAGE = false, bool FIXED_STORES = false>
+template <int W, typename ST, int M_BITS, bool BUF, bool STAGE = false, bool FIXED_STORES = false,
+          bool VALU = false>
 __device__ __forceinline__ void cg_llr_epilogue(const DetectParams& prm, int64_t n, int s0,
                                                 const GramAcc<W>& acc, const AOperand<W>& at,
                                                 const float (&d)[W], const float* Gs,
@@ -105,7 +106,7 @@ __device__ __forceinline__ void cg_llr_epilogue(const DetectParams& prm, int64_t
   tk.init();
   for (int k = 0; k < prm.K; ++k) {
     ST al[4], be[4];
-    cg_step<W, ST>(st, at, Ps, c, g, al, be);
+    cg_step<W, ST, VALU>(st, at, Ps, c, g, al, be);
     tracker_step<W, ST>(tk, d, al, be);
   }
   DetectStore<M_BITS> os;

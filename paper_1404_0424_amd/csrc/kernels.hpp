@@ -88,7 +88,7 @@ struct Schedule {
   int blocks_per_cu;
 };
 enum { kDetectGeneric = 0, kDetectStream = 1, kDetectStreamSmall = 2, kDetectPlain = 3,
-       kDetectRing = 4, kDetectSplit = 5, kDetectVariants = 6 };
+       kDetectRing = 4, kDetectSplit = 5, kDetectValu = 6, kDetectVariants = 7 };
 enum { kPrecodeGeneric = 0, kPrecodeStream = 1, kPrecodeStreamSmall = 2, kPrecodeResident = 3,
        kPrecodeSplit = 4, kPrecodeVariants = 5 };
 
