@@ -68,8 +68,8 @@ enum { MIMO_C32 = 0, MIMO_C16 = 1, MIMO_CBF16 = 2 };
 enum { MIMO_SINR_APPROX = 0, MIMO_SINR_EXACT = 1 };
 /* Precision of the CG scalar recurrences (||r||^2, p^H e, alpha, beta) */
 enum { MIMO_SCALAR_F32 = 0, MIMO_SCALAR_F64 = 1 };
-/* Operations, for mimo_workspace_bytes */
-enum { MIMO_OP_GRAM_MF = 0, MIMO_OP_DETECT = 1, MIMO_OP_PRECODE = 2 };
+/* Operations, for mimo_workspace_bytes and the schedule table */
+enum { MIMO_OP_GRAM_MF = 0, MIMO_OP_DETECT = 1, MIMO_OP_PRECODE = 2, MIMO_OP_SLOT = 3 };
 
 typedef enum mimo_status {
   MIMO_OK = 0,
@@ -143,6 +143,33 @@ int mimo_precode_cg(const mimo_shape* shape, const void* H, const void* T,
                     int in_dtype, float beta, int normalize, int scalar_prec,
                     void* Q, float* qnorm, void* workspace,
                     size_t workspace_bytes, void* stream);
+
+/*
+ * mimo_detect_precode_cg -- one uplink + downlink slot on a reciprocal
+ * channel: mimo_detect_cg (approximate SINR) of Y and mimo_precode_cg of T
+ * with the same H.  By reciprocity (Sec. II-B, H_d = H_u^H) the two systems
+ * share the Gram matrix G = H_u^H H_u = H_d H_d^H, A_u = G + (n0/es) I for
+ * detection and A_d = G + beta I for precoding (eq. (16)); the fused kernel
+ * forms G once per subcarrier and reads H once for both directions.
+ *   ul  B, U, n_sc; S = receive vectors per subcarrier, K = detection
+ *       iterations;  dl  the same B, U, n_sc; S = downlink vectors,
+ *       K = precoding iterations (S and K may differ between ul and dl)
+ *   H   [n_sc][B][U] storage in_dtype;  Y [n_sc][B][ul.S] storage in_dtype;
+ *   T   complex64 [n_sc][U][dl.S]
+ *   n0, es, qam_bits, scalar_prec, llr, xhat, mu, sinr as mimo_detect_cg;
+ *   beta, normalize, Q, qnorm as mimo_precode_cg (scalar_prec applies to
+ *   both directions)
+ * Outputs are bitwise those of mimo_detect_cg(ul, ...) followed by
+ * mimo_precode_cg(dl, ...) on the same inputs.  The fused kernel covers
+ * complex64 storage with U <= 16, B <= 128 and S <= 16 in both directions;
+ * other calls (and the schedule variant "separate") run the two operations
+ * as two launches on `stream`.
+ */
+int mimo_detect_precode_cg(const mimo_shape* ul, const mimo_shape* dl, const void* H,
+                           const void* Y, const void* T, int in_dtype, float n0, float es,
+                           int qam_bits, float beta, int normalize, int scalar_prec,
+                           float* llr, void* xhat, float* mu, float* sinr, void* Q,
+                           float* qnorm, void* stream);
 
 /*
  * mimo_convert -- channel / receive-vector ingest into reduced precision.
@@ -267,11 +294,25 @@ int mimo_precode_cgls(const mimo_shape* shape, const void* H, const void* T,
  *                 S <= 16 and B <= 128 in any storage type; other shapes use
  *                 1, or 0 when S > 16; Gram + matched filter: 0 generic,
  *                 1 stream = next block and next subcarrier in flight, for
- *                 S <= 16 or no Y, larger S uses 0)
+ *                 S <= 16 or no Y, larger S uses 0; uplink + downlink slot:
+ *                 0 separate = two launches with the detection and precoding
+ *                 schedules, 1 fused = one H-resident kernel where
+ *                 mimo_detect_precode_cg allows it, else 0)
+ *                 Further detection variants (measured forms, correct for
+ *                 every shape, never faster on the workloads measured):
+ *                 4 ring = chunks of H and Y loaded straight into an LDS
+ *                 ring (complex64, U <= 16, S <= 16, LLRs only), 5 split =
+ *                 four wavefronts per subcarrier over antenna quarters
+ *                 (complex64, U <= 32, S <= 16), 6 stream-valu = stream with
+ *                 the CG mat-vec on VALU FMAs; precoding 4 split (complex64,
+ *                 U <= 32, S <= 16, B <= 256).  Where a variant does not
+ *                 cover a call, stream-small runs.  split and stream-valu
+ *                 sum in another order: equal to the others to rounding.
  *   blocks_per_cu 0: one wavefront per subcarrier; k in [1, 64]: persistent
  *                 grid of k four-wavefront blocks per compute unit
- * Results do not depend on the schedule (every variant performs the same
- * operations in the same order per system).  mimo_tune_set is not
+ * Results do not depend on the schedule (every variant other than split
+ * and stream-valu performs the same operations in the same order per
+ * system).  mimo_tune_set is not
  * synchronized with launches already enqueued; it affects later calls.
  */
 int mimo_tune_set(int op, int user_class, int in_dtype, int variant, int blocks_per_cu);

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libmimocg.so")
 MIMO_C32, MIMO_C16, MIMO_CBF16 = 0, 1, 2
 MIMO_SINR_APPROX, MIMO_SINR_EXACT = 0, 1
 MIMO_SCALAR_F32, MIMO_SCALAR_F64 = 0, 1
-MIMO_OP_GRAM_MF, MIMO_OP_DETECT, MIMO_OP_PRECODE = 0, 1, 2
+MIMO_OP_GRAM_MF, MIMO_OP_DETECT, MIMO_OP_PRECODE, MIMO_OP_SLOT = 0, 1, 2, 3
 MIMO_OK, MIMO_EINVAL, MIMO_EUNSUPPORTED, MIMO_EWORKSPACE, MIMO_EHIP = 0, -1, -2, -3, -4
 MIMO_MAX_USERS = 32
 MIMO_MAX_ANTENNAS = 4096
@@ -95,6 +95,8 @@ _SIGNATURES = {
     "mimo_detect_cg": (_i, [_shape_p, _vp, _vp, _i, _f, _f, _i, _i, _i, _vp, _vp, _vp, _vp,
                             _vp, _sz, _vp]),
     "mimo_precode_cg": (_i, [_shape_p, _vp, _vp, _i, _f, _i, _i, _vp, _vp, _vp, _sz, _vp]),
+    "mimo_detect_precode_cg": (_i, [_shape_p, _shape_p, _vp, _vp, _vp, _i, _f, _f, _i, _f, _i,
+                                    _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "mimo_convert": (_i, [_vp, _vp, _i, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _vp]),
     "mimo_workspace_bytes": (_sz, [_shape_p, _i, _i]),
     "mimo_status_string": (ctypes.c_char_p, [_i]),

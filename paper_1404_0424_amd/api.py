@@ -166,9 +166,36 @@ def precode_cg(H, T: torch.Tensor, beta: float, K: int, normalize: bool = False,
     return Q, qn
 
 
+def detect_precode_cg(H, Y, T: torch.Tensor, n0: float, es: float, beta: float, K_ul: int,
+                      K_dl: int, qam_bits: int, normalize: bool = False,
+                      scalar_prec: str = "f32", xhat: bool = False, mu: bool = False,
+                      sinr: bool = False, qnorm: bool = True, out=None, stream=None):
+    """One uplink + downlink slot on the reciprocal channel H: detect_cg of Y
+    (approximate SINR) and precode_cg of T with one shared Gram matrix per
+    subcarrier.  Returns (detection dict, Q, qnorm); ``out`` may hold
+    preallocated tensors under the keys of both ('llr', 'xhat', 'mu', 'sinr',
+    'Q', 'qnorm')."""
+    hp, code, n, B, U = _channel(H)
+    yp, Su = _rhs(Y, code, n, B)
+    out = out or {}
+    res, llr, xh, mu_t, sn = _detect_outputs(H.device, n, U, Su, qam_bits, xhat, mu, sinr,
+                                             {k: v for k, v in out.items()
+                                              if k in ("llr", "xhat", "mu", "sinr")} or None)
+    _, _, _, _, _, Sd, Q, qn = _precode_outputs(H, T, out.get("Q"), qnorm)
+    if "qnorm" in out and out["qnorm"] is not None:
+        qn = out["qnorm"]
+    prec = {"f32": L.MIMO_SCALAR_F32, "f64": L.MIMO_SCALAR_F64}[scalar_prec]
+    L.check(L.lib().mimo_detect_precode_cg(L.shape(B, U, Su, K_ul, n), L.shape(B, U, Sd, K_dl, n),
+                                           hp, yp, T.data_ptr(), code, float(n0), float(es),
+                                           int(qam_bits), float(beta), int(bool(normalize)), prec,
+                                           llr.data_ptr(), _ptr(xh), _ptr(mu_t), _ptr(sn),
+                                           Q.data_ptr(), _ptr(qn), _stream(stream)))
+    return res, Q, qn
+
+
 def workspace_bytes(B, U, S, K, n_sc, op: str = "detect", sinr_mode: str = "approx") -> int:
     opc = {"gram_mf": L.MIMO_OP_GRAM_MF, "detect": L.MIMO_OP_DETECT,
-           "precode": L.MIMO_OP_PRECODE}[op]
+           "precode": L.MIMO_OP_PRECODE, "slot": L.MIMO_OP_SLOT}[op]
     mode = {"approx": L.MIMO_SINR_APPROX, "exact": L.MIMO_SINR_EXACT}[sinr_mode]
     return int(L.lib().mimo_workspace_bytes(L.shape(B, U, S, K, n_sc), opc, mode))
 

@@ -26,8 +26,10 @@ BASELINE_VARIANTS = {"plain"}      # reference mappings, never chosen
 # variants that sum in another order (the Gram over antenna quarters; the CG
 # mat-vec on VALU FMAs): equal to the others to rounding, not bit for bit
 ROUNDING_VARIANTS = {"split", "stream-valu"}
+# variants whose launches take their grids from other table entries
+GRID_FREE = {("slot", "separate")}
 OPS = {"detect": L.MIMO_OP_DETECT, "precode": L.MIMO_OP_PRECODE,
-       "gram_mf": L.MIMO_OP_GRAM_MF}
+       "gram_mf": L.MIMO_OP_GRAM_MF, "slot": L.MIMO_OP_SLOT}
 
 
 def variants(op: str) -> list[str]:
@@ -75,6 +77,8 @@ def tune(op: str, U: int, dtype_code: int, fn, reps: int = 5, log=None) -> dict:
         if name in BASELINE_VARIANTS:
             continue
         for b in BLOCKS_PER_CU:
+            if (op, name) in GRID_FREE and b != 0:
+                continue
             set_schedule(op, U, dtype_code, v, b)
             t = time_call(fn, reps)
             results.append({"variant": v, "blocks_per_cu": b, "seconds": t})
@@ -137,6 +141,10 @@ def tune_workload(name: str, frames: int = 16, dtypes=("c32", "f16", "bf16"), lo
             Hx, Yx, up.n0, up.es, wl.K, wl.m, "approx", sc, out={"llr": llr}), log=log))
         entries.append(tune("precode", wl.U, code, lambda: api.precode_cg(
             Hx, T, dn.beta, wl.K, True, sc, qnorm=False, out=Q), log=log))
+        # the uplink + downlink slot, after its separate form's schedules
+        entries.append(tune("slot", wl.U, code, lambda: api.detect_precode_cg(
+            Hx, Yx, T, up.n0, up.es, dn.beta, wl.K, wl.K, wl.m, True, sc, qnorm=False,
+            out={"llr": llr, "Q": Q}), log=log))
     return entries
 
 

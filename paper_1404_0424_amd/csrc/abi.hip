@@ -71,7 +71,7 @@ int check_ptr(const void* p, const char* name, bool required) {
 // Process-wide table of kernel schedules, indexed by operation, user class
 // (U <= 16, U <= 32) and storage type; written by mimo_tune_set (the
 // autotuner), read at every launch.  Each entry packs variant | blocks << 8.
-constexpr int kOps = 3, kUClasses = 2, kDtypes = 3;
+constexpr int kOps = 4, kUClasses = 2, kDtypes = 3;
 std::atomic<int> g_sched[kOps][kUClasses][kDtypes];
 std::atomic<bool> g_sched_init{false};
 
@@ -90,6 +90,7 @@ void sched_defaults() {
       g_sched[MIMO_OP_DETECT][u][d].store(pack(mimo::kDetectStream, 0));
       g_sched[MIMO_OP_PRECODE][u][d].store(pack(mimo::kPrecodeResident, 8));
       g_sched[MIMO_OP_GRAM_MF][u][d].store(pack(mimo::kGramStream, 0));
+      g_sched[MIMO_OP_SLOT][u][d].store(pack(mimo::kSlotFused, 0));
     }
 }
 
@@ -104,6 +105,7 @@ int variant_count(int op) {
     case MIMO_OP_DETECT: return mimo::kDetectVariants;
     case MIMO_OP_PRECODE: return mimo::kPrecodeVariants;
     case MIMO_OP_GRAM_MF: return mimo::kGramVariants;
+    case MIMO_OP_SLOT: return mimo::kSlotVariants;
   }
   return 0;
 }
@@ -167,6 +169,11 @@ const char* mimo_tune_variant_name(int op, int variant) {
     switch (variant) {
       case mimo::kGramGeneric: return "generic";
       case mimo::kGramStream: return "stream";
+    }
+  } else if (op == MIMO_OP_SLOT) {
+    switch (variant) {
+      case mimo::kSlotSeparate: return "separate";
+      case mimo::kSlotFused: return "fused";
     }
   }
   return nullptr;
@@ -300,6 +307,57 @@ int mimo_precode_cg(const mimo_shape* shape, const void* H, const void* T, int i
                                          get_sched(MIMO_OP_PRECODE, shape->U, in_dtype),
                                          (hipStream_t)stream),
                     "precode_cg launch");
+}
+
+int mimo_detect_precode_cg(const mimo_shape* ul, const mimo_shape* dl, const void* H,
+                           const void* Y, const void* T, int in_dtype, float n0, float es,
+                           int qam_bits, float beta, int normalize, int scalar_prec,
+                           float* llr, void* xhat, float* mu, float* sinr, void* Q,
+                           float* qnorm, void* stream) {
+  g_last_error[0] = 0;
+  CHECK(check_shape(ul, true));
+  CHECK(check_shape(dl, true));
+  if (ul->B != dl->B || ul->U != dl->U || ul->n_sc != dl->n_sc)
+    return fail(MIMO_EINVAL, "uplink (B=%d, U=%d, n_sc=%lld) and downlink (B=%d, U=%d, "
+                "n_sc=%lld) shapes must share the channel", ul->B, ul->U, (long long)ul->n_sc,
+                dl->B, dl->U, (long long)dl->n_sc);
+  CHECK(check_dtype(in_dtype, ul->B));
+  if (!(n0 > 0.f) || !std::isfinite(n0)) return fail(MIMO_EINVAL, "n0=%g must be > 0", n0);
+  if (!(es > 0.f) || !std::isfinite(es)) return fail(MIMO_EINVAL, "es=%g must be > 0", es);
+  if (qam_bits != 2 && qam_bits != 4 && qam_bits != 6 && qam_bits != 8)
+    return fail(MIMO_EUNSUPPORTED, "qam_bits=%d not in {2,4,6,8}", qam_bits);
+  if (!(beta >= 0.f) || !std::isfinite(beta)) return fail(MIMO_EINVAL, "beta=%g must be >= 0", beta);
+  if (scalar_prec != MIMO_SCALAR_F32 && scalar_prec != MIMO_SCALAR_F64)
+    return fail(MIMO_EINVAL, "scalar_prec=%d unknown", scalar_prec);
+  CHECK(check_ptr(H, "H", true));
+  CHECK(check_ptr(Y, "Y", true));
+  CHECK(check_ptr(T, "T", true));
+  CHECK(check_ptr(llr, "llr", true));
+  CHECK(check_ptr(xhat, "xhat", false));
+  CHECK(check_ptr(mu, "mu", false));
+  CHECK(check_ptr(sinr, "sinr", false));
+  CHECK(check_ptr(Q, "Q", true));
+  CHECK(check_ptr(qnorm, "qnorm", false));
+  if (ul->n_sc == 0) return MIMO_OK;
+  const float scale = qam_scale(es, qam_bits);
+  mimo::SlotParams p{
+      mimo::DetectParams{H, Y, ul->B, ul->U, ul->S, ul->K, ul->n_sc, n0 / es, n0, es, scale,
+                         1.0f / scale, llr, (float2*)xhat, mu, sinr},
+      mimo::PrecodeParams{H, (const float2*)T, dl->B, dl->U, dl->S, dl->K, dl->n_sc, beta,
+                          normalize ? 1 : 0, (float2*)Q, qnorm}};
+  const int f64 = scalar_prec == MIMO_SCALAR_F64;
+  const mimo::Schedule sch = get_sched(MIMO_OP_SLOT, ul->U, in_dtype);
+  if (sch.variant == mimo::kSlotFused && mimo::slot_eligible(p, in_dtype))
+    return hip_status(mimo::launch_slot(p, f64, qam_bits, sch, (hipStream_t)stream),
+                      "detect_precode_cg launch");
+  CHECK(hip_status(mimo::launch_detect_approx(p.ul, in_dtype, f64, qam_bits,
+                                              get_sched(MIMO_OP_DETECT, ul->U, in_dtype),
+                                              (hipStream_t)stream),
+                   "detect_precode_cg: detection launch"));
+  return hip_status(mimo::launch_precode(p.dl, in_dtype, f64,
+                                         get_sched(MIMO_OP_PRECODE, dl->U, in_dtype),
+                                         (hipStream_t)stream),
+                    "detect_precode_cg: precoding launch");
 }
 
 // ---------------------------------------------------------------- Sec. III-F

@@ -181,22 +181,15 @@ __device__ __forceinline__ void matvec_valu(const AOperand<W>& at, const float2*
   }
 }
 
-// One iteration of Algorithm 1 (loop body) for the lane's 4 right-hand
-// sides.  alpha/beta are returned for the trackers.  A right-hand side whose
-// residual norm is zero (converged or b = 0) freezes: alpha = beta = 0.
-// Branch-free (selects), with the four right-hand sides' reductions
-// interleaved.
-// VALU: the mat-vec on VALU FMAs (matvec_valu) instead of MFMA.
-template <int W, typename ST, bool VALU = false>
-__device__ __forceinline__ void cg_step(CGState<W, ST>& st, const AOperand<W>& at,
-                                        float2* __restrict__ Ps, int c, int g, ST (&alpha)[4],
-                                        ST (&beta)[4]) {
-  stage_vec<W>(Ps, c, g, st.p);
-  wave_lds_sync();
-  float2 e[W][4];
-  if constexpr (VALU) matvec_valu<W>(at, Ps, c, g, e);   // e_{k-1} = A p_{k-1}
-  else matvec_mfma<W>(at, Ps, c, g, e);
-  wave_lds_sync();
+// The part of one iteration of Algorithm 1 (loop body) after the mat-vec
+// e = A p, for the lane's 4 right-hand sides: step size, v, r, residual
+// norm, beta, p.  alpha/beta are returned for the trackers.  A right-hand
+// side whose residual norm is zero (converged or b = 0) freezes: alpha =
+// beta = 0.  Branch-free (selects), with the four right-hand sides'
+// reductions interleaved.
+template <int W, typename ST>
+__device__ __forceinline__ void cg_update(CGState<W, ST>& st, const float2 (&e)[W][4],
+                                          ST (&alpha)[4], ST (&beta)[4]) {
   ST pe[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -239,6 +232,44 @@ __device__ __forceinline__ void cg_step(CGState<W, ST>& st, const AOperand<W>& a
     }
     st.rr[j] = live[j] ? rr_new[j] : st.rr[j];
   }
+}
+
+// One iteration of Algorithm 1 (loop body): P through LDS, e = A p, then
+// cg_update.
+// VALU: the mat-vec on VALU FMAs (matvec_valu) instead of MFMA.
+template <int W, typename ST, bool VALU = false>
+__device__ __forceinline__ void cg_step(CGState<W, ST>& st, const AOperand<W>& at,
+                                        float2* __restrict__ Ps, int c, int g, ST (&alpha)[4],
+                                        ST (&beta)[4]) {
+  stage_vec<W>(Ps, c, g, st.p);
+  wave_lds_sync();
+  float2 e[W][4];
+  if constexpr (VALU) matvec_valu<W>(at, Ps, c, g, e);   // e_{k-1} = A p_{k-1}
+  else matvec_mfma<W>(at, Ps, c, g, e);
+  wave_lds_sync();
+  cg_update<W, ST>(st, e, alpha, beta);
+}
+
+// One iteration each of two independent systems of the same subcarrier (the
+// uplink and downlink systems of a slot): their P go through LDS together
+// (Pa, Pb), both mat-vecs follow one exchange, and the two updates, which
+// do not depend on each other, can overlap.  Per system the operations are
+// those of cg_step, in the same order.
+template <int W, typename ST>
+__device__ __forceinline__ void cg_step2(CGState<W, ST>& sa, const AOperand<W>& ata,
+                                         float2* __restrict__ Pa, ST (&aa)[4], ST (&ba)[4],
+                                         CGState<W, ST>& sb, const AOperand<W>& atb,
+                                         float2* __restrict__ Pb, ST (&ab)[4], ST (&bb)[4],
+                                         int c, int g) {
+  stage_vec<W>(Pa, c, g, sa.p);
+  stage_vec<W>(Pb, c, g, sb.p);
+  wave_lds_sync();
+  float2 ea[W][4], eb[W][4];
+  matvec_mfma<W>(ata, Pa, c, g, ea);
+  matvec_mfma<W>(atb, Pb, c, g, eb);
+  wave_lds_sync();
+  cg_update<W, ST>(sa, ea, aa, ba);
+  cg_update<W, ST>(sb, eb, ab, bb);
 }
 
 template <int W, typename ST>

@@ -67,11 +67,8 @@ struct DetectStore {
 template <typename IN>
 constexpr bool kUncondMem = std::is_same<IN, InC32>::value || std::is_same<IN, InC32P>::value;
 
-// K iterations of Algorithm 1 with the tracker of eq. (13), then mu (eq. (14)),
-// rho (eq. (15)), z = xhat / mu and the LLRs (eq. (4)) of right-hand sides
-// s0 + 4 g + j of subcarrier n.  A^T, d and G_ii come from the Gram phase.
-// BUF: stores through buffer descriptors (no branches) or plain stores.
-// STAGE (all right-hand sides in this chunk): the subcarrier's LLR
+// LLR stores.  BUF: stores through buffer descriptors (no branches) or plain
+// stores.  STAGE (all right-hand sides in this chunk): the subcarrier's LLR
 // tile, U x S x M_BITS floats contiguous in memory, is assembled in `stg`
 // (wave-private LDS, free once the CG is done) and written with one
 // contiguous 16-byte (or 8-byte) piece per lane, so every store instruction
@@ -87,28 +84,15 @@ constexpr int kStagedStores = (16 * W * 16 * M_BITS / 2 + kWave - 1) / kWave;
 // xhat, mu and SINR outputs are not written, so a caller that counts
 // outstanding memory operations knows that this call adds exactly
 // kStagedStores<W, M_BITS> of them.
-template <int W, typename ST, int M_BITS, bool BUF, bool STAGE = false, bool FIXED_STORES = false,
-          bool VALU = false>
-__device__ __forceinline__ void cg_llr_epilogue(const DetectParams& prm, int64_t n, int s0,
-                                                const GramAcc<W>& acc, const AOperand<W>& at,
-                                                const float (&d)[W], const float* Gs,
-                                                float2* Ps, int c, int g,
-                                                float* __restrict__ stg = nullptr) {
+// mu (eq. (14)), rho (eq. (15)), z = xhat / mu and the LLRs (eq. (4)) of
+// right-hand sides s0 + 4 g + j of subcarrier n, from the CG solution v and
+// the tracker's v~ (tv), and their stores (BUF, STAGE, FIXED_STORES above).
+template <int W, typename ST, int M_BITS, bool BUF, bool STAGE = false, bool FIXED_STORES = false>
+__device__ __forceinline__ void llr_stage(const DetectParams& prm, int64_t n, int s0,
+                                          const float2 (&v)[W][4], const ST (&tv)[W][4],
+                                          const float* Gs, int c, int g,
+                                          float* __restrict__ stg = nullptr) {
   const int U = prm.U, S = prm.S;
-  float2 b[W][4];
-#pragma unroll
-  for (int w = 0; w < W; ++w)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) b[w][j] = make_float2(acc.dr[w][j], acc.di[w][j]);
-  CGState<W, ST> st;
-  cg_init<W, ST>(st, b);
-  Tracker<W, ST> tk;
-  tk.init();
-  for (int k = 0; k < prm.K; ++k) {
-    ST al[4], be[4];
-    cg_step<W, ST, VALU>(st, at, Ps, c, g, al, be);
-    tracker_step<W, ST>(tk, d, al, be);
-  }
   DetectStore<M_BITS> os;
   if (BUF || STAGE) os.init(prm, n);
 #pragma unroll
@@ -119,8 +103,8 @@ __device__ __forceinline__ void cg_llr_epilogue(const DetectParams& prm, int64_t
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int s = s0 + 4 * g + j;
-      const float mu = (float)(tk.tv[w][j] * (ST)Guu);
-      const float2 x = st.v[w][j];
+      const float mu = (float)(tv[w][j] * (ST)Guu);
+      const float2 x = v[w][j];
       // |mu| < FLT_MIN only when the right-hand side froze at (near) zero:
       // z = 0 as for b = 0.
       const float imu = fabsf(mu) >= __FLT_MIN__ ? __builtin_amdgcn_rcpf(mu) : 0.f;
@@ -157,24 +141,51 @@ __device__ __forceinline__ void cg_llr_epilogue(const DetectParams& prm, int64_t
 #pragma unroll
       for (int i = 0; i < kStagedStores<W, M_BITS>; ++i) {
         const int o = i * kWave + lane;
-        const float2 v = src[o < np ? o : 0];
-        bstore2(os.llr, o < np ? (uint32_t)o * 8u : kOOB, v.x, v.y);
+        const float2 q = src[o < np ? o : 0];
+        bstore2(os.llr, o < np ? (uint32_t)o * 8u : kOOB, q.x, q.y);
       }
     } else if ((total & 3) == 0) {                // 16-byte aligned tile
       const float4* src = (const float4*)stg;
       for (int o = lane; o < total / 4; o += kWave) {
-        const float4 v = src[o];
-        bstore4(os.llr, (uint32_t)o * 16u, v.x, v.y, v.z, v.w);
+        const float4 q = src[o];
+        bstore4(os.llr, (uint32_t)o * 16u, q.x, q.y, q.z, q.w);
       }
     } else {
       const float2* src = (const float2*)stg;
       for (int o = lane; o < total / 2; o += kWave) {
-        const float2 v = src[o];
-        bstore2(os.llr, (uint32_t)o * 8u, v.x, v.y);
+        const float2 q = src[o];
+        bstore2(os.llr, (uint32_t)o * 8u, q.x, q.y);
       }
     }
     wave_lds_sync();                              // stg is A / P of the next subcarrier
   }
+}
+
+// K iterations of Algorithm 1 with the tracker of eq. (13), then llr_stage
+// for right-hand sides s0 + 4 g + j of subcarrier n.  A^T, d and G_ii come
+// from the Gram phase, b = H^H y from acc.
+template <int W, typename ST, int M_BITS, bool BUF, bool STAGE = false, bool FIXED_STORES = false,
+          bool VALU = false>
+__device__ __forceinline__ void cg_llr_epilogue(const DetectParams& prm, int64_t n, int s0,
+                                                const GramAcc<W>& acc, const AOperand<W>& at,
+                                                const float (&d)[W], const float* Gs,
+                                                float2* Ps, int c, int g,
+                                                float* __restrict__ stg = nullptr) {
+  float2 b[W][4];
+#pragma unroll
+  for (int w = 0; w < W; ++w)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[w][j] = make_float2(acc.dr[w][j], acc.di[w][j]);
+  CGState<W, ST> st;
+  cg_init<W, ST>(st, b);
+  Tracker<W, ST> tk;
+  tk.init();
+  for (int k = 0; k < prm.K; ++k) {
+    ST al[4], be[4];
+    cg_step<W, ST, VALU>(st, at, Ps, c, g, al, be);
+    tracker_step<W, ST>(tk, d, al, be);
+  }
+  llr_stage<W, ST, M_BITS, BUF, STAGE, FIXED_STORES>(prm, n, s0, st.v, tk.tv, Gs, c, g, stg);
 }
 
 // Gram tiles -> LDS A, A^T operand and diagonal d = A_ii.

@@ -35,6 +35,14 @@ struct PrecodeParams {
   float* qnorm;         // [n_sc][S] or null
 };
 
+// One uplink + downlink slot on a reciprocal channel: detection and
+// precoding of the same subcarriers with the same H (ul.H == dl.H, equal B,
+// U and n_sc; S and K may differ).
+struct SlotParams {
+  DetectParams ul;
+  PrecodeParams dl;
+};
+
 struct GramParams {
   const void* H;
   const void* Y;        // may be null
@@ -91,6 +99,9 @@ enum { kDetectGeneric = 0, kDetectStream = 1, kDetectStreamSmall = 2, kDetectPla
        kDetectRing = 4, kDetectSplit = 5, kDetectValu = 6, kDetectVariants = 7 };
 enum { kPrecodeGeneric = 0, kPrecodeStream = 1, kPrecodeStreamSmall = 2, kPrecodeResident = 3,
        kPrecodeSplit = 4, kPrecodeVariants = 5 };
+// uplink + downlink slot: two launches (detection and precoding with their
+// own schedules), or one fused H-resident kernel
+enum { kSlotSeparate = 0, kSlotFused = 1, kSlotVariants = 2 };
 
 int num_compute_units();   // of the current device (cached per device)
 

@@ -1,0 +1,210 @@
+// One uplink + downlink slot on a reciprocal channel, fused per subcarrier:
+// CG-D detection (Sec. III-B/C, Algorithm 1, eqs. (4), (13)-(15)) of the
+// uplink receive vectors and CG-P precoding (Sec. III-D, eq. (16)) of the
+// downlink symbol vectors of the same subcarrier, in one wavefront.
+//
+// With H_d = H_u^H (reciprocity, Sec. II-B) both systems have the same Gram
+// matrix, G = H_u^H H_u = H_d H_d^H; they differ only in the diagonal shift:
+// A_u = G + (N0/E_s) I for detection and A_d = G + beta I for precoding.  G
+// is therefore formed once per subcarrier, and the subcarrier's channel,
+// held in registers from the Gram to the output contraction q = H_u v
+// (resident.hpp), crosses HBM once for both directions.
+//
+// Per subcarrier:
+//   1. G and the matched filter b = H^H y (MFMA), H from registers, Y
+//      streamed through a ring of NY k-steps;
+//   2. downlink: K_d CG iterations on A_d v = t, ||q||, q = H_u v (MFMA),
+//      output tiles staged and stored; the freed H registers receive the
+//      next subcarrier's channel;
+//   3. uplink: K_u CG iterations on A_u x = b with the approximate SINR
+//      tracker, mu, rho and max-log LLRs, while the next subcarrier's
+//      channel (and, from the LLR stage on, the first NY k-steps of its Y)
+//      are in flight.
+// Every step runs the same arithmetic in the same order as the detection and
+// precoding kernels, so LLRs (and xhat, mu, SINR), Q and qnorm are bitwise
+// those of mimo_detect_cg and mimo_precode_cg on the same inputs.
+#include <type_traits>
+
+#include "detect_core.hpp"
+#include "launch.hpp"
+#include "resident.hpp"
+
+namespace mimo {
+
+// Y rows of k-step t (antennas 4 t .. 4 t + 3) for lane (c, g): Y[4 t + g][c]
+template <typename Sub>
+__device__ __forceinline__ float2 load_y_step(const Sub& sb, int t) {
+  return bload2(sb.ry, sb.oy, (uint32_t)(4 * t) * sb.S * 8u);
+}
+
+// Matched-filter MFMAs of one k-step: the same expressions as the block's
+// own MF path, with y supplied from the ring.
+template <typename RB>
+__device__ __forceinline__ void mf_step(const RB& hk, float2 y, GramAcc<1>& acc) {
+  RB blk = hk;
+  blk.y[0] = y;
+  blk.template mma<false, true>(acc);
+}
+
+// Register budget: 2 waves per SIMD.  The channel (64 VGPRs at B = 128) is
+// held from the Gram to the output stage and the next subcarrier's is in
+// flight during the uplink stage, ~190 VGPRs in all; a 3-wave budget (168)
+// spills and measured slower (260 vs 253 us per 19,200 subcarriers of
+// 128x16 at K = 4).
+constexpr int kSlotMinBlocks = 2;
+
+template <int BMAX, typename IN, typename ST, int M_BITS>
+__global__ __launch_bounds__(256, kSlotMinBlocks) void slot_resident_kernel(SlotParams sp) {
+  constexpr int NU = 16, AST = NU + 2;
+  using Sub = typename Storage<IN, 1>::Sub;
+  using RB = typename ResidentBlock<IN>::type;
+  constexpr int NK = BMAX / RB::ANT;            // k-steps of H held in registers
+  constexpr int NY = 8;                         // k-steps of Y in flight (16, 32: no faster)
+  // per wave: A, P, the second H tile buffer and the output tile (float2),
+  // reused as the uplink LLR staging tile
+  constexpr int APH = 2 * (NU * AST + 2 * NU * kPST + 16 * 16);       // floats
+  constexpr int STG = NU * 16 * M_BITS;
+  __shared__ __align__(16) float W_s[kWavesPerBlock][APH > STG ? APH : STG];
+  __shared__ float G_s[kWavesPerBlock][NU];
+  __shared__ float N_s[kWavesPerBlock][16];
+  const DetectParams& ul = sp.ul;
+  const PrecodeParams& dl = sp.dl;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+  const int c = lane & 15, g = lane >> 4;
+  float2* As = (float2*)W_s[wv];
+  float2* Ps = As + NU * AST;
+  float2* H2 = Ps + NU * kPST;
+  float2* Qs = H2 + NU * kPST;                        // output tile of the downlink
+  float* Gs = G_s[wv];
+  float* Ns = N_s[wv];
+  const int B = ul.B, U = ul.U, Su = ul.S, Sd = dl.S;
+  const int64_t n_sc = ul.n_sc;
+  const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
+
+  int64_t n = (int64_t)blockIdx.x * kWavesPerBlock + wv;
+  RB hb[NK];
+  float2 yv[NY];
+  Sub cur;
+  if (n < n_sc) {
+    cur.init(offset_sc(IN{}, ul.H, n, B, U), offset_sc(IN{}, ul.Y, n, B, Su), B, U, Su, 0, c, g);
+#pragma unroll
+    for (int t = 0; t < NK; ++t) hb[t].template load<false, kOnceCPol>(cur, t * RB::ANT);
+#pragma unroll
+    for (int t = 0; t < NY; ++t) yv[t] = load_y_step(cur, t);
+  }
+  while (n < n_sc) {
+    const int64_t nn = n + stride;
+    const int64_t nc = nn < n_sc ? nn : n;            // descriptors only used if nn < n_sc
+    Sub nxt;
+    nxt.init(offset_sc(IN{}, ul.H, nc, B, U), offset_sc(IN{}, ul.Y, nc, B, Su), B, U, Su, 0, c,
+             g);
+    if (nn >= n_sc) nxt.disable();                    // last subcarrier: prefetch reads nothing
+    float2 bd[1][4];                                  // downlink right-hand sides b = t
+    {
+      const __amdgpu_buffer_rsrc_t rt = make_rsrc(dl.T + (size_t)n * U * Sd, (uint32_t)U * Sd * 8u);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {                   // T[c][4 g + j]
+        const int s = 4 * g + j;
+        bd[0][j] = bload2(rt, (c < U && s < Sd) ? (uint32_t)(c * Sd + s) * 8u : kOOB, 0u);
+      }
+    }
+    // ---- G = H^H H and b = H^H y (Algorithm 1, initialization)
+    GramAcc<1> acc;
+    acc.clear();
+#pragma unroll
+    for (int t = 0; t < NK; ++t) {
+      if (t * RB::ANT < B) {
+        hb[t].template mma<true, false>(acc);
+        mf_step(hb[t], yv[t % NY], acc);
+      }
+      if (t + NY < NK) yv[t % NY] = load_y_step(cur, t + NY);
+    }
+    finish_mf(IN{}, acc);
+    // A_u = G + (N0/E_s) I: A^T operand and d = diag(A_u); Gs = diag(G)
+    AOperand<1> at;
+    float d[1];
+    gram_to_operands<1>(IN{}, acc, As, Gs, Ps, AST, ul.reg, U, c, g, at, d);
+    // A_d = G + beta I: the diagonal of A_u replaced
+    AOperand<1> atd = at;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (c == 4 * t + g) atd.a[0][t] = make_float2(Gs[c] + dl.beta, 0.f);
+
+    // ---- downlink: K_d iterations on A_d v = t, then ||q||, q = H_u v; the
+    // freed H registers receive the next subcarrier's channel
+    {
+      CGState<1, ST> sd;
+      cg_init<1, ST>(sd, bd);
+      for (int k = 0; k < dl.K; ++k) {
+        ST al[4], be[4];
+        cg_step<1, ST>(sd, atd, Ps, c, g, al, be);
+      }
+      resident_output<BMAX, IN, ST>(dl, n, hb, nxt, atd, Gs, sd.v, Qs, H2, Ps, Ns, c, g, lane);
+    }
+    wave_lds_sync();                                  // output tiles read before reuse of LDS
+
+    // ---- uplink: K_u iterations on A_u x = b with the tracker, then mu,
+    // rho and the LLRs; the next subcarrier's first Y k-steps join its
+    // channel in flight before the LLR stage
+    CGState<1, ST> su;
+    {
+      float2 bu[1][4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bu[0][j] = make_float2(acc.dr[0][j], acc.di[0][j]);
+      cg_init<1, ST>(su, bu);
+    }
+    Tracker<1, ST> tk;
+    tk.init();
+    for (int k = 0; k < ul.K; ++k) {
+      ST al[4], be[4];
+      cg_step<1, ST>(su, at, Ps, c, g, al, be);
+      tracker_step<1, ST>(tk, d, al, be);
+    }
+#pragma unroll
+    for (int t = 0; t < NY; ++t) yv[t] = load_y_step(nxt, t);
+    llr_stage<1, ST, M_BITS, true, true>(ul, n, 0, su.v, tk.tv, Gs, c, g, W_s[wv]);
+    n = nn;
+    cur = nxt;
+  }
+}
+
+bool slot_eligible(const SlotParams& p, int in_dtype) {
+  return in_dtype == 0 && p.ul.U <= 16 && p.ul.S <= 16 && p.dl.S <= 16 && p.ul.B <= 128;
+}
+
+template <int BMAX, typename IN, typename ST>
+static hipError_t launch_m(const SlotParams& p, int m_bits, const Schedule& sch,
+                           hipStream_t stream) {
+  const dim3 grid(sched_grid(p.ul.n_sc, sch)), block(kWave * kWavesPerBlock);
+  switch (m_bits) {
+    case 2: hipLaunchKernelGGL((slot_resident_kernel<BMAX, IN, ST, 2>), grid, block, 0, stream, p); break;
+    case 4: hipLaunchKernelGGL((slot_resident_kernel<BMAX, IN, ST, 4>), grid, block, 0, stream, p); break;
+    case 6: hipLaunchKernelGGL((slot_resident_kernel<BMAX, IN, ST, 6>), grid, block, 0, stream, p); break;
+    case 8: hipLaunchKernelGGL((slot_resident_kernel<BMAX, IN, ST, 8>), grid, block, 0, stream, p); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename IN, typename ST>
+static hipError_t launch_b(const SlotParams& p, int m_bits, const Schedule& sch,
+                           hipStream_t stream) {
+  return p.ul.B <= 64 ? launch_m<64, IN, ST>(p, m_bits, sch, stream)
+                      : launch_m<128, IN, ST>(p, m_bits, sch, stream);
+}
+
+template <typename IN>
+static hipError_t launch_st(const SlotParams& p, int f64, int m_bits, const Schedule& sch,
+                            hipStream_t stream) {
+  return f64 ? launch_b<IN, double>(p, m_bits, sch, stream)
+             : launch_b<IN, float>(p, m_bits, sch, stream);
+}
+
+hipError_t launch_slot(const SlotParams& p, int scalar_f64, int m_bits, const Schedule& sch,
+                       hipStream_t stream) {
+  if (p.ul.U <= 8) return launch_st<InC32P>(p, scalar_f64, m_bits, sch, stream);
+  return launch_st<InC32>(p, scalar_f64, m_bits, sch, stream);
+}
+
+}  // namespace mimo

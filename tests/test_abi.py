@@ -174,6 +174,41 @@ def test_comparison_methods_validation():
     assert lib.mimo_precode_neumann(k0, P, P, 0, 0.1, 0, P2, None, None) == L.MIMO_EINVAL
 
 
+def _slot(ul, dl, **kw):
+    a = dict(H=P, Y=P, T=P, dt=0, n0=0.5, es=1.0, m=4, beta=0.5, norm=1, prec=0, llr=P2,
+             xhat=None, mu=None, sinr=None, Q=P2, qnorm=None)
+    a.update(kw)
+    return L.lib().mimo_detect_precode_cg(ul, dl, a["H"], a["Y"], a["T"], a["dt"], a["n0"],
+                                          a["es"], a["m"], a["beta"], a["norm"], a["prec"],
+                                          a["llr"], a["xhat"], a["mu"], a["sinr"], a["Q"],
+                                          a["qnorm"], None)
+
+
+def test_slot_validation_without_a_gpu():
+    """mimo_detect_precode_cg: both shapes must describe one channel (B, U,
+    n_sc); S and K may differ; every argument is checked before anything is
+    enqueued, and n_sc = 0 is a no-op."""
+    ul, dl = L.shape(32, 8, 14, 3, 4), L.shape(32, 8, 5, 6, 4)
+    for kw, want in ((dict(n0=0.0), L.MIMO_EINVAL), (dict(es=-1.0), L.MIMO_EINVAL),
+                     (dict(beta=-0.1), L.MIMO_EINVAL), (dict(beta=float("inf")), L.MIMO_EINVAL),
+                     (dict(m=5), L.MIMO_EUNSUPPORTED), (dict(prec=3), L.MIMO_EINVAL),
+                     (dict(dt=4), L.MIMO_EINVAL), (dict(H=None), L.MIMO_EINVAL),
+                     (dict(Y=None), L.MIMO_EINVAL), (dict(T=None), L.MIMO_EINVAL),
+                     (dict(llr=None), L.MIMO_EINVAL), (dict(Q=None), L.MIMO_EINVAL),
+                     (dict(qnorm=P2 + 4), L.MIMO_EINVAL), (dict(xhat=P + 8), L.MIMO_EINVAL)):
+        assert _slot(ul, dl, **kw) == want, kw
+        assert L.lib().mimo_last_error()
+    for other in (L.shape(64, 8, 5, 6, 4), L.shape(32, 4, 5, 6, 4), L.shape(32, 8, 5, 6, 5)):
+        assert _slot(ul, other) == L.MIMO_EINVAL
+        assert b"share the channel" in L.lib().mimo_last_error()
+    assert _slot(ul, L.shape(32, 8, 5, 0, 4)) == L.MIMO_EINVAL             # K_dl < 1
+    assert _slot(L.shape(32, 8, 0, 3, 4), dl) == L.MIMO_EINVAL             # S_ul < 1
+    assert _slot(L.shape(64, 33, 2, 3, 4), L.shape(64, 33, 2, 3, 4)) == L.MIMO_EUNSUPPORTED
+    assert _slot(L.shape(32, 8, 14, 3, 0), L.shape(32, 8, 5, 6, 0)) == L.MIMO_OK
+    assert L.lib().mimo_tune_variant_count(L.MIMO_OP_SLOT) == 2
+    assert L.lib().mimo_tune_variant_name(L.MIMO_OP_SLOT, 1) == b"fused"
+
+
 def test_status_strings():
     lib = L.lib()
     for st in (0, -1, -2, -3, -4):
