@@ -41,10 +41,14 @@ DETECT_KERNEL = {"generic": "detect_approx_kernel", "stream": "detect_stream_ker
 # translation units the complex64 approximate-SINR detection kernels are built from
 DETECT_SOURCES = ["detect.hip", "detect_core.hpp", "detect_ring.hip", "split.hip", "cg_core.hpp",
                   "gram_phase.hpp", "llr.hpp", "kernels.hpp", "common.hpp"]
+# ... and the fused uplink + downlink slot kernel
+SLOT_KERNEL = "slot_resident_kernel"
+SLOT_SOURCES = ["slot.hip", "resident.hpp", "precode_out.hpp", "detect_core.hpp", "cg_core.hpp",
+                "gram_phase.hpp", "llr.hpp", "kernels.hpp", "common.hpp"]
 PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
 
 
-def recorded_traffic(kernel, workload, n_sc, persistent=False):
+def recorded_traffic(kernel, workload, n_sc, persistent=False, sources=None):
     """HBM bytes per launch of ``kernel`` from the committed counter summary
     profiles/<kernel>_<workload>_c32.md (FETCH_SIZE + WRITE_SIZE passes,
     scaled by a plain copy of known size), for a grid of one wavefront per
@@ -63,7 +67,7 @@ def recorded_traffic(kernel, workload, n_sc, persistent=False):
                 k, v = line[3:].split("` = ", 1)
                 rec[k] = v.strip().strip("`")
     try:
-        if (rec.get("source_digest") != source_digest(DETECT_SOURCES)
+        if (rec.get("source_digest") != source_digest(sources or DETECT_SOURCES)
                 or int(rec["subcarriers_per_launch"]) != n_sc):
             return None
         key = "hbm_bytes_per_launch_persistent" if persistent else "hbm_bytes_per_launch"
@@ -82,6 +86,18 @@ def detect_bytes_per_sc(B, U, S, m, elem_bytes=8):
 def precode_bytes_per_sc(B, U, S, elem_bytes=8):
     """Read H and T, write Q (complex64)."""
     return elem_bytes * B * U + 8 * U * S + 8 * B * S
+
+
+def slot_bytes_per_sc(B, U, S, m, elem_bytes=8):
+    """Uplink + downlink slot on one channel: read H once, Y and T, write the
+    LLRs and Q."""
+    return (elem_bytes * B * U + elem_bytes * B * S + 8 * U * S + 4 * U * S * m
+            + 8 * B * S)
+
+
+def slot_fused_covers(B, U, S, storage="c32"):
+    """Whether mimo_detect_precode_cg runs the fused kernel for this shape."""
+    return storage == "c32" and U <= 16 and S <= 16 and B <= 128
 
 
 def main():
@@ -103,6 +119,9 @@ def main():
                     help="run detection under this schedule instead of tuning (e.g. stream-valu:0)")
     ap.add_argument("--precode-schedule", metavar="VARIANT:BLOCKS_PER_CU",
                     help="run precoding under this schedule instead of tuning (e.g. split:2)")
+    ap.add_argument("--slot-schedule", metavar="VARIANT:BLOCKS_PER_CU",
+                    help="run the uplink + downlink step under this schedule instead of tuning "
+                         "(fused:4, or separate:0 for the two launches)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-stream leg")
     ap.add_argument("--serving-frames", type=int, default=2000)
     ap.add_argument("--serving-skip", type=int, default=200,
@@ -149,7 +168,9 @@ def main():
     scalar = "f64" if wl.scalar_f64 else "f32"
     n0, es, beta, K, m = up.n0, up.es, dn.beta, wl.K, wl.m
 
-    def run_steps(Hx, Yx, steps):
+    def run_separate(Hx, Yx, steps):
+        """The step as two launches with events between them (per-kernel
+        times of detection and precoding)."""
         evs = []
         for _ in range(steps):
             e0 = torch.cuda.Event(enable_timing=True)
@@ -163,18 +184,40 @@ def main():
             evs.append((e0, e1, e2))
         return evs
 
-    def timed(Hx, Yx, label):
-        run_steps(Hx, Yx, args.warmup)
+    def slot_call(Hx, Yx):
+        api.detect_precode_cg(Hx, Yx, T, n0, es, beta, K, K, m, True, scalar, qnorm=False,
+                              out={"llr": llr, "Q": Q})
+
+    def run_slot(Hx, Yx, steps):
+        """The step as one mimo_detect_precode_cg call (its tuned schedule:
+        the fused kernel, or the two launches)."""
+        evs = []
+        for _ in range(steps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            slot_call(Hx, Yx)
+            e1.record()
+            evs.append((e0, e1))
+        return evs
+
+    def timed(Hx, Yx, label, separate=False):
+        run = run_separate if separate else run_slot
+        run(Hx, Yx, args.warmup)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        evs = run_steps(Hx, Yx, args.steps)
+        evs = run(Hx, Yx, args.steps)
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / args.steps
-        det = float(np.mean([a.elapsed_time(b) for a, b, _ in evs])) / 1e3
-        pre = float(np.mean([b.elapsed_time(c) for _, b, c in evs])) / 1e3
-        log(f"{label}: {wall * 1e3:.3f} ms/step (detect {det * 1e3:.3f} ms, "
-            f"precode {pre * 1e3:.3f} ms)")
-        return wall, det, pre
+        if separate:
+            det = float(np.mean([a.elapsed_time(b) for a, b, _ in evs])) / 1e3
+            pre = float(np.mean([b.elapsed_time(c) for _, b, c in evs])) / 1e3
+            log(f"{label}: {wall * 1e3:.3f} ms/step (detect {det * 1e3:.3f} ms, "
+                f"precode {pre * 1e3:.3f} ms)")
+            return wall, det, pre
+        ker = float(np.mean([a.elapsed_time(b) for a, b in evs])) / 1e3
+        log(f"{label}: {wall * 1e3:.3f} ms/step ({ker * 1e3:.3f} ms between the step's events)")
+        return wall, ker
 
     def kernel_time(fn, reps=20):
         """Average duration of back-to-back launches between two events on
@@ -191,15 +234,17 @@ def main():
 
     from paper_1404_0424_amd import autotune
     tuned = {}
+    ops = ("detect", "precode", "slot")
     if args.schedules:
         autotune.load(args.schedules)
-        for op in ("detect", "precode"):
+        for op in ops:
             v, b = autotune.get_schedule(op, wl.U, 0)
             tuned[op] = {"variant": autotune.variants(op)[v], "blocks_per_cu": b,
                          "from": os.path.basename(args.schedules)}
         log(f"loaded schedules: {tuned}")
-    elif args.detect_schedule or args.precode_schedule:
-        for op, spec in (("detect", args.detect_schedule), ("precode", args.precode_schedule)):
+    elif args.detect_schedule or args.precode_schedule or args.slot_schedule:
+        for op, spec in zip(ops, (args.detect_schedule, args.precode_schedule,
+                                  args.slot_schedule)):
             if spec:
                 name, bpc = spec.split(":")
                 autotune.set_schedule(op, wl.U, 0, autotune.variants(op).index(name), int(bpc))
@@ -207,35 +252,39 @@ def main():
             tuned[op] = {"variant": autotune.variants(op)[v], "blocks_per_cu": b, "from": "command line"}
         log(f"schedules: {tuned}")
     elif not args.no_tune:
-        # schedules picked by the autotuner on these inputs (not timed)
+        # schedules picked by the autotuner on these inputs (not timed); the
+        # slot's "separate" form runs the two tuned schedules
         e1 = autotune.tune("detect", wl.U, 0, lambda: api.detect_cg(
             H, Y, n0, es, K, m, "approx", scalar, out={"llr": llr}))
         e2 = autotune.tune("precode", wl.U, 0, lambda: api.precode_cg(
             H, T, beta, K, normalize=True, scalar_prec=scalar, qnorm=False, out=Q))
+        e3 = autotune.tune("slot", wl.U, 0, lambda: slot_call(H, Y))
         if args.save_schedules:
-            autotune.save([e1, e2], args.save_schedules)
-        for e in (e1, e2):
+            autotune.save([e1, e2, e3], args.save_schedules)
+        for e in (e1, e2, e3):
             b = e["best"]
             tuned[e["op"]] = {"variant": autotune.variants(e["op"])[b["variant"]],
                               "blocks_per_cu": b["blocks_per_cu"],
                               "us": round(b["seconds"] * 1e6, 1)}
         log(f"autotuned schedules: {tuned}")
 
-    # det_s / pre_s: average launch durations from the events around each
-    # launch of the timed steps (the roofline uses these)
-    wall, det_s, pre_s = timed(H, Y, "complex64")
+    # the step: one mimo_detect_precode_cg call; slot_s = average time
+    # between the events around it in the timed steps (the roofline uses it)
+    wall, slot_s = timed(H, Y, "complex64 slot")
     wall_eager = wall
+    # context: the same step as two launches (detection, then precoding)
+    wall_sep, det_s, pre_s = timed(H, Y, "complex64 separate launches", separate=True)
     det_b2b = kernel_time(lambda: api.detect_cg(H, Y, n0, es, K, m, "approx", scalar,
                                                 out={"llr": llr}))
     pre_b2b = kernel_time(lambda: api.precode_cg(H, T, beta, K, normalize=True,
                                                  scalar_prec=scalar, qnorm=False, out=Q))
-    log(f"back-to-back: detect {det_b2b * 1e3:.3f} ms, precode {pre_b2b * 1e3:.3f} ms per launch")
+    slot_b2b = kernel_time(lambda: slot_call(H, Y))
+    log(f"back-to-back: detect {det_b2b * 1e3:.3f} ms, precode {pre_b2b * 1e3:.3f} ms, "
+        f"slot {slot_b2b * 1e3:.3f} ms per launch")
 
     # the same step captured once as a hipGraph and replayed
     from paper_1404_0424_amd.graphs import StepGraph
-    g = StepGraph(lambda: (api.detect_cg(H, Y, n0, es, K, m, "approx", scalar, out={"llr": llr}),
-                           api.precode_cg(H, T, beta, K, normalize=True, scalar_prec=scalar,
-                                          qnorm=False, out=Q)))
+    g = StepGraph(lambda: slot_call(H, Y))
     for _ in range(args.warmup):
         g.replay()
     torch.cuda.synchronize()
@@ -264,23 +313,37 @@ def main():
     # a solve is one (subcarrier, OFDM symbol) system; a step solves each of
     # the batch's n x S systems twice, once by uplink detection and once by
     # downlink precoding, and `value` counts both (uplink.solves_per_s is the
-    # detection-only rate over the detection kernel's time)
+    # detection-only rate over the separate detection kernel's time)
     solves = 2 * n * wl.S
     llr_bits = n * wl.S * wl.U * wl.m
     det_bytes = detect_bytes_per_sc(wl.B, wl.U, wl.S, wl.m) * n
     pre_bytes = precode_bytes_per_sc(wl.B, wl.U, wl.S) * n
-    achieved = det_bytes / det_s / 1e9
+    slot_v, slot_bpc = autotune.get_schedule("slot", wl.U, 0)
+    fused = (autotune.variants("slot")[slot_v] == "fused"
+             and slot_fused_covers(wl.B, wl.U, wl.S))
     det_v, det_bpc = autotune.get_schedule("detect", wl.U, 0)
-    det_kernel = DETECT_KERNEL[autotune.variants("detect")[det_v]]
-    traffic = recorded_traffic(det_kernel, wl.name, n, persistent=det_bpc > 0)
+    if fused:
+        # dominant (only) kernel of the step: the fused slot kernel
+        dom_kernel, dom_bps = SLOT_KERNEL, slot_bytes_per_sc(wl.B, wl.U, wl.S, wl.m)
+        dom_s, dom_bpc, dom_src = slot_s, slot_bpc, SLOT_SOURCES
+        dom_mfma = mfma_count(wl.B, wl.U, wl.S, wl.K, "slot")
+    else:
+        dom_kernel = DETECT_KERNEL[autotune.variants("detect")[det_v]]
+        dom_bps = detect_bytes_per_sc(wl.B, wl.U, wl.S, wl.m)
+        dom_s, dom_bpc, dom_src = det_s, det_bpc, DETECT_SOURCES
+        dom_mfma = mfma_count(wl.B, wl.U, wl.S, wl.K, "detect")
+    dom_bytes = dom_bps * n
+    achieved = dom_bytes / dom_s / 1e9
+    traffic = recorded_traffic(dom_kernel, wl.name, n, persistent=dom_bpc > 0, sources=dom_src)
     # reference: a plain device copy moving the same number of bytes (half
     # read, half written), timed the same way
-    src = torch.empty(det_bytes // 8, dtype=torch.float32, device=dev).fill_(1.0)
+    src = torch.empty(dom_bytes // 8, dtype=torch.float32, device=dev).fill_(1.0)
     dst = torch.empty_like(src)
     copy_s = kernel_time(lambda: dst.copy_(src), reps=10)
     copy_gbs = 2 * src.numel() * 4 / copy_s / 1e9
     del src, dst
-    log(f"device copy of the same byte count: {copy_gbs:.0f} GB/s; detection {achieved:.0f} GB/s")
+    log(f"device copy of the same byte count: {copy_gbs:.0f} GB/s; {dom_kernel} "
+        f"{achieved:.0f} GB/s")
 
     result = {
         "metric": METRIC,
@@ -297,16 +360,25 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "B": wl.B, "U": wl.U, "subcarriers_per_frame": wl.n_sc,
                    "S": wl.S, "qam_bits": wl.m, "K": wl.K, "snr_db": snr, "channel": wl.channel,
-                   "frames_per_step": F, "step": "uplink detection + downlink precoding",
+                   "frames_per_step": F,
+                   "step": "uplink detection + downlink precoding on the same (reciprocal) "
+                           "channels, one mimo_detect_precode_cg call",
                    "storage": "complex64"},
         "llr_gbit_s": llr_bits / wall / 1e9,
         "schedules": tuned,
         "launch": launch,
         "eager_ms_per_step": wall_eager * 1e3,
         "graph_ms_per_step": wall_graph * 1e3,
+        "slot_kernel_ms": slot_s * 1e3,
+        "slot_kernel_ms_back_to_back": slot_b2b * 1e3,
+        "separate_launches": {"ms_per_step": wall_sep * 1e3,
+                              "solves_per_s": solves / wall_sep,
+                              "what": "the same step as mimo_detect_cg then mimo_precode_cg "
+                                      "(H read and the Gram formed once per direction)"},
         "plain_fp32_per_system": plain,
         "uplink": {"solves_per_s": n * wl.S / det_s, "llr_gbit_s": llr_bits / det_s / 1e9,
-                   "kernel_ms": det_s * 1e3, "hbm_gbs": achieved,
+                   "kernel_ms": det_s * 1e3, "hbm_gbs": det_bytes / det_s / 1e9,
+                   "hbm_frac": det_bytes / det_s / 1e9 / HBM_PEAK_GBS,
                    "kernel_ms_back_to_back": det_b2b * 1e3},
         "downlink": {"solves_per_s": n * wl.S / pre_s, "kernel_ms": pre_s * 1e3,
                      "hbm_gbs": pre_bytes / pre_s / 1e9,
@@ -315,11 +387,13 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic["bytes_per_launch"] if traffic else None,
                      "traffic_source": traffic["file"] if traffic else None,
-                     "kernel": det_kernel,
+                     "kernel": dom_kernel,
                      "copy_reference_gbs": copy_gbs,
                      "frac_of_copy": achieved / copy_gbs,
-                     "bytes_per_subcarrier": detect_bytes_per_sc(wl.B, wl.U, wl.S, wl.m),
-                     "subcarriers_per_launch": n},
+                     "bytes_per_subcarrier": dom_bps,
+                     "subcarriers_per_launch": n,
+                     "mfma_issued_tflops": dom_mfma * n * MFMA_FLOPS / dom_s / 1e12,
+                     "mfma_frac": dom_mfma * n * MFMA_FLOPS / dom_s / MFMA_PEAK_FP32},
     }
 
     samples = []          # GPU results checked against the oracle in the baseline leg
@@ -333,7 +407,7 @@ def main():
                     H16, Y16, n0, es, K, m, "approx", scalar, out={"llr": llr}))
                 autotune.tune("precode", wl.U, H16.dtype_code, lambda: api.precode_cg(
                     H16, T, beta, K, normalize=True, scalar_prec=scalar, qnorm=False, out=Q))
-            w2, d2, p2 = timed(H16, Y16, dt)
+            w2, d2, p2 = timed(H16, Y16, dt, separate=True)
             o = api.detect_cg(H16, Y16, n0, es, K, m, "approx", scalar, xhat=True,
                               out={"llr": llr})
             api.precode_cg(H16, T, beta, K, normalize=True, scalar_prec=scalar, qnorm=False,
@@ -380,8 +454,8 @@ def main():
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record()
-            api.detect_cg(H1, Y1, n0, es, K, m, "approx", scalar, out={"llr": l1})
-            api.precode_cg(H1, T1, beta, K, normalize=True, scalar_prec=scalar, qnorm=False, out=Q1)
+            api.detect_precode_cg(H1, Y1, T1, n0, es, beta, K, K, m, True, scalar, qnorm=False,
+                                  out={"llr": l1, "Q": Q1})
             e1.record()
             torch.cuda.synchronize()
             if i >= 10:
@@ -523,6 +597,10 @@ def mfma_count(B, U, S, K, op):
     matvec = 4 * W * nk
     if op == "detect":
         return gram + chunks * (mf + K * matvec)
+    if op == "slot":
+        # one Gram; uplink matched filter and K mat-vecs; downlink K + 1
+        # mat-vecs and q = H v
+        return gram + chunks * (mf + K * matvec + (K + 1) * matvec + (-(-B // 16)) * 3 * nk)
     # precode: Gram, K mat-vecs + one for ||q||^2, q = H v per 16-antenna tile
     return gram + chunks * ((K + 1) * matvec + (-(-B // 16)) * 3 * nk)
 
@@ -556,10 +634,15 @@ def configs_leg(api, autotune, kernel_time, dev, samples):
             fd = lambda: api.detect_cg(H, Y, up.n0, up.es, wl.K, wl.m, "approx", scalar,
                                        out={"llr": llr})
             fp = lambda: api.precode_cg(H, T, dn.beta, wl.K, True, scalar, qnorm=False, out=Q)
+            fs = lambda: api.detect_precode_cg(H, Y, T, up.n0, up.es, dn.beta, wl.K, wl.K,
+                                               wl.m, True, scalar, qnorm=False,
+                                               out={"llr": llr, "Q": Q})
             if snr == snrs[0]:
                 autotune.tune("detect", wl.U, 0, fd)
                 autotune.tune("precode", wl.U, 0, fp)
-            td, tp = kernel_time(fd, reps=10), kernel_time(fp, reps=10)
+                autotune.tune("slot", wl.U, 0, fs)
+            td, tp, ts = kernel_time(fd, reps=10), kernel_time(fp, reps=10), kernel_time(fs, reps=10)
+            sv, sb = autotune.get_schedule("slot", wl.U, 0)
             o = api.detect_cg(H, Y, up.n0, up.es, wl.K, wl.m, "approx", scalar, xhat=True,
                               out={"llr": llr})
             idx = sample_index(n, 24, 3)
@@ -576,7 +659,10 @@ def configs_leg(api, autotune, kernel_time, dev, samples):
                 "llr_gbit_s": n * wl.S * wl.U * wl.m / td / 1e9,
                 "detect_hbm_gbs": det_b / td / 1e9, "detect_frac": det_b / td / 1e9 / HBM_PEAK_GBS,
                 "detect_mfma_tflops": mf / td / 1e12,
-                "detect_mfma_frac": mf / td / MFMA_PEAK_FP32}
+                "detect_mfma_frac": mf / td / MFMA_PEAK_FP32,
+                "slot_ms": ts * 1e3, "slot_solves_per_s": 2 * n * wl.S / ts,
+                "slot_schedule": {"variant": autotune.variants("slot")[sv], "blocks_per_cu": sb,
+                                  "fused_kernel": slot_fused_covers(wl.B, wl.U, wl.S)}}
             if name in ("mixed_128x32", "corr_256x32") and snr == snrs[0]:
                 fg = lambda: api.gram_mf(H, Y, up.n0 / up.es)
                 eg = autotune.tune("gram_mf", wl.U, 0, fg)
@@ -591,7 +677,7 @@ def configs_leg(api, autotune, kernel_time, dev, samples):
                     "what": "standalone mimo_gram_mf (A = H^H H + reg I and b = H^H Y)"}
             log(f"config {name} ({F} frames) {snr:g} dB: detect {td * 1e3:.3f} ms "
                 f"({det_b / td / 1e9:.0f} GB/s, MFMA {mf / td / 1e12:.1f} TF), "
-                f"precode {tp * 1e3:.3f} ms"
+                f"precode {tp * 1e3:.3f} ms, slot {ts * 1e3:.3f} ms"
                 + (f"; Gram stage {rows[f'{snr:g}dB']['gram_stage']['mfma_frac']:.2f} of FP32 "
                    f"MFMA peak" if "gram_stage" in rows[f"{snr:g}dB"] else ""))
             del H, Y, T, llr, Q
