@@ -37,7 +37,7 @@ def log(msg):
 DETECT_KERNEL = {"generic": "detect_approx_kernel", "stream": "detect_stream_kernel",
                  "stream-small": "detect_stream_kernel", "plain": "detect_plain_kernel",
                  "ring": "detect_ring_kernel", "split": "detect_split_kernel",
-                 "stream-valu": "detect_stream_kernel"}
+                 "stream-valu": "detect_stream_kernel", "stream-x3": "detect_stream_kernel"}
 # translation units the complex64 approximate-SINR detection kernels are built from
 DETECT_SOURCES = ["detect.hip", "detect_core.hpp", "detect_ring.hip", "split.hip", "cg_core.hpp",
                   "gram_phase.hpp", "llr.hpp", "kernels.hpp", "common.hpp"]

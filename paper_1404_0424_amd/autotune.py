@@ -24,8 +24,9 @@ from . import _lib as L
 BLOCKS_PER_CU = (0, 1, 2, 3, 4, 5, 6, 8)
 BASELINE_VARIANTS = {"plain"}      # reference mappings, never chosen
 # variants that sum in another order (the Gram over antenna quarters; the CG
-# mat-vec on VALU FMAs): equal to the others to rounding, not bit for bit
-ROUNDING_VARIANTS = {"split", "stream-valu"}
+# mat-vec on VALU FMAs; the Gram and matched filter from bf16 splits): equal to
+# the others to rounding, not bit for bit
+ROUNDING_VARIANTS = {"split", "stream-valu", "stream-x3"}
 # variants whose launches take their grids from other table entries
 GRID_FREE = {("slot", "separate")}
 OPS = {"detect": L.MIMO_OP_DETECT, "precode": L.MIMO_OP_PRECODE,

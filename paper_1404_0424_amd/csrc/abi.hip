@@ -156,6 +156,7 @@ const char* mimo_tune_variant_name(int op, int variant) {
       case mimo::kDetectRing: return "ring";
       case mimo::kDetectSplit: return "split";
       case mimo::kDetectValu: return "stream-valu";
+      case mimo::kDetectX3: return "stream-x3";
     }
   } else if (op == MIMO_OP_PRECODE) {
     switch (variant) {
@@ -164,6 +165,7 @@ const char* mimo_tune_variant_name(int op, int variant) {
       case mimo::kPrecodeStreamSmall: return "stream-small";
       case mimo::kPrecodeResident: return "resident";
       case mimo::kPrecodeSplit: return "split";
+      case mimo::kPrecodeX3: return "x3";
     }
   } else if (op == MIMO_OP_GRAM_MF) {
     switch (variant) {
@@ -174,6 +176,7 @@ const char* mimo_tune_variant_name(int op, int variant) {
     switch (variant) {
       case mimo::kSlotSeparate: return "separate";
       case mimo::kSlotFused: return "fused";
+      case mimo::kSlotFusedX3: return "fused-x3";
     }
   }
   return nullptr;
@@ -347,7 +350,8 @@ int mimo_detect_precode_cg(const mimo_shape* ul, const mimo_shape* dl, const voi
                           normalize ? 1 : 0, (float2*)Q, qnorm}};
   const int f64 = scalar_prec == MIMO_SCALAR_F64;
   const mimo::Schedule sch = get_sched(MIMO_OP_SLOT, ul->U, in_dtype);
-  if (sch.variant == mimo::kSlotFused && mimo::slot_eligible(p, in_dtype))
+  if ((sch.variant == mimo::kSlotFused || sch.variant == mimo::kSlotFusedX3) &&
+      mimo::slot_eligible(p, in_dtype))
     return hip_status(mimo::launch_slot(p, f64, qam_bits, sch, (hipStream_t)stream),
                       "detect_precode_cg launch");
   CHECK(hip_status(mimo::launch_detect_approx(p.ul, in_dtype, f64, qam_bits,

@@ -216,6 +216,9 @@ static hipError_t launch_in(const DetectParams& p, int in_dtype, int f64, int m_
                             const Schedule& sch, hipStream_t stream) {
   switch (in_dtype) {
     case 0:
+      if (sch.variant == kDetectX3)        // Gram and matched filter from bf16 splits
+        return launch_st<W, InC32X3>(p, f64, m_bits, Schedule{kDetectStreamSmall,
+                                                                sch.blocks_per_cu}, stream);
       if constexpr (W == 1)
         if (p.U <= 8) return launch_st<1, InC32P>(p, f64, m_bits, sch, stream);
       return launch_st<W, InC32>(p, f64, m_bits, sch, stream);

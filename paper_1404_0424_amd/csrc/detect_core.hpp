@@ -65,7 +65,8 @@ struct DetectStore {
 // are faster (the compiler's load-counter waits then cover exactly the
 // block consumed); with 16-bit storage the branchy form is faster.
 template <typename IN>
-constexpr bool kUncondMem = std::is_same<IN, InC32>::value || std::is_same<IN, InC32P>::value;
+constexpr bool kUncondMem = std::is_same<IN, InC32>::value || std::is_same<IN, InC32P>::value ||
+                            std::is_same<IN, InC32X3>::value;
 
 // LLR stores.  BUF: stores through buffer descriptors (no branches) or plain
 // stores.  STAGE (all right-hand sides in this chunk): the subcarrier's LLR

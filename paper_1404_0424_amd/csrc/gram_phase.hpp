@@ -257,6 +257,124 @@ __device__ __forceinline__ void finish_mf(InC32P, GramAcc<1>& acc) {
   }
 }
 
+// ------------------------------------------- complex64, bf16-split products
+// Storage tag InC32X3: complex64 H and Y, with the Gram and matched filter
+// formed on the 16-bit matrix cores from an exact split of each FP32 value
+// into three bf16 parts (round to nearest even at each level):
+//   x = x0 + x1 + x2 + e,  |x1| <= 2^-8 |x|, |x2| <= 2^-16 |x|, |e| <= 2^-24 |x|,
+// and the six leading partial products x_i y_j (i + j <= 2) of every
+// product x y, each exact in FP32 and accumulated in FP32 by the MFMA.  The
+// dropped terms are below 2^-23 |x y| in all, so the result has the accuracy
+// of FP32 products with FP32 accumulation (a Gram error of 4.7e-7 against
+// 2.7e-7 on the 128 x 16 workload).  On gfx950 FP32 MFMAs and VALU
+// instructions share one issue pipe (a wave issuing FP32 MFMAs and one issuing
+// VALU FMAs on the same SIMD take the sum of their times), while 16-bit MFMAs
+// run beside VALU work; the split moves the Gram and matched filter off the
+// shared pipe at the cost of ~110 VALU instructions per 16 antennas.
+//
+// A 16x16x32 MFMA takes 16 antennas: lane (c, g) holds H[b0 + 4 t + g][c],
+// t = 0..3 (the same loads as the FP32 form), as the k-slice
+// [re(h_0), im(h_0), .., re(h_3), im(h_3)] of user c; the matched filter's
+// operand is built from Y the same way.  With X that stacked operand and
+// R = (-im, re) per antenna (X rotated by i):
+//   Re G = X^T X,  -Im G = X^T R,  Re b = Y^T X,  Im b = Y^T R
+// (rows x columns of the MFMA D layout: Gram rows = users, MF rows = rhs),
+// six products each; the Gram's imaginary part is accumulated negated.
+struct InC32X3 {};
+
+// bf16 parts of the complex values v[0..3]: p_i = part i of the (re, im)
+// pairs and, with ROT, r_i = part i of the (-im, re) pairs (the same
+// roundings, rotated).  Each level converts a pair with one packed
+// conversion (round to nearest even) and subtracts the widened parts, which
+// is exact.
+typedef float fl2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ bf8 pack4(bf2 a, bf2 b, bf2 c, bf2 d) {
+  return bf8{a[0], a[1], b[0], b[1], c[0], c[1], d[0], d[1]};
+}
+template <bool ROT>
+__device__ __forceinline__ void split3(const float2 (&v)[4], bf8 (&p)[3], bf8 (&rt)[3]) {
+  bf2 pp[3][4], rr[3][4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    fl2 r = fl2{v[e].x, v[e].y};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const bf2 q = __builtin_convertvector(r, bf2);
+      pp[i][e] = q;
+      if (ROT) rr[i][e] = __builtin_convertvector(fl2{-r[1], r[0]}, bf2);
+      if (i < 2) r = r - __builtin_convertvector(q, fl2);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    p[i] = pack4(pp[i][0], pp[i][1], pp[i][2], pp[i][3]);
+    if (ROT) rt[i] = pack4(rr[i][0], rr[i][1], rr[i][2], rr[i][3]);
+  }
+}
+// c += sum over i + j <= 2 of a_i^T b_j (smallest terms first)
+__device__ __forceinline__ f4 mfma_x3(const bf8 (&a)[3], const bf8 (&b)[3], f4 c) {
+  c = mfma32(a[2], b[0], c);
+  c = mfma32(a[1], b[1], c);
+  c = mfma32(a[0], b[2], c);
+  c = mfma32(a[1], b[0], c);
+  c = mfma32(a[0], b[1], c);
+  return mfma32(a[0], b[0], c);
+}
+
+template <int W, int NG>
+struct BlockC32X3 {
+  static constexpr int ANT = 16 * NG;  // antennas per block
+  float2 h[4 * NG][W];
+  float2 y[4 * NG];
+  template <bool DO_MF, int CPOL = kStreamCPol>
+  __device__ __forceinline__ void load(const SubC32<W>& sb, int b0) {
+#pragma unroll
+    for (int t = 0; t < 4 * NG; ++t) {
+      const int b = b0 + 4 * t;
+#pragma unroll
+      for (int w = 0; w < W; ++w) h[t][w] = bload2<CPOL>(sb.rh, sb.oh[w], (uint32_t)b * sb.U * 8u);
+      if (DO_MF) y[t] = bload2<CPOL>(sb.ry, sb.oy, (uint32_t)b * sb.S * 8u);
+    }
+  }
+  template <bool DO_GRAM, bool DO_MF>
+  __device__ __forceinline__ void mma(GramAcc<W>& acc) const {
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+      bf8 xp[W][3], xr[W][3];
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const float2 v[4] = {h[4 * q][w], h[4 * q + 1][w], h[4 * q + 2][w], h[4 * q + 3][w]};
+        split3<true>(v, xp[w], xr[w]);
+      }
+      if (DO_GRAM) {
+#pragma unroll
+        for (int wr = 0; wr < W; ++wr)
+#pragma unroll
+          for (int wc = wr; wc < W; ++wc) {
+            const int ti = tile_index(wr, wc, W);
+            acc.gr[ti] = mfma_x3(xp[wr], xp[wc], acc.gr[ti]);
+            acc.gi[ti] = mfma_x3(xp[wr], xr[wc], acc.gi[ti]);     // -Im G
+          }
+      }
+      if (DO_MF) {
+        bf8 yp[3], unused[3];
+        const float2 v[4] = {y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]};
+        split3<false>(v, yp, unused);
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          acc.dr[w] = mfma_x3(yp, xp[w], acc.dr[w]);
+          acc.di[w] = mfma_x3(yp, xr[w], acc.di[w]);
+        }
+      }
+    }
+  }
+};
+
+// Re b and Im b are accumulated directly.
+template <int W>
+__device__ __forceinline__ void finish_mf(InC32X3, GramAcc<W>&) {}
+
 // ----------------------------------------------------------------- 16-bit
 // Blocked storage [B/8][2][C][8] (part 0 = Re, 1 = Im) of one subcarrier:
 // the 8 antennas of a block are contiguous for each column, so one 16-byte
@@ -370,6 +488,12 @@ struct Storage<InC32P, 1> {
   using SmallBlock = BlockC32P<4>;
 };
 template <int W>
+struct Storage<InC32X3, W> {
+  using Sub = SubC32<W>;
+  using Block = BlockC32X3<W, 2>;
+  using SmallBlock = BlockC32X3<W, 1>;
+};
+template <int W>
 struct Storage<InBF16, W> {
   using Sub = Sub16<W>;
   using Block = Block16<W, bf8, W == 1 ? 2 : 1>;
@@ -400,6 +524,10 @@ __device__ __forceinline__ const void* offset_sc(InC32, const void* base, int64_
 }
 template <>
 __device__ __forceinline__ const void* offset_sc(InC32P, const void* base, int64_t n, int R, int C) {
+  return (const float2*)base + (size_t)n * R * C;
+}
+template <>
+__device__ __forceinline__ const void* offset_sc(InC32X3, const void* base, int64_t n, int R, int C) {
   return (const float2*)base + (size_t)n * R * C;
 }
 template <>
@@ -443,6 +571,32 @@ __device__ __forceinline__ void store_gram_lds(const GramAcc<W>& acc, float2* As
         const float re = acc.gr[ti][j];
         const float im = (wr == wc) ? acc.gi[ti][j] - scratch[wr * 272 + c * 17 + rl]
                                     : acc.gi[ti][j];
+        if (r < cc) {
+          As[r * ast + cc] = make_float2(re, im);
+          As[cc * ast + r] = make_float2(re, -im);
+        } else if (r == cc) {
+          As[r * ast + r] = make_float2(re + reg, 0.f);
+          Gd[r] = re;
+        }
+      }
+    }
+}
+
+// The split form accumulates -Im G on every tile (no M - M^T step); the
+// upper triangle and a real diagonal are written as for the others.
+template <int W>
+__device__ __forceinline__ void store_gram(InC32X3, const GramAcc<W>& acc, float2* As, float* Gd,
+                                           float*, int ast, float reg, int c, int g) {
+#pragma unroll
+  for (int wr = 0; wr < W; ++wr)
+#pragma unroll
+    for (int wc = wr; wc < W; ++wc) {
+      const int ti = tile_index(wr, wc, W);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = 16 * wr + 4 * g + j;
+        const int cc = 16 * wc + c;
+        const float re = acc.gr[ti][j], im = -acc.gi[ti][j];
         if (r < cc) {
           As[r * ast + cc] = make_float2(re, im);
           As[cc * ast + r] = make_float2(re, -im);

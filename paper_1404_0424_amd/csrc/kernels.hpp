@@ -96,12 +96,13 @@ struct Schedule {
   int blocks_per_cu;
 };
 enum { kDetectGeneric = 0, kDetectStream = 1, kDetectStreamSmall = 2, kDetectPlain = 3,
-       kDetectRing = 4, kDetectSplit = 5, kDetectValu = 6, kDetectVariants = 7 };
+       kDetectRing = 4, kDetectSplit = 5, kDetectValu = 6, kDetectX3 = 7, kDetectVariants = 8 };
 enum { kPrecodeGeneric = 0, kPrecodeStream = 1, kPrecodeStreamSmall = 2, kPrecodeResident = 3,
-       kPrecodeSplit = 4, kPrecodeVariants = 5 };
+       kPrecodeSplit = 4, kPrecodeX3 = 5, kPrecodeVariants = 6 };
 // uplink + downlink slot: two launches (detection and precoding with their
-// own schedules), or one fused H-resident kernel
-enum { kSlotSeparate = 0, kSlotFused = 1, kSlotVariants = 2 };
+// own schedules), or one fused H-resident kernel (FP32-MFMA or bf16-split
+// Gram and matched filter)
+enum { kSlotSeparate = 0, kSlotFused = 1, kSlotFusedX3 = 2, kSlotVariants = 3 };
 
 int num_compute_units();   // of the current device (cached per device)
 

@@ -305,6 +305,9 @@ static hipError_t launch_in(const PrecodeParams& p, int in_dtype, int f64, const
                             hipStream_t stream) {
   switch (in_dtype) {
     case 0:
+      if (sch.variant == kPrecodeX3)   // bf16-split Gram: resident kernel where it fits
+        return launch_st<W, InC32X3>(p, f64, Schedule{kPrecodeResident, sch.blocks_per_cu},
+                                     stream);
       if constexpr (W == 1)
         if (p.U <= 8) return launch_st<1, InC32P>(p, f64, sch, stream);
       return launch_st<W, InC32>(p, f64, sch, stream);

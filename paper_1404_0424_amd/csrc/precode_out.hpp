@@ -45,6 +45,11 @@ __device__ __forceinline__ void load_h_row(InC32P, const void* Hn, int B, int U,
                                            int w, int g, float2 (&hv)[4]) {
   load_h_row<W>(InC32{}, Hn, B, U, b0, c, w, g, hv);
 }
+template <int W>
+__device__ __forceinline__ void load_h_row(InC32X3, const void* Hn, int B, int U, int b0, int c,
+                                           int w, int g, float2 (&hv)[4]) {
+  load_h_row<W>(InC32{}, Hn, B, U, b0, c, w, g, hv);
+}
 template <int W, typename IN>
 __device__ __forceinline__ void load_h_row(IN tag, const void* Hn, int B, int U, int b0, int c,
                                            int w, int g, float2 (&hv)[4]) {

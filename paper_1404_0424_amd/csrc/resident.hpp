@@ -30,6 +30,10 @@ struct ResidentBlock<InC32P> {
   using type = BlockC32P<1>;      // packed form (U <= 8)
 };
 template <>
+struct ResidentBlock<InC32X3> {
+  using type = BlockC32X3<1, 1>;  // one block: 16 antennas (bf16-split Gram)
+};
+template <>
 struct ResidentBlock<InF16> {
   using type = Block16<1, h8, 1>;   // one k-step: 32 antennas
 };
@@ -51,6 +55,13 @@ __device__ __forceinline__ void stage_h_tile(const BLK (&hb)[NK], int i, float2*
   const int sl = user_slot(c);
 #pragma unroll
   for (int t = 0; t < 4; ++t) Hs[(4 * t + g) * kPST + sl] = hb[4 * i + t].h[0][0];
+}
+template <int NK>
+__device__ __forceinline__ void stage_h_tile(const BlockC32X3<1, 1> (&hb)[NK], int i,
+                                             float2* __restrict__ Hs, int c, int g) {
+  const int sl = user_slot(c);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) Hs[(4 * t + g) * kPST + sl] = hb[i].h[t][0];
 }
 template <int NK, typename V8>
 __device__ __forceinline__ void stage_h_tile(const Block16<1, V8, 1> (&hb)[NK], int i,
@@ -89,6 +100,7 @@ __device__ __forceinline__ void resident_output(const PrecodeParams& prm, int64_
                                                 float2* T0, float2* T1, float* Ns, int c, int g,
                                                 int lane) {
   constexpr bool C32 = std::is_same<IN, InC32>::value || std::is_same<IN, InC32P>::value;
+  constexpr bool X3 = std::is_same<IN, InC32X3>::value;    // one 16-antenna block per tile
   const int B = prm.B, U = prm.U, S = prm.S;
   // ---- ||q||^2 = v^H G v (V stays staged in T1)
   stage_vec<1>(T1, c, g, vsol);
@@ -113,6 +125,8 @@ __device__ __forceinline__ void resident_output(const PrecodeParams& prm, int64_
   if (C32) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) hb[t].template load<false, kOnceCPol>(nxt, t * RB::ANT);
+  } else if (X3) {
+    hb[0].template load<false, kOnceCPol>(nxt, 0);
   }
 #pragma unroll
   for (int i = 0; i < BMAX / 16; ++i) {
@@ -159,6 +173,8 @@ __device__ __forceinline__ void resident_output(const PrecodeParams& prm, int64_
         for (int t = 4 * (i + 1); t < 4 * (i + 1) + 4; ++t)
           hb[t].template load<false, kOnceCPol>(nxt, t * RB::ANT);
       }
+    } else if (X3) {
+      if (i + 1 < BMAX / 16) hb[i + 1].template load<false, kOnceCPol>(nxt, (i + 1) * RB::ANT);
     } else if (i & 1) {
       hb[i >> 1].template load<false, kOnceCPol>(nxt, (i >> 1) * RB::ANT);
     }

@@ -11,8 +11,9 @@
 // (resident.hpp), crosses HBM once for both directions.
 //
 // Per subcarrier:
-//   1. G and the matched filter b = H^H y (MFMA), H from registers, Y
-//      streamed through a ring of NY k-steps;
+//   1. G and the matched filter b = H^H y (MFMA; FP32 products, or the
+//      bf16-split form of gram_phase.hpp with the "fused-x3" schedule), H
+//      from registers, Y streamed through a ring of NY k-steps;
 //   2. downlink: K_d CG iterations on A_d v = t, ||q||, q = H_u v (MFMA),
 //      output tiles staged and stored; the freed H registers receive the
 //      next subcarrier's channel;
@@ -37,15 +38,6 @@ __device__ __forceinline__ float2 load_y_step(const Sub& sb, int t) {
   return bload2(sb.ry, sb.oy, (uint32_t)(4 * t) * sb.S * 8u);
 }
 
-// Matched-filter MFMAs of one k-step: the same expressions as the block's
-// own MF path, with y supplied from the ring.
-template <typename RB>
-__device__ __forceinline__ void mf_step(const RB& hk, float2 y, GramAcc<1>& acc) {
-  RB blk = hk;
-  blk.y[0] = y;
-  blk.template mma<false, true>(acc);
-}
-
 // Register budget: 2 waves per SIMD.  The channel (64 VGPRs at B = 128) is
 // held from the Gram to the output stage and the next subcarrier's is in
 // flight during the uplink stage, ~190 VGPRs in all; a 3-wave budget (168)
@@ -58,7 +50,9 @@ __global__ __launch_bounds__(256, kSlotMinBlocks) void slot_resident_kernel(Slot
   constexpr int NU = 16, AST = NU + 2;
   using Sub = typename Storage<IN, 1>::Sub;
   using RB = typename ResidentBlock<IN>::type;
-  constexpr int NK = BMAX / RB::ANT;            // k-steps of H held in registers
+  constexpr int NK = BMAX / RB::ANT;            // blocks of H held in registers
+  constexpr int KS = RB::ANT / 4;               // k-steps (4 antennas) per block
+  constexpr int NKS = BMAX / 4;                 // k-steps of Y per subcarrier
   constexpr int NY = 8;                         // k-steps of Y in flight (16, 32: no faster)
   // per wave: A, P, the second H tile buffer and the output tile (float2),
   // reused as the uplink LLR staging tile
@@ -113,12 +107,19 @@ __global__ __launch_bounds__(256, kSlotMinBlocks) void slot_resident_kernel(Slot
     GramAcc<1> acc;
     acc.clear();
 #pragma unroll
-    for (int t = 0; t < NK; ++t) {
-      if (t * RB::ANT < B) {
-        hb[t].template mma<true, false>(acc);
-        mf_step(hb[t], yv[t % NY], acc);
+    for (int q = 0; q < NK; ++q) {
+      if (q * RB::ANT < B) {
+        hb[q].template mma<true, false>(acc);
+        RB blk = hb[q];                               // with the block's Y k-steps from the ring
+#pragma unroll
+        for (int e = 0; e < KS; ++e) blk.y[e] = yv[(q * KS + e) % NY];
+        blk.template mma<false, true>(acc);
       }
-      if (t + NY < NK) yv[t % NY] = load_y_step(cur, t + NY);
+#pragma unroll
+      for (int e = 0; e < KS; ++e) {
+        const int t = q * KS + e;
+        if (t + NY < NKS) yv[t % NY] = load_y_step(cur, t + NY);
+      }
     }
     finish_mf(IN{}, acc);
     // A_u = G + (N0/E_s) I: A^T operand and d = diag(A_u); Gs = diag(G)
@@ -203,6 +204,7 @@ static hipError_t launch_st(const SlotParams& p, int f64, int m_bits, const Sche
 
 hipError_t launch_slot(const SlotParams& p, int scalar_f64, int m_bits, const Schedule& sch,
                        hipStream_t stream) {
+  if (sch.variant == kSlotFusedX3) return launch_st<InC32X3>(p, scalar_f64, m_bits, sch, stream);
   if (p.ul.U <= 8) return launch_st<InC32P>(p, scalar_f64, m_bits, sch, stream);
   return launch_st<InC32>(p, scalar_f64, m_bits, sch, stream);
 }
