@@ -205,7 +205,7 @@ def test_slot_validation_without_a_gpu():
     assert _slot(L.shape(32, 8, 0, 3, 4), dl) == L.MIMO_EINVAL             # S_ul < 1
     assert _slot(L.shape(64, 33, 2, 3, 4), L.shape(64, 33, 2, 3, 4)) == L.MIMO_EUNSUPPORTED
     assert _slot(L.shape(32, 8, 14, 3, 0), L.shape(32, 8, 5, 6, 0)) == L.MIMO_OK
-    assert L.lib().mimo_tune_variant_count(L.MIMO_OP_SLOT) == 2
+    assert L.lib().mimo_tune_variant_count(L.MIMO_OP_SLOT) == 3
     assert L.lib().mimo_tune_variant_name(L.MIMO_OP_SLOT, 1) == b"fused"
 
 
