@@ -254,11 +254,13 @@ def main():
     elif not args.no_tune:
         # schedules picked by the autotuner on these inputs (not timed); the
         # slot's "separate" form runs the two tuned schedules
+        # (FP32 products throughout: the bf16-split forms are timed apart)
+        x3 = autotune.X3_VARIANTS
         e1 = autotune.tune("detect", wl.U, 0, lambda: api.detect_cg(
-            H, Y, n0, es, K, m, "approx", scalar, out={"llr": llr}))
+            H, Y, n0, es, K, m, "approx", scalar, out={"llr": llr}), exclude=x3)
         e2 = autotune.tune("precode", wl.U, 0, lambda: api.precode_cg(
-            H, T, beta, K, normalize=True, scalar_prec=scalar, qnorm=False, out=Q))
-        e3 = autotune.tune("slot", wl.U, 0, lambda: slot_call(H, Y))
+            H, T, beta, K, normalize=True, scalar_prec=scalar, qnorm=False, out=Q), exclude=x3)
+        e3 = autotune.tune("slot", wl.U, 0, lambda: slot_call(H, Y), exclude=x3)
         if args.save_schedules:
             autotune.save([e1, e2, e3], args.save_schedules)
         for e in (e1, e2, e3):
@@ -281,6 +283,31 @@ def main():
     slot_b2b = kernel_time(lambda: slot_call(H, Y))
     log(f"back-to-back: detect {det_b2b * 1e3:.3f} ms, precode {pre_b2b * 1e3:.3f} ms, "
         f"slot {slot_b2b * 1e3:.3f} ms per launch")
+    # context: the same launches with the Gram and matched filter formed from
+    # bf16 splits of the FP32 inputs (FP32-accurate), each at its best grid
+    saved = {op: autotune.get_schedule(op, wl.U, 0) for op in ("detect", "precode", "slot")}
+    x3t = {}
+    for op, name, fn in (("detect", "stream-x3", lambda: api.detect_cg(
+                              H, Y, n0, es, K, m, "approx", scalar, out={"llr": llr})),
+                         ("precode", "x3", lambda: api.precode_cg(
+                              H, T, beta, K, normalize=True, scalar_prec=scalar, qnorm=False,
+                              out=Q)),
+                         ("slot", "fused-x3", lambda: slot_call(H, Y))):
+        best = None
+        for bpc in (0, 2, 4, 6, 8):
+            autotune.set_schedule(op, wl.U, 0, autotune.variants(op).index(name), bpc)
+            tt = kernel_time(fn)
+            best = tt if best is None else min(best, tt)
+        x3t[op] = best
+    for op, (v, b) in saved.items():
+        autotune.set_schedule(op, wl.U, 0, v, b)
+    split_x3 = {"detect_ms": x3t["detect"] * 1e3, "precode_ms": x3t["precode"] * 1e3,
+                "slot_ms": x3t["slot"] * 1e3, "slot_solves_per_s": 2 * n * wl.S / x3t["slot"],
+                "what": "back-to-back launches with the Gram and matched filter from an exact "
+                        "three-way bf16 split of the FP32 inputs on the 16-bit matrix cores "
+                        "(FP32 accumulation); not used for value"}
+    log(f"bf16-split Gram: detect {x3t['detect'] * 1e3:.3f} ms, precode "
+        f"{x3t['precode'] * 1e3:.3f} ms, slot {x3t['slot'] * 1e3:.3f} ms")
 
     # the same step captured once as a hipGraph and replayed
     from paper_1404_0424_amd.graphs import StepGraph
@@ -319,7 +346,7 @@ def main():
     det_bytes = detect_bytes_per_sc(wl.B, wl.U, wl.S, wl.m) * n
     pre_bytes = precode_bytes_per_sc(wl.B, wl.U, wl.S) * n
     slot_v, slot_bpc = autotune.get_schedule("slot", wl.U, 0)
-    fused = (autotune.variants("slot")[slot_v] == "fused"
+    fused = (autotune.variants("slot")[slot_v] in ("fused", "fused-x3")
              and slot_fused_covers(wl.B, wl.U, wl.S))
     det_v, det_bpc = autotune.get_schedule("detect", wl.U, 0)
     if fused:
@@ -376,6 +403,7 @@ def main():
                               "what": "the same step as mimo_detect_cg then mimo_precode_cg "
                                       "(H read and the Gram formed once per direction)"},
         "plain_fp32_per_system": plain,
+        "bf16_split_gram": split_x3,
         "uplink": {"solves_per_s": n * wl.S / det_s, "llr_gbit_s": llr_bits / det_s / 1e9,
                    "kernel_ms": det_s * 1e3, "hbm_gbs": det_bytes / det_s / 1e9,
                    "hbm_frac": det_bytes / det_s / 1e9 / HBM_PEAK_GBS,
@@ -638,11 +666,21 @@ def configs_leg(api, autotune, kernel_time, dev, samples):
                                                wl.m, True, scalar, qnorm=False,
                                                out={"llr": llr, "Q": Q})
             if snr == snrs[0]:
-                autotune.tune("detect", wl.U, 0, fd)
-                autotune.tune("precode", wl.U, 0, fp)
-                autotune.tune("slot", wl.U, 0, fs)
+                x3 = autotune.X3_VARIANTS
+                autotune.tune("detect", wl.U, 0, fd, exclude=x3)
+                autotune.tune("precode", wl.U, 0, fp, exclude=x3)
+                autotune.tune("slot", wl.U, 0, fs, exclude=x3)
             td, tp, ts = kernel_time(fd, reps=10), kernel_time(fp, reps=10), kernel_time(fs, reps=10)
             sv, sb = autotune.get_schedule("slot", wl.U, 0)
+            dsaved, psaved = autotune.get_schedule("detect", wl.U, 0), autotune.get_schedule(
+                "precode", wl.U, 0)
+            autotune.set_schedule("detect", wl.U, 0, autotune.variants("detect").index("stream-x3"),
+                                  dsaved[1])
+            autotune.set_schedule("precode", wl.U, 0, autotune.variants("precode").index("x3"),
+                                  psaved[1])
+            tdx, tpx = kernel_time(fd, reps=10), kernel_time(fp, reps=10)
+            autotune.set_schedule("detect", wl.U, 0, *dsaved)
+            autotune.set_schedule("precode", wl.U, 0, *psaved)
             o = api.detect_cg(H, Y, up.n0, up.es, wl.K, wl.m, "approx", scalar, xhat=True,
                               out={"llr": llr})
             idx = sample_index(n, 24, 3)
@@ -661,6 +699,7 @@ def configs_leg(api, autotune, kernel_time, dev, samples):
                 "detect_mfma_tflops": mf / td / 1e12,
                 "detect_mfma_frac": mf / td / MFMA_PEAK_FP32,
                 "slot_ms": ts * 1e3, "slot_solves_per_s": 2 * n * wl.S / ts,
+                "bf16_split_gram": {"detect_ms": tdx * 1e3, "precode_ms": tpx * 1e3},
                 "slot_schedule": {"variant": autotune.variants("slot")[sv], "blocks_per_cu": sb,
                                   "fused_kernel": slot_fused_covers(wl.B, wl.U, wl.S)}}
             if name in ("mixed_128x32", "corr_256x32") and snr == snrs[0]:

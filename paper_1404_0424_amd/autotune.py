@@ -26,7 +26,11 @@ BASELINE_VARIANTS = {"plain"}      # reference mappings, never chosen
 # variants that sum in another order (the Gram over antenna quarters; the CG
 # mat-vec on VALU FMAs; the Gram and matched filter from bf16 splits): equal to
 # the others to rounding, not bit for bit
-ROUNDING_VARIANTS = {"split", "stream-valu", "stream-x3"}
+ROUNDING_VARIANTS = {"split", "stream-valu", "stream-x3", "x3", "fused-x3"}
+# variants that form the Gram and matched filter from bf16 splits of the FP32
+# inputs (FP32-accurate, on the 16-bit matrix cores); a caller that wants FP32
+# products throughout excludes them
+X3_VARIANTS = {"stream-x3", "x3", "fused-x3"}
 # variants whose launches take their grids from other table entries
 GRID_FREE = {("slot", "separate")}
 OPS = {"detect": L.MIMO_OP_DETECT, "precode": L.MIMO_OP_PRECODE,
@@ -70,12 +74,13 @@ def time_call(fn, reps: int = 5, warmup: int = 2) -> float:
     return e0.elapsed_time(e1) / reps / 1e3
 
 
-def tune(op: str, U: int, dtype_code: int, fn, reps: int = 5, log=None) -> dict:
+def tune(op: str, U: int, dtype_code: int, fn, reps: int = 5, log=None, exclude=()) -> dict:
     """Time ``fn`` (which launches ``op`` on fixed inputs) under every
-    candidate schedule, install the fastest, return the measurements."""
+    candidate schedule (variants named in ``exclude`` left out), install the
+    fastest, return the measurements."""
     results = []
     for v, name in enumerate(variants(op)):
-        if name in BASELINE_VARIANTS:
+        if name in BASELINE_VARIANTS or name in exclude:
             continue
         for b in BLOCKS_PER_CU:
             if (op, name) in GRID_FREE and b != 0:
