@@ -46,7 +46,12 @@
 extern "C" {
 #endif
 
-#define MIMO_MAX_USERS 32   /* largest U supported */
+#define MIMO_MAX_USERS 64          /* largest U: mimo_detect_cg (approximate SINR),
+                                      mimo_precode_cg, mimo_detect_precode_cg with
+                                      complex64 storage */
+#define MIMO_MAX_USERS_COMMON 32   /* largest U of every other call, of 16-bit
+                                      storage and of the exact SINR; a larger U
+                                      there returns MIMO_EUNSUPPORTED */
 #define MIMO_MAX_ANTENNAS 4096
 /* Bound on one subcarrier's arrays: S * 8 * max(B, 4 U) bytes must be below
  * this (2^31), i.e. Y and Q (8 B S bytes) and the LLRs (up to 32 U S bytes)
@@ -55,7 +60,8 @@ extern "C" {
 
 typedef struct mimo_shape {
   int32_t B;     /* base-station antennas, U <= B <= MIMO_MAX_ANTENNAS */
-  int32_t U;     /* single-antenna users, 1 <= U <= MIMO_MAX_USERS */
+  int32_t U;     /* single-antenna users, 1 <= U <= B; U <= MIMO_MAX_USERS
+                    or MIMO_MAX_USERS_COMMON per entry point */
   int32_t S;     /* right-hand sides per subcarrier (OFDM symbols), >= 1,
                     S * 8 * max(B, 4 U) < MIMO_MAX_SPAN_BYTES */
   int32_t K;     /* CG iterations (Algorithm 1), 1 <= K <= 1024 */
@@ -122,6 +128,10 @@ int mimo_gram_mf(const mimo_shape* shape, const void* H, const void* Y,
  *   sinr  out, float [n_sc][U][S] or NULL
  *   workspace / workspace_bytes: may be NULL / 0 when
  *         mimo_workspace_bytes(shape, MIMO_OP_DETECT, sinr_mode) is 0.
+ * U up to MIMO_MAX_USERS_COMMON in every mode and storage type; beyond it,
+ * up to MIMO_MAX_USERS, with complex64 storage and MIMO_SINR_APPROX (four
+ * wavefronts per subcarrier, one per 16 users, any B and S); other calls
+ * with U > MIMO_MAX_USERS_COMMON return MIMO_EUNSUPPORTED.
  */
 int mimo_detect_cg(const mimo_shape* shape, const void* H, const void* Y,
                    int in_dtype, float n0, float es, int qam_bits,
@@ -138,6 +148,8 @@ int mimo_detect_cg(const mimo_shape* shape, const void* H, const void* Y,
  * ||q|| = 0 gives s = 0).  qnorm receives ||q||_2 either way.
  *   H  [n_sc][B][U] storage type in_dtype;  T complex64 [n_sc][U][S]
  *   beta >= 0;  Q out complex64 [n_sc][B][S];  qnorm out float [n_sc][S] or NULL
+ * U beyond MIMO_MAX_USERS_COMMON (up to MIMO_MAX_USERS) with complex64
+ * storage only, as mimo_detect_cg.
  */
 int mimo_precode_cg(const mimo_shape* shape, const void* H, const void* T,
                     int in_dtype, float beta, int normalize, int scalar_prec,
@@ -163,7 +175,8 @@ int mimo_precode_cg(const mimo_shape* shape, const void* H, const void* T,
  * mimo_precode_cg(dl, ...) on the same inputs.  The fused kernel covers
  * complex64 storage with U <= 16, B <= 128 and S <= 16 in both directions;
  * other calls (and the schedule variant "separate") run the two operations
- * as two launches on `stream`.
+ * as two launches on `stream`.  U up to MIMO_MAX_USERS as mimo_detect_cg
+ * and mimo_precode_cg (complex64 storage beyond MIMO_MAX_USERS_COMMON).
  */
 int mimo_detect_precode_cg(const mimo_shape* ul, const mimo_shape* dl, const void* H,
                            const void* Y, const void* T, int in_dtype, float n0, float es,
@@ -281,7 +294,8 @@ int mimo_precode_cgls(const mimo_shape* shape, const void* H, const void* T,
  * is mapped onto the GPU).  Each operation has kernel variants and a grid
  * size; the pair used for (op, user class, storage type) comes from a
  * process-wide table that an autotuner fills by timing the variants.
- *   user_class    0: U <= 16, 1: 16 < U <= 32
+ *   user_class    0: U <= 16, 1: 16 < U <= 32 (calls with a larger U run
+ *                 the four-wavefront kernels whatever the table holds)
  *   variant       0 .. mimo_tune_variant_count(op) - 1 (detection: 0 generic,
  *                 1 stream = next subcarrier's loads in flight during CG,
  *                 2 stream with half-size load blocks; variant 1/2 apply for

@@ -16,7 +16,8 @@ MIMO_SINR_APPROX, MIMO_SINR_EXACT = 0, 1
 MIMO_SCALAR_F32, MIMO_SCALAR_F64 = 0, 1
 MIMO_OP_GRAM_MF, MIMO_OP_DETECT, MIMO_OP_PRECODE, MIMO_OP_SLOT = 0, 1, 2, 3
 MIMO_OK, MIMO_EINVAL, MIMO_EUNSUPPORTED, MIMO_EWORKSPACE, MIMO_EHIP = 0, -1, -2, -3, -4
-MIMO_MAX_USERS = 32
+MIMO_MAX_USERS = 64
+MIMO_MAX_USERS_COMMON = 32
 MIMO_MAX_ANTENNAS = 4096
 MIMO_MAX_SPAN_BYTES = 1 << 31
 

@@ -21,7 +21,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmimocg.so")
 SOURCES = ["abi.hip", "detect.hip", "detect_ring.hip", "precode.hip", "exact.hip", "gram_mf.hip", "plain.hip",
-           "inverse.hip", "cgls.hip", "serve.hip", "split.hip", "slot.hip"]
+           "inverse.hip", "cgls.hip", "serve.hip", "split.hip", "slot.hip",
+           "wide.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

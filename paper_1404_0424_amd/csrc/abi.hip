@@ -30,11 +30,23 @@ int hip_status(hipError_t e, const char* what) {
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
-int check_shape(const mimo_shape* s, bool need_k) {
+// Calls with U > MIMO_MAX_USERS_COMMON run the four-wavefront kernels, built
+// for complex64 storage.
+int check_wide(int U, int in_dtype) {
+  if (U > MIMO_MAX_USERS_COMMON && in_dtype != MIMO_C32)
+    return fail(MIMO_EUNSUPPORTED, "U=%d > %d needs complex64 storage", U,
+                MIMO_MAX_USERS_COMMON);
+  return MIMO_OK;
+}
+
+// max_u: the entry point's largest U (MIMO_MAX_USERS for the CG detection
+// and precoding calls, MIMO_MAX_USERS_COMMON for the others).
+int check_shape(const mimo_shape* s, bool need_k, int max_u = MIMO_MAX_USERS_COMMON) {
   if (!s) return fail(MIMO_EINVAL, "shape is NULL");
-  if (s->U < 1 || s->U > MIMO_MAX_USERS)
-    return fail(s->U > MIMO_MAX_USERS ? MIMO_EUNSUPPORTED : MIMO_EINVAL,
-                "U=%d outside [1, %d]", s->U, MIMO_MAX_USERS);
+  if (s->U < 1) return fail(MIMO_EINVAL, "U=%d < 1", s->U);
+  if (s->U > max_u)
+    return fail(MIMO_EUNSUPPORTED, "U=%d > %d (U up to %d: CG detection with the approximate "
+                "SINR and CG precoding, complex64 storage)", s->U, max_u, MIMO_MAX_USERS);
   if (s->B < s->U) return fail(MIMO_EINVAL, "B=%d < U=%d", s->B, s->U);
   if (s->B > MIMO_MAX_ANTENNAS)
     return fail(MIMO_EUNSUPPORTED, "B=%d > %d", s->B, MIMO_MAX_ANTENNAS);
@@ -254,14 +266,17 @@ int mimo_detect_cg(const mimo_shape* shape, const void* H, const void* Y, int in
                    float* mu, float* sinr, void* workspace, size_t workspace_bytes,
                    void* stream) {
   g_last_error[0] = 0;
-  CHECK(check_shape(shape, true));
+  CHECK(check_shape(shape, true, MIMO_MAX_USERS));
   CHECK(check_dtype(in_dtype, shape->B));
+  CHECK(check_wide(shape->U, in_dtype));
   if (!(n0 > 0.f) || !std::isfinite(n0)) return fail(MIMO_EINVAL, "n0=%g must be > 0", n0);
   if (!(es > 0.f) || !std::isfinite(es)) return fail(MIMO_EINVAL, "es=%g must be > 0", es);
   if (qam_bits != 2 && qam_bits != 4 && qam_bits != 6 && qam_bits != 8)
     return fail(MIMO_EUNSUPPORTED, "qam_bits=%d not in {2,4,6,8}", qam_bits);
   if (sinr_mode != MIMO_SINR_APPROX && sinr_mode != MIMO_SINR_EXACT)
     return fail(MIMO_EINVAL, "sinr_mode=%d unknown", sinr_mode);
+  if (sinr_mode == MIMO_SINR_EXACT && shape->U > MIMO_MAX_USERS_COMMON)
+    return fail(MIMO_EUNSUPPORTED, "exact SINR with U=%d > %d", shape->U, MIMO_MAX_USERS_COMMON);
   if (scalar_prec != MIMO_SCALAR_F32 && scalar_prec != MIMO_SCALAR_F64)
     return fail(MIMO_EINVAL, "scalar_prec=%d unknown", scalar_prec);
   CHECK(check_ptr(H, "H", true));
@@ -281,6 +296,8 @@ int mimo_detect_cg(const mimo_shape* shape, const void* H, const void* Y, int in
   const int f64 = scalar_prec == MIMO_SCALAR_F64;
   hipError_t e = sinr_mode == MIMO_SINR_EXACT
                      ? mimo::launch_detect_exact(p, in_dtype, f64, qam_bits, (hipStream_t)stream)
+                 : shape->U > MIMO_MAX_USERS_COMMON
+                     ? mimo::launch_detect_wide(p, f64, qam_bits, (hipStream_t)stream)
                      : mimo::launch_detect_approx(p, in_dtype, f64, qam_bits,
                                                   get_sched(MIMO_OP_DETECT, shape->U, in_dtype),
                                                   (hipStream_t)stream);
@@ -291,8 +308,9 @@ int mimo_precode_cg(const mimo_shape* shape, const void* H, const void* T, int i
                     float beta, int normalize, int scalar_prec, void* Q, float* qnorm,
                     void* workspace, size_t workspace_bytes, void* stream) {
   g_last_error[0] = 0;
-  CHECK(check_shape(shape, true));
+  CHECK(check_shape(shape, true, MIMO_MAX_USERS));
   CHECK(check_dtype(in_dtype, shape->B));
+  CHECK(check_wide(shape->U, in_dtype));
   if (!(beta >= 0.f) || !std::isfinite(beta)) return fail(MIMO_EINVAL, "beta=%g must be >= 0", beta);
   if (scalar_prec != MIMO_SCALAR_F32 && scalar_prec != MIMO_SCALAR_F64)
     return fail(MIMO_EINVAL, "scalar_prec=%d unknown", scalar_prec);
@@ -306,6 +324,10 @@ int mimo_precode_cg(const mimo_shape* shape, const void* H, const void* T, int i
   if (shape->n_sc == 0) return MIMO_OK;
   mimo::PrecodeParams p{H, (const float2*)T, shape->B, shape->U, shape->S, shape->K,
                         shape->n_sc, beta, normalize ? 1 : 0, (float2*)Q, qnorm};
+  if (shape->U > MIMO_MAX_USERS_COMMON)
+    return hip_status(mimo::launch_precode_wide(p, scalar_prec == MIMO_SCALAR_F64,
+                                                (hipStream_t)stream),
+                      "precode_cg launch");
   return hip_status(mimo::launch_precode(p, in_dtype, scalar_prec == MIMO_SCALAR_F64,
                                          get_sched(MIMO_OP_PRECODE, shape->U, in_dtype),
                                          (hipStream_t)stream),
@@ -318,13 +340,14 @@ int mimo_detect_precode_cg(const mimo_shape* ul, const mimo_shape* dl, const voi
                            float* llr, void* xhat, float* mu, float* sinr, void* Q,
                            float* qnorm, void* stream) {
   g_last_error[0] = 0;
-  CHECK(check_shape(ul, true));
-  CHECK(check_shape(dl, true));
+  CHECK(check_shape(ul, true, MIMO_MAX_USERS));
+  CHECK(check_shape(dl, true, MIMO_MAX_USERS));
   if (ul->B != dl->B || ul->U != dl->U || ul->n_sc != dl->n_sc)
     return fail(MIMO_EINVAL, "uplink (B=%d, U=%d, n_sc=%lld) and downlink (B=%d, U=%d, "
                 "n_sc=%lld) shapes must share the channel", ul->B, ul->U, (long long)ul->n_sc,
                 dl->B, dl->U, (long long)dl->n_sc);
   CHECK(check_dtype(in_dtype, ul->B));
+  CHECK(check_wide(ul->U, in_dtype));
   if (!(n0 > 0.f) || !std::isfinite(n0)) return fail(MIMO_EINVAL, "n0=%g must be > 0", n0);
   if (!(es > 0.f) || !std::isfinite(es)) return fail(MIMO_EINVAL, "es=%g must be > 0", es);
   if (qam_bits != 2 && qam_bits != 4 && qam_bits != 6 && qam_bits != 8)
@@ -349,6 +372,12 @@ int mimo_detect_precode_cg(const mimo_shape* ul, const mimo_shape* dl, const voi
       mimo::PrecodeParams{H, (const float2*)T, dl->B, dl->U, dl->S, dl->K, dl->n_sc, beta,
                           normalize ? 1 : 0, (float2*)Q, qnorm}};
   const int f64 = scalar_prec == MIMO_SCALAR_F64;
+  if (ul->U > MIMO_MAX_USERS_COMMON) {
+    CHECK(hip_status(mimo::launch_detect_wide(p.ul, f64, qam_bits, (hipStream_t)stream),
+                     "detect_precode_cg: detection launch"));
+    return hip_status(mimo::launch_precode_wide(p.dl, f64, (hipStream_t)stream),
+                      "detect_precode_cg: precoding launch");
+  }
   const mimo::Schedule sch = get_sched(MIMO_OP_SLOT, ul->U, in_dtype);
   if ((sch.variant == mimo::kSlotFused || sch.variant == mimo::kSlotFusedX3) &&
       mimo::slot_eligible(p, in_dtype))

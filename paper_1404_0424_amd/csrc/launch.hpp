@@ -32,6 +32,11 @@ hipError_t launch_precode_split(const PrecodeParams& p, int scalar_f64, const Sc
 bool slot_eligible(const SlotParams& p, int in_dtype);
 hipError_t launch_slot(const SlotParams& p, int scalar_f64, int m_bits, const Schedule& sch,
                        hipStream_t stream);
+// Four wavefronts per subcarrier, one 16-user tile each (complex64,
+// 32 < U <= 64, approximate SINR; any B and S).
+hipError_t launch_detect_wide(const DetectParams& p, int scalar_f64, int m_bits,
+                              hipStream_t stream);
+hipError_t launch_precode_wide(const PrecodeParams& p, int scalar_f64, hipStream_t stream);
 hipError_t launch_detect_plain(const DetectParams& p, int scalar_f64, int m_bits,
                                const Schedule& sch, hipStream_t stream);
 hipError_t launch_detect_batch(const BatchArgs& a, int max_u, int in_dtype, int scalar_f64,

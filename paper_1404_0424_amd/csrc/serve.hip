@@ -621,7 +621,9 @@ int mimo_server_register_channel(mimo_server* s, int64_t ch_id, const void* H, i
   if (!H || ((uintptr_t)H & 15u)) return fail(MIMO_EINVAL, "H is NULL or not 16-byte aligned");
   if (in_dtype != MIMO_C32 && in_dtype != MIMO_C16 && in_dtype != MIMO_CBF16)
     return fail(MIMO_EINVAL, "in_dtype=%d unknown", in_dtype);
-  if (n_sc < 1 || U < 1 || U > MIMO_MAX_USERS || B < U || B > MIMO_MAX_ANTENNAS ||
+  if (U > MIMO_MAX_USERS_COMMON && U <= B && B <= MIMO_MAX_ANTENNAS)
+    return fail(MIMO_EUNSUPPORTED, "U=%d > %d", U, MIMO_MAX_USERS_COMMON);
+  if (n_sc < 1 || U < 1 || U > MIMO_MAX_USERS_COMMON || B < U || B > MIMO_MAX_ANTENNAS ||
       (in_dtype != MIMO_C32 && B % 8))
     return fail(MIMO_EINVAL, "bad channel shape n_sc=%lld B=%d U=%d", (long long)n_sc, B, U);
   const int64_t bytes = n_sc * B * U * (in_dtype == MIMO_C32 ? 8 : 4);

@@ -44,7 +44,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_header_constants_match_binding():
     src = open(HEADER).read()
-    assert f"#define MIMO_MAX_USERS {L.MIMO_MAX_USERS}" in src
+    assert re.search(rf"#define MIMO_MAX_USERS {L.MIMO_MAX_USERS}\b", src)
+    assert re.search(rf"#define MIMO_MAX_USERS_COMMON {L.MIMO_MAX_USERS_COMMON}\b", src)
     assert f"#define MIMO_MAX_ANTENNAS {L.MIMO_MAX_ANTENNAS}" in src
     assert f"#define MIMO_MAX_BATCH {L.MIMO_MAX_BATCH}" in src
     m = re.search(r"#define MIMO_MAX_SPAN_BYTES (\d+)LL", src)
@@ -88,7 +89,10 @@ def _detect(shape, **kw):
     ((32, 8, 0, 3, 4), {}, L.MIMO_EINVAL),                   # S < 1
     ((4, 8, 1, 3, 4), {}, L.MIMO_EINVAL),                    # B < U
     ((32, 0, 1, 3, 4), {}, L.MIMO_EINVAL),                   # U < 1
-    ((64, 33, 1, 3, 4), {}, L.MIMO_EUNSUPPORTED),            # U > MIMO_MAX_USERS
+    ((128, 65, 1, 3, 4), {}, L.MIMO_EUNSUPPORTED),           # U > MIMO_MAX_USERS
+    ((64, 33, 1, 3, 4), dict(mode=1), L.MIMO_EUNSUPPORTED),  # exact SINR, U > 32
+    ((64, 33, 1, 3, 4), dict(dt=1), L.MIMO_EUNSUPPORTED),    # 16-bit storage, U > 32
+    ((64, 40, 1, 3, 4), dict(dt=2), L.MIMO_EUNSUPPORTED),
     ((32, 8, 1, 3, -1), {}, L.MIMO_EINVAL),                  # n_sc < 0
 ])
 def test_detect_rejects_invalid_arguments(shape, kw, status):
@@ -127,6 +131,41 @@ def test_rhs_count_bounded_by_32bit_offsets(B, U):
     fr[0] = L.MimoFrame(4, B, U, s_bad, 3, P, P, P2, None, 0.5, 1.0, 0.0, 0)
     assert lib.mimo_detect_cg_batch(ctypes.addressof(fr), 1, 0, 4, 0,
                                     None) == L.MIMO_EUNSUPPORTED
+
+
+def test_users_beyond_32_validation():
+    """33 <= U <= MIMO_MAX_USERS passes validation on the CG detection
+    (approximate SINR), precoding and slot calls with complex64 storage (n_sc
+    = 0 here, so nothing runs) and is rejected with MIMO_EUNSUPPORTED by
+    every call that is not built for it."""
+    lib = L.lib()
+    for U in (33, 48, L.MIMO_MAX_USERS):
+        empty = L.shape(128, U, 14, 4, 0)
+        assert _detect(empty) == L.MIMO_OK
+        assert _detect(empty, prec=1, m=8) == L.MIMO_OK
+        assert lib.mimo_precode_cg(empty, P, P, 0, 0.1, 1, 0, P2, None, None, 0,
+                                   None) == L.MIMO_OK
+        s = L.shape(128, U, 14, 4, 4)
+        assert lib.mimo_precode_cg(s, P, P, 1, 0.1, 1, 0, P2, None, None, 0,
+                                   None) == L.MIMO_EUNSUPPORTED
+        assert lib.mimo_gram_mf(s, P, P, 0, 0.5, P2, P2, None) == L.MIMO_EUNSUPPORTED
+        assert lib.mimo_detect_cholesky(s, P, P, 0, 0.5, 1.0, 4, P2, None, None, None,
+                                        None) == L.MIMO_EUNSUPPORTED
+        assert lib.mimo_detect_neumann(s, P, P, 0, 0.5, 1.0, 4, P2, None, None, None,
+                                       None) == L.MIMO_EUNSUPPORTED
+        assert lib.mimo_precode_cholesky(s, P, P, 0, 0.1, 0, P2, None,
+                                         None) == L.MIMO_EUNSUPPORTED
+        assert lib.mimo_detect_cgls(s, P, P, 0, 0.5, 1.0, 4, 0, P2, None, None, None,
+                                    None) == L.MIMO_EUNSUPPORTED
+        assert lib.mimo_precode_cgls(s, P, P, 0, 0.1, 0, 0, P2, None,
+                                     None) == L.MIMO_EUNSUPPORTED
+        fr = (L.MimoFrame * 1)()
+        fr[0] = L.MimoFrame(4, 128, U, 14, 4, P, P, P2, None, 0.5, 1.0, 0.1, 1)
+        assert lib.mimo_detect_cg_batch(ctypes.addressof(fr), 1, 0, 4, 0,
+                                        None) == L.MIMO_EUNSUPPORTED
+        assert lib.mimo_precode_cg_batch(ctypes.addressof(fr), 1, 0, 0,
+                                         None) == L.MIMO_EUNSUPPORTED
+        assert b"U=" in lib.mimo_last_error()
 
 
 def test_zero_subcarriers_is_a_noop():
@@ -203,7 +242,9 @@ def test_slot_validation_without_a_gpu():
         assert b"share the channel" in L.lib().mimo_last_error()
     assert _slot(ul, L.shape(32, 8, 5, 0, 4)) == L.MIMO_EINVAL             # K_dl < 1
     assert _slot(L.shape(32, 8, 0, 3, 4), dl) == L.MIMO_EINVAL             # S_ul < 1
-    assert _slot(L.shape(64, 33, 2, 3, 4), L.shape(64, 33, 2, 3, 4)) == L.MIMO_EUNSUPPORTED
+    assert _slot(L.shape(128, 65, 2, 3, 4), L.shape(128, 65, 2, 3, 4)) == L.MIMO_EUNSUPPORTED
+    assert _slot(L.shape(64, 33, 2, 3, 4), L.shape(64, 33, 2, 3, 4), dt=1) == L.MIMO_EUNSUPPORTED
+    assert _slot(L.shape(64, 64, 2, 3, 0), L.shape(64, 64, 5, 2, 0)) == L.MIMO_OK
     assert _slot(L.shape(32, 8, 14, 3, 0), L.shape(32, 8, 5, 6, 0)) == L.MIMO_OK
     assert L.lib().mimo_tune_variant_count(L.MIMO_OP_SLOT) == 3
     assert L.lib().mimo_tune_variant_name(L.MIMO_OP_SLOT, 1) == b"fused"

@@ -507,23 +507,27 @@ def test_plain_baseline_variant_parity(case):
 
 @pytest.mark.parametrize("scalar", ["f32", "f64"])
 def test_maximum_sizes(scalar):
-    """B = MIMO_MAX_ANTENNAS, U = MIMO_MAX_USERS and 40 right-hand sides (three
-    chunks of 16): detection in both tracker modes and precoding against the
-    oracle."""
+    """B = MIMO_MAX_ANTENNAS and 40 right-hand sides (three chunks of 16):
+    detection in both tracker modes and precoding at U = MIMO_MAX_USERS_COMMON,
+    and detection (approximate SINR) and precoding at U = MIMO_MAX_USERS,
+    against the oracle."""
     from paper_1404_0424_amd import _lib as L
-    B, U, S, n, K = L.MIMO_MAX_ANTENNAS, L.MIMO_MAX_USERS, 40, 2, 5
-    rng = np.random.default_rng(4096)
-    f = W.uplink_frame(rng, n, B, U, S, 4, 15.0)
-    d = W.downlink_frame(rng, n, B, U, S, 4, 15.0, H=f.H)
-    A = api()
-    for mode in ("approx", "exact"):
-        o = A.detect_cg(dev(f.H), dev(f.Y), f.n0, f.es, K, 4, mode, scalar, xhat=True)
-        ref = O.detect_cg(f.H, f.Y, f.n0, f.es, K, 4, mode)
-        ex = rel_err_vec(host(o["xhat"]), ref["xhat"], axis=1)
-        el = llr_err(host(o["llr"]), ref["llr"])
-        print(f"{mode} {scalar}: eps_x={ex:.2e} eps_L={el:.2e}")
-        assert ex <= TOL_X and el <= TOL_L
-    Q, qn = A.precode_cg(dev(f.H), dev(d.T), d.beta, K, True, scalar)
-    refp = O.precode_cg(f.H, d.T, d.beta, K, True)
-    assert rel_err_vec(host(Q), refp["Q"], axis=1) <= TOL_X
-    assert rel_err_scalar(host(qn), refp["qnorm"]) <= TOL_X
+    for U, modes in ((L.MIMO_MAX_USERS_COMMON, ("approx", "exact")),
+                     (L.MIMO_MAX_USERS, ("approx",))):
+        B, S, n, K = L.MIMO_MAX_ANTENNAS, 40, 2, 5
+        print(f"maximum sizes B={B} U={U} S={S} {scalar}", flush=True)
+        rng = np.random.default_rng(4096 + U)
+        f = W.uplink_frame(rng, n, B, U, S, 4, 15.0)
+        d = W.downlink_frame(rng, n, B, U, S, 4, 15.0, H=f.H)
+        A = api()
+        for mode in modes:
+            o = A.detect_cg(dev(f.H), dev(f.Y), f.n0, f.es, K, 4, mode, scalar, xhat=True)
+            ref = O.detect_cg(f.H, f.Y, f.n0, f.es, K, 4, mode)
+            ex = rel_err_vec(host(o["xhat"]), ref["xhat"], axis=1)
+            el = llr_err(host(o["llr"]), ref["llr"])
+            print(f"U={U} {mode} {scalar}: eps_x={ex:.2e} eps_L={el:.2e}")
+            assert ex <= TOL_X and el <= TOL_L
+        Q, qn = A.precode_cg(dev(f.H), dev(d.T), d.beta, K, True, scalar)
+        refp = O.precode_cg(f.H, d.T, d.beta, K, True)
+        assert rel_err_vec(host(Q), refp["Q"], axis=1) <= TOL_X
+        assert rel_err_scalar(host(qn), refp["qnorm"]) <= TOL_X
