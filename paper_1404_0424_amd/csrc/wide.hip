@@ -1,20 +1,24 @@
 // CG-D detection and CG-P precoding for 32 < U <= 64 (the paper's U <= B
 // allows any U; Sec. II-A), complex64 storage: one workgroup of four
-// wavefronts per subcarrier, wavefront w owning users 16 w .. 16 w + 15.
+// wavefronts per subcarrier.  Wavefront w takes role r = (w + n) mod 4 on
+// subcarrier n and owns users 16 r .. 16 r + 15; the rotation spreads the
+// roles' unequal Gram work evenly over the four SIMDs.
 //
-// Each wavefront accumulates its 16 rows of G = H^H H (all 64 columns: the
-// four tiles (w, j) on MFMA, the channel streamed from HBM; the other
-// wavefronts' loads of the same rows hit the CU's caches) and, for
-// detection, the matched filter of its users; its rows of A = G + reg I go
-// to LDS and come back as the A^T operand of its part of the mat-vec.  Per
-// CG iteration (Algorithm 1 loop body) the wavefronts exchange P through a
-// shared LDS array and the partial inner products Re(p^H e) and ||r||^2 of
-// their users through a small LDS table, summed over the four wavefronts in
-// a fixed order, so every wavefront computes the same step sizes.  The
-// approximate SINR tracker of eq. (13), mu, rho and the LLRs (eq. (4)) are
-// per user and stay in the owning wavefront.  Precoding forms ||q||^2 =
-// v^H G v the same way and then q = H_u v (Algorithm 1 output) with V from
-// LDS, each wavefront taking every fourth 16-antenna tile.
+// Gram: the ten 16 x 16 tiles of the Hermitian G = H^H H are divided over
+// the roles (r, r), (r, r + 1) and, for r < 2, (r, r + 2) (tile indices mod
+// 4), each tile in three real products on MFMA, the channel streamed from
+// HBM in groups of antennas with the next group in flight; role r also
+// forms the matched filter b = H^H y of its users.  The tiles and their
+// conjugate mirrors make A = G + reg I in LDS, whose rows 16 r .. come back
+// as the A^T operand of the role's part of the mat-vec.  Per CG iteration
+// (Algorithm 1 loop body) the wavefronts exchange P through a shared LDS
+// array and the partial inner products Re(p^H e) and ||r||^2 of their users
+// through a small LDS table, summed over the four roles in a fixed order, so
+// every wavefront computes the same step sizes.  The approximate SINR
+// tracker of eq. (13), mu, rho and the LLRs (eq. (4)) are per user and stay
+// in the owning wavefront.  Precoding forms ||q||^2 = v^H G v the same way
+// and then q = H_u v (Algorithm 1 output) with V from LDS, each wavefront
+// taking every fourth 16-antenna tile.
 #include <type_traits>
 
 #include "detect_core.hpp"
@@ -25,119 +29,169 @@ namespace mimo {
 
 constexpr int kWideTiles = 4;
 constexpr int kWideUsers = 16 * kWideTiles;
-constexpr int kWideAst = kWideUsers + 2;   // LDS row stride (complex) of a wavefront's rows of A
+constexpr int kWideAst = kWideUsers + 2;   // LDS row stride (complex) of A
 
 template <typename ST>
 struct WideLds {
-  float2 A[kWideTiles][16 * kWideAst];       // rows 16 w .. 16 w + 15 of A, per wavefront
+  float2 A[kWideUsers * kWideAst];           // A = G + reg I, row-major
   float2 P[kWideUsers * kPST];               // P[user][rhs] of all users
-  ST red[2][kWideTiles][16];                 // partial sums per wavefront and rhs
+  ST red[2][kWideTiles][16];                 // partial sums per role and rhs
   float G[kWideUsers];                       // raw diagonal G_uu
-  float N[16];                               // ||q||^2 per rhs (precoding)
 };
 
-// Lane (c, g) of wavefront w: user 16 w + c, right-hand sides s0 + 4 g + j.
+// Lane (c, g) of the wavefront in role r: user 16 r + c, right-hand sides
+// s0 + 4 g + j.
 struct WideLane {
-  int w, c, g, lane;
+  int r, c, g, lane;
 };
 
-// Rows 16 w .. of G (all four column tiles) and, with Y, b = H^H y of the
-// wavefront's users for right-hand sides s0 ..; four antennas per MFMA step.
-// gr/gi: Re and Im of tile (w, j); p1, p2, p3: the three-product matched
-// filter (Re b = p1 + p2, Im b = p3 - p1 + p2).
+// Accumulators of role r: Gram tiles (r, r + j) for j < 3 as P1 = ar br,
+// P2 = ai bi, P3 = (ar + ai)(br - bi) over the row operand a (conjugated)
+// and the column operand b, so that Re G = P1 + P2 and Im G = P1 - P2 - P3;
+// and the matched filter of the role's users, Re b = p1 + p2,
+// Im b = p3 - p1 + p2 with p3 = (yr + yi)(hr - hi).
 struct WideAcc {
-  f4 gr[kWideTiles], gi[kWideTiles];
+  f4 t[3][3];
   f4 p1, p2, p3;
 };
 
-template <bool DO_GRAM, bool DO_MF>
-__device__ __forceinline__ void wide_gram_mf(const void* Hn, const void* Yn, int B, int U, int S,
-                                             int s0, const WideLane& L, WideAcc& acc) {
-  const __amdgpu_buffer_rsrc_t rh = make_rsrc(Hn, (uint32_t)B * U * 8u);
-  const __amdgpu_buffer_rsrc_t ry =
-      make_rsrc(DO_MF ? Yn : Hn, DO_MF ? (uint32_t)B * S * 8u : 0u);
-  uint32_t oh[kWideTiles];
-#pragma unroll
-  for (int j = 0; j < kWideTiles; ++j) {
-    const int u = 16 * j + L.c;
-    oh[j] = u < U ? (uint32_t)(L.g * U + u) * 8u : kOOB;
-  }
-  const int uw = 16 * L.w + L.c;
-  const uint32_t ow = uw < U ? (uint32_t)(L.g * U + uw) * 8u : kOOB;
-  const int s = s0 + L.c;
-  const uint32_t oy = s < S ? (uint32_t)(L.g * S + s) * 8u : kOOB;
-#pragma unroll
-  for (int j = 0; j < kWideTiles; ++j) { acc.gr[j] = zero4(); acc.gi[j] = zero4(); }
-  acc.p1 = acc.p2 = acc.p3 = zero4();
-  constexpr int UNR = 4;                         // k-steps loaded together
-  for (int b0 = 0; b0 < B; b0 += 4 * UNR) {
-    float2 h[UNR][kWideTiles], hw[UNR], y[UNR];
+// k-steps (4 antennas each) per load group: two groups are in registers
+constexpr int kWideUnrDetect = 2;
+constexpr int kWideUnrPrecode = 2;
+
+// One group of 4 UNR antennas: lane (c, g) holds H[b0 + 4 t + g][16 q_j + c]
+// of the NH tiles q_j the role needs (q_0 = r) and Y[b0 + 4 t + g][s0 + c].
+template <int NH, int UNR, bool DO_MF>
+struct WideGroup {
+  float2 h[UNR][NH];
+  float2 y[UNR];
+  __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rh, const uint32_t (&oh)[3],
+                                       __amdgpu_buffer_rsrc_t ry, uint32_t oy, int U, int S,
+                                       int b0) {
 #pragma unroll
     for (int t = 0; t < UNR; ++t) {
       const int b = b0 + 4 * t;
-      hw[t] = bload2(rh, ow, (uint32_t)b * U * 8u);
-      if (DO_GRAM) {
 #pragma unroll
-        for (int j = 0; j < kWideTiles; ++j) h[t][j] = bload2(rh, oh[j], (uint32_t)b * U * 8u);
-      }
+      for (int j = 0; j < NH; ++j) h[t][j] = bload2(rh, oh[j], (uint32_t)b * U * 8u);
       if (DO_MF) y[t] = bload2(ry, oy, (uint32_t)b * S * 8u);
     }
+  }
+  template <bool DO_GRAM>
+  __device__ __forceinline__ void mma(WideAcc& acc) const {
 #pragma unroll
     for (int t = 0; t < UNR; ++t) {
+      const float2 a = h[t][0];
+      const float da = a.x - a.y;
       if (DO_GRAM) {
+        const float sa = a.x + a.y;
 #pragma unroll
-        for (int j = 0; j < kWideTiles; ++j) {
-          acc.gr[j] = mfma4(hw[t].x, h[t][j].x, acc.gr[j]);
-          acc.gr[j] = mfma4(hw[t].y, h[t][j].y, acc.gr[j]);
-          acc.gi[j] = mfma4(hw[t].x, h[t][j].y, acc.gi[j]);
-          acc.gi[j] = mfma4(-hw[t].y, h[t][j].x, acc.gi[j]);
+        for (int j = 0; j < NH; ++j) {
+          const float2 b = h[t][j];
+          const float db = j == 0 ? da : b.x - b.y;
+          acc.t[j][0] = mfma4(a.x, b.x, acc.t[j][0]);
+          acc.t[j][1] = mfma4(a.y, b.y, acc.t[j][1]);
+          acc.t[j][2] = mfma4(sa, db, acc.t[j][2]);
         }
       }
       if (DO_MF) {
-        acc.p1 = mfma4(y[t].x, hw[t].x, acc.p1);
-        acc.p2 = mfma4(y[t].y, hw[t].y, acc.p2);
-        acc.p3 = mfma4(y[t].x + y[t].y, hw[t].x - hw[t].y, acc.p3);
+        acc.p1 = mfma4(y[t].x, a.x, acc.p1);
+        acc.p2 = mfma4(y[t].y, a.y, acc.p2);
+        acc.p3 = mfma4(y[t].x + y[t].y, da, acc.p3);
       }
     }
   }
+};
+
+// The antennas in groups of 4 UNR, the next group's loads in flight while
+// the current group's MFMAs run.
+template <int NH, int UNR, bool DO_GRAM, bool DO_MF>
+__device__ __forceinline__ void wide_stream(__amdgpu_buffer_rsrc_t rh, const uint32_t (&oh)[3],
+                                            __amdgpu_buffer_rsrc_t ry, uint32_t oy, int B, int U,
+                                            int S, WideAcc& acc) {
+  constexpr int GA = 4 * UNR;                      // antennas per group
+  WideGroup<NH, UNR, DO_MF> g0, g1;
+  g0.load(rh, oh, ry, oy, U, S, 0);
+  for (int b0 = 0; b0 < B; b0 += 2 * GA) {
+    if (b0 + GA < B) g1.load(rh, oh, ry, oy, U, S, b0 + GA);
+    g0.template mma<DO_GRAM>(acc);
+    if (b0 + GA >= B) break;
+    if (b0 + 2 * GA < B) g0.load(rh, oh, ry, oy, U, S, b0 + 2 * GA);
+    g1.template mma<DO_GRAM>(acc);
+  }
 }
 
-// The wavefront's rows of A = G + reg I to LDS (the diagonal real, G_uu to
-// lds.G), then its A^T operand a[t] = A[16 w + c][4 t + g] and d = A_uu.
+// Role r's Gram tiles (DO_GRAM) and matched filter for right-hand sides
+// s0 .. s0 + 15 (DO_MF).  A role whose users are all padding (16 r >= U)
+// has zero tiles and b.
+template <int UNR, bool DO_GRAM, bool DO_MF>
+__device__ __forceinline__ void wide_gram_mf(const void* Hn, const void* Yn, int B, int U, int S,
+                                             int s0, const WideLane& L, WideAcc& acc) {
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int e = 0; e < 3; ++e) acc.t[j][e] = zero4();
+  acc.p1 = acc.p2 = acc.p3 = zero4();
+  if (16 * L.r >= U) return;
+  const __amdgpu_buffer_rsrc_t rh = make_rsrc(Hn, (uint32_t)B * U * 8u);
+  const __amdgpu_buffer_rsrc_t ry =
+      make_rsrc(DO_MF ? Yn : Hn, DO_MF ? (uint32_t)B * S * 8u : 0u);
+  uint32_t oh[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int u = 16 * ((L.r + j) & 3) + L.c;
+    oh[j] = u < U ? (uint32_t)(L.g * U + u) * 8u : kOOB;
+  }
+  const int s = s0 + L.c;
+  const uint32_t oy = s < S ? (uint32_t)(L.g * S + s) * 8u : kOOB;
+  if (!DO_GRAM) wide_stream<1, UNR, false, DO_MF>(rh, oh, ry, oy, B, U, S, acc);
+  else if (L.r < 2) wide_stream<3, UNR, true, DO_MF>(rh, oh, ry, oy, B, U, S, acc);
+  else wide_stream<2, UNR, true, DO_MF>(rh, oh, ry, oy, B, U, S, acc);
+}
+
+// Role r's tiles and their conjugate mirrors into A = G + reg I in LDS
+// (diagonal tiles: the upper part, mirrored; the diagonal real, G_uu to
+// lds.G), then the role's A^T operand a[t] = A[16 r + c][4 t + g] and
+// d = A_uu.
 template <typename ST>
 __device__ __forceinline__ void wide_store_a(const WideAcc& acc, WideLds<ST>& lds, float reg,
-                                             int U, const WideLane& L, float2 (&a)[16],
-                                             float& d) {
-  float2* Aw = lds.A[L.w];
+                                             const WideLane& L, float2 (&a)[16], float& d) {
+  const int nt = L.r < 2 ? 3 : 2;
 #pragma unroll
-  for (int j = 0; j < kWideTiles; ++j)
+  for (int j = 0; j < 3; ++j) {
+    if (j < nt) {
+      const int q = (L.r + j) & 3;
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
-      const int rl = 4 * L.g + jj;                 // local row
-      const int col = 16 * j + L.c;
-      if (16 * L.w + rl == col) {
-        Aw[rl * kWideAst + col] = make_float2(acc.gr[j][jj] + reg, 0.f);
-        lds.G[col] = acc.gr[j][jj];
-      } else {
-        Aw[rl * kWideAst + col] = make_float2(acc.gr[j][jj], acc.gi[j][jj]);
+      for (int jj = 0; jj < 4; ++jj) {
+        const int i = 4 * L.g + jj;               // row within tile r
+        const int row = 16 * L.r + i, col = 16 * q + L.c;
+        const float p1 = acc.t[j][0][jj], p2 = acc.t[j][1][jj], p3 = acc.t[j][2][jj];
+        const float re = p1 + p2, im = p1 - p2 - p3;
+        if (j > 0 || i < L.c) {
+          lds.A[row * kWideAst + col] = make_float2(re, im);
+          lds.A[col * kWideAst + row] = make_float2(re, -im);
+        } else if (i == L.c) {
+          lds.A[row * kWideAst + row] = make_float2(re + reg, 0.f);
+          lds.G[row] = re;
+        }
       }
     }
+  }
   __syncthreads();
+  const float2* Ar = &lds.A[(16 * L.r + L.c) * kWideAst];
 #pragma unroll
-  for (int t = 0; t < 16; ++t) a[t] = Aw[L.c * kWideAst + 4 * t + L.g];
-  d = Aw[L.c * kWideAst + 16 * L.w + L.c].x;
-  (void)U;
+  for (int t = 0; t < 16; ++t) a[t] = Ar[4 * t + L.g];
+  d = Ar[16 * L.r + L.c].x;
 }
 
-// Sum of the four wavefronts' partial sums x[j] (rhs 4 g + j, the row sum
-// of the wavefront's users already taken) through lds.red[slot]: the same
-// value, in the same order, in every wavefront.
+// Sum of the four roles' partial sums x[j] (rhs 4 g + j, the row sum of
+// the role's users already taken) through lds.red[slot]: the same value, in
+// the same order, in every wavefront.
 template <typename ST>
 __device__ __forceinline__ void wide_sum(ST (&x)[4], WideLds<ST>& lds, int slot,
                                          const WideLane& L) {
   if (L.c == 0) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) lds.red[slot][L.w][4 * L.g + j] = x[j];
+    for (int j = 0; j < 4; ++j) lds.red[slot][L.r][4 * L.g + j] = x[j];
   }
   __syncthreads();
 #pragma unroll
@@ -169,7 +223,7 @@ __device__ __forceinline__ void wide_matvec(const float2 (&a)[16], const float2*
 
 template <typename ST>
 __device__ __forceinline__ void wide_stage(const float2 (&x)[4], float2* Ps, const WideLane& L) {
-  float4* d = (float4*)&Ps[(16 * L.w + L.c) * kPST + 4 * L.g];
+  float4* d = (float4*)&Ps[(16 * L.r + L.c) * kPST + 4 * L.g];
   d[0] = make_float4(x[0].x, x[0].y, x[1].x, x[1].y);
   d[1] = make_float4(x[2].x, x[2].y, x[3].x, x[3].y);
 }
@@ -177,7 +231,7 @@ __device__ __forceinline__ void wide_stage(const float2 (&x)[4], float2* Ps, con
 template <typename ST>
 __device__ __forceinline__ void wide_cg_init(CGState<1, ST>& st, const float2 (&b)[4],
                                              WideLds<ST>& lds, const WideLane& L) {
-  __syncthreads();                                   // last readers of lds.red are done
+  __syncthreads();                                   // last readers of lds.red and P are done
   ST part[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -194,12 +248,13 @@ __device__ __forceinline__ void wide_cg_init(CGState<1, ST>& st, const float2 (&
 
 // One iteration of Algorithm 1 over the four wavefronts of the subcarrier:
 // the arithmetic of cg_update with the inner products summed over users of
-// all wavefronts.
+// all roles.  Three barriers: P staged; Re(p^H e) and ||r||^2 exchanged (the
+// last readers of P and of both tables passed one of them before the next
+// write; wide_cg_init's barrier covers the first iteration).
 template <typename ST>
 __device__ __forceinline__ void wide_cg_step(CGState<1, ST>& st, const float2 (&a)[16], int nk,
                                              WideLds<ST>& lds, const WideLane& L,
                                              ST (&alpha)[4], ST (&beta)[4]) {
-  __syncthreads();                                   // previous readers of P are done
   wide_stage<ST>(st.p[0], lds.P, L);
   __syncthreads();
   float2 e[4];
@@ -249,7 +304,7 @@ __device__ __forceinline__ void wide_llr(const DetectParams& prm, int64_t n, int
                                          const WideLane& L) {
   DetectStore<M_BITS> os;
   os.init(prm, n);
-  const int u = 16 * L.w + L.c;
+  const int u = 16 * L.r + L.c;
   const bool uok = u < prm.U;
   const float Guu = Gs[uok ? u : 0];
   const float rho = Guu / prm.n0;
@@ -266,14 +321,20 @@ __device__ __forceinline__ void wide_llr(const DetectParams& prm, int64_t n, int
   }
 }
 
-template <typename ST, int M_BITS>
-__global__ __launch_bounds__(256) void detect_wide_kernel(DetectParams prm) {
-  __shared__ __align__(16) WideLds<ST> lds;
+// Role of wavefront w on subcarrier n.
+__device__ __forceinline__ WideLane wide_lane(int64_t n) {
   const int lane = threadIdx.x & 63;
-  const WideLane L{__builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane & 15, lane >> 4, lane};
+  const int r = __builtin_amdgcn_readfirstlane((int)(((threadIdx.x >> 6) + n) & 3));
+  return WideLane{r, lane & 15, lane >> 4, lane};
+}
+
+template <typename ST, int M_BITS>
+__global__ __launch_bounds__(256, 2) void detect_wide_kernel(DetectParams prm) {
+  __shared__ __align__(16) WideLds<ST> lds;
   const int B = prm.B, U = prm.U, S = prm.S;
   const int nk = __builtin_amdgcn_readfirstlane((U + 3) >> 2);
   for (int64_t n = blockIdx.x; n < prm.n_sc; n += gridDim.x) {
+    const WideLane L = wide_lane(n);
     const void* Hn = offset_sc(InC32{}, prm.H, n, B, U);
     const void* Yn = offset_sc(InC32{}, prm.Y, n, B, S);
     float2 a[16];
@@ -281,10 +342,10 @@ __global__ __launch_bounds__(256) void detect_wide_kernel(DetectParams prm) {
     for (int s0 = 0; s0 < S; s0 += 16) {
       WideAcc acc;
       if (s0 == 0) {
-        wide_gram_mf<true, true>(Hn, Yn, B, U, S, s0, L, acc);
-        wide_store_a<ST>(acc, lds, prm.reg, U, L, a, d[0]);
+        wide_gram_mf<kWideUnrDetect, true, true>(Hn, Yn, B, U, S, s0, L, acc);
+        wide_store_a<ST>(acc, lds, prm.reg, L, a, d[0]);
       } else {
-        wide_gram_mf<false, true>(Hn, Yn, B, U, S, s0, L, acc);
+        wide_gram_mf<kWideUnrDetect, false, true>(Hn, Yn, B, U, S, s0, L, acc);
       }
       float2 b[4];
 #pragma unroll
@@ -307,28 +368,35 @@ __global__ __launch_bounds__(256) void detect_wide_kernel(DetectParams prm) {
   }
 }
 
+// H[b0 + c][4 t + g] for t < 16 (antenna row b0 + c, users 4 t + g): the
+// A operand of q = H_u v over k-steps of 4 users.  Rows past B and users
+// past U read as zero.
+__device__ __forceinline__ void wide_load_hrows(__amdgpu_buffer_rsrc_t rh, int U, int b0,
+                                                const WideLane& L, float2 (&h)[16]) {
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int u = 4 * t + L.g;
+    h[t] = bload2(rh, u < U ? (uint32_t)(L.c * U + u) * 8u : kOOB, (uint32_t)b0 * U * 8u);
+  }
+}
+
 template <typename ST>
-__global__ __launch_bounds__(256) void precode_wide_kernel(PrecodeParams prm) {
+__global__ __launch_bounds__(256, 2) void precode_wide_kernel(PrecodeParams prm) {
   __shared__ __align__(16) WideLds<ST> lds;
-  const int lane = threadIdx.x & 63;
-  const WideLane L{__builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane & 15, lane >> 4, lane};
   const int B = prm.B, U = prm.U, S = prm.S;
   const int nk = __builtin_amdgcn_readfirstlane((U + 3) >> 2);
-  const int u = 16 * L.w + L.c;
   for (int64_t n = blockIdx.x; n < prm.n_sc; n += gridDim.x) {
+    const WideLane L = wide_lane(n);
+    const int u = 16 * L.r + L.c;
     const void* Hn = offset_sc(InC32{}, prm.H, n, B, U);
     float2 a[16];
     float d;
     {
       WideAcc acc;
-      wide_gram_mf<true, false>(Hn, nullptr, B, U, S, 0, L, acc);
-      wide_store_a<ST>(acc, lds, prm.beta, U, L, a, d);
+      wide_gram_mf<kWideUnrPrecode, true, false>(Hn, nullptr, B, U, S, 0, L, acc);
+      wide_store_a<ST>(acc, lds, prm.beta, L, a, d);
     }
-    // G operand for ||q||^2 = v^H G v: A's diagonal entries replaced by G_uu
-    float2 ga[16];
-#pragma unroll
-    for (int t = 0; t < 16; ++t)
-      ga[t] = (u == 4 * t + L.g) ? make_float2(lds.G[u], 0.f) : a[t];
+    const __amdgpu_buffer_rsrc_t rh = make_rsrc(Hn, (uint32_t)B * U * 8u);
     const __amdgpu_buffer_rsrc_t rt =
         make_rsrc(prm.T + (size_t)n * U * S, (uint32_t)U * S * 8u);
     const __amdgpu_buffer_rsrc_t rq = make_rsrc(prm.Q + (size_t)n * B * S, (uint32_t)B * S * 8u);
@@ -345,12 +413,23 @@ __global__ __launch_bounds__(256) void precode_wide_kernel(PrecodeParams prm) {
         ST al[4], be[4];
         wide_cg_step<ST>(st, a, nk, lds, L, al, be);
       }
-      // ---- ||q||^2 = v^H G v over all users; V stays in LDS for q = H v
-      __syncthreads();
+      // ---- ||q||^2 = v^H G v over all users (the mat-vec on A's operand
+      // with the diagonal entries replaced by G_uu, so beta never enters the
+      // sum); V stays in LDS for q = H v.  The last CG iteration's barriers
+      // follow every read of P.
+      float2 hc[16];                                 // first antenna tile of q = H v
+      const int bw = 16 * L.r;
+      if (bw < B) wide_load_hrows(rh, U, bw, L, hc);
       wide_stage<ST>(st.v[0], lds.P, L);
       __syncthreads();
       float2 e[4];
-      wide_matvec(ga, lds.P, nk, L, e);
+      {
+        float2 ga[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t)
+          ga[t] = (u == 4 * t + L.g) ? make_float2(lds.G[u], 0.f) : a[t];
+        wide_matvec(ga, lds.P, nk, L, e);
+      }
       ST qq[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j)
@@ -360,15 +439,16 @@ __global__ __launch_bounds__(256) void precode_wide_kernel(PrecodeParams prm) {
       float nrm2[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) nrm2[j] = (float)(qq[j] > ST(0) ? qq[j] : ST(0));
-      if (L.w == 0 && L.c == 0) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) lds.N[4 * L.g + j] = nrm2[j];
-      }
-      __syncthreads();
-      const float nc = lds.N[L.c];
+      // ||q||^2 of rhs c = 4 g' + j' for the lanes of column c: lane
+      // 16 g' + j' holds it in nrm2[j'] (every lane of a row holds its row's
+      // four sums)
+      const int jc = L.c & 3;
+      const float mine = jc == 0 ? nrm2[0] : jc == 1 ? nrm2[1] : jc == 2 ? nrm2[2] : nrm2[3];
+      const float nc = __shfl(mine, 16 * (L.c >> 2) + jc, 64);
       const float scl = prm.normalize ? (nc > 0.f ? __builtin_amdgcn_rsqf(nc) : 0.f) : 1.0f;
-      // ---- q = H_u v (Algorithm 1 output): 16-antenna tiles w, w + 4, ...;
-      // P1 = Hr Vr, P2 = Hi Vi, P3 = (Hr + Hi)(Vr + Vi)
+      // ---- q = H_u v (Algorithm 1 output): 16-antenna tiles 16 r, 16 r + 64,
+      // ..., the next tile's loads in flight; P1 = Hr Vr, P2 = Hi Vi,
+      // P3 = (Hr + Hi)(Vr + Vi), Re q = P1 - P2, Im q = P3 - P1 - P2
       float2 vv[16];
       float vs[16];
 #pragma unroll
@@ -377,21 +457,17 @@ __global__ __launch_bounds__(256) void precode_wide_kernel(PrecodeParams prm) {
         vs[t] = vv[t].x + vv[t].y;
       }
       const int s = s0 + L.c;
-      for (int b0 = 16 * L.w; b0 < B; b0 += 16 * kWideTiles) {
+      for (int b0 = bw; b0 < B; b0 += 16 * kWideTiles) {
+        float2 hn[16];
+        const int b1 = b0 + 16 * kWideTiles;
+        if (b1 < B) wide_load_hrows(rh, U, b1, L, hn);
         f4 p1 = zero4(), p2 = zero4(), p3 = zero4();
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {               // users 16 q .. 16 q + 15
-          if (16 * q < U) {
-            float2 hv[4];
-            load_h_row<4>(InC32{}, Hn, B, U, b0, L.c, q, L.g, hv);
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-              if (16 * q + 4 * t < U) {
-                p1 = mfma4(hv[t].x, vv[4 * q + t].x, p1);
-                p2 = mfma4(hv[t].y, vv[4 * q + t].y, p2);
-                p3 = mfma4(hv[t].x + hv[t].y, vs[4 * q + t], p3);
-              }
-            }
+        for (int t = 0; t < 16; ++t) {
+          if (t < nk) {                              // users 4 t .. exist
+            p1 = mfma4(hc[t].x, vv[t].x, p1);
+            p2 = mfma4(hc[t].y, vv[t].y, p2);
+            p3 = mfma4(hc[t].x + hc[t].y, vs[t], p3);
           }
         }
 #pragma unroll
@@ -400,8 +476,12 @@ __global__ __launch_bounds__(256) void precode_wide_kernel(PrecodeParams prm) {
           const float qr = p1[jj] - p2[jj], qi = p3[jj] - p1[jj] - p2[jj];
           bstore2(rq, (bb < B && s < S) ? (uint32_t)(bb * S + s) * 8u : kOOB, qr * scl, qi * scl);
         }
+        if (b1 < B) {
+#pragma unroll
+          for (int t = 0; t < 16; ++t) hc[t] = hn[t];
+        }
       }
-      if (prm.qnorm && L.w == 0 && L.c == 0) {
+      if (prm.qnorm && L.r == 0 && L.c == 0) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int ss = s0 + 4 * L.g + j;
