@@ -129,6 +129,8 @@ def main():
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the per-configuration leg (32x8, 128x8 SNR sweep, 128x32, "
                          "256x32 correlated, Gram-stage MFMA utilisation)")
+    ap.add_argument("--no-wide", action="store_true",
+                    help="skip the more-than-32-users leg (128x48, 128x64)")
     ap.add_argument("--no-comparison", action="store_true",
                     help="skip the comparison-methods leg (Cholesky, Neumann, CGLS, CG-D vs K)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -494,6 +496,8 @@ def main():
 
     if not args.no_configs:
         result["configs"] = configs_leg(api, autotune, kernel_time, dev, samples)
+    if not args.no_wide:
+        result["users_over_32"] = wide_leg(api, kernel_time, dev, samples)
 
     if not args.no_comparison:
         result["comparison"] = comparison_leg(api, autotune, H, Y, T, llr, Q, up, dn, wl, n,
@@ -631,6 +635,71 @@ def mfma_count(B, U, S, K, op):
         return gram + chunks * (mf + K * matvec + (K + 1) * matvec + (-(-B // 16)) * 3 * nk)
     # precode: Gram, K mat-vecs + one for ||q||^2, q = H v per 16-antenna tile
     return gram + chunks * ((K + 1) * matvec + (-(-B // 16)) * 3 * nk)
+
+
+def mfma_count_wide(B, U, S, K, op):
+    """v_mfma_f32_16x16x4_f32 instructions per subcarrier of the four-wavefront
+    kernels (32 < U <= 64): Gram tiles in three products (roles 0 and 1 three
+    tiles, roles 2 and 3 two; a role without users skips its tiles and
+    matched filter), the three-product matched filter of each role, the
+    CG mat-vec of every role (4 per k-step of 4 users) and, for precoding,
+    ||q||^2 and q = H v (3 per k-step per 16-antenna tile)."""
+    ksteps = -(-B // 4)
+    chunks = -(-S // 16)
+    nk = -(-U // 4)
+    roles = [r for r in range(4) if 16 * r < U]
+    gram = ksteps * sum(9 if r < 2 else 6 for r in roles)
+    mf = ksteps * 3 * len(roles)
+    matvec = 4 * 4 * nk
+    if op == "detect":
+        return gram + chunks * (mf + K * matvec)
+    return gram + chunks * ((K + 1) * matvec + (-(-B // 16)) * 3 * nk)
+
+
+def wide_leg(api, kernel_time, dev, samples):
+    """Detection and precoding with more than 32 users (the four-wavefront
+    kernels) on 4,800 subcarriers x 14 symbols of 128x48 and 128x64 (64-QAM,
+    15 dB, K = 4, i.i.d. channel): time, HBM rate, issued-MFMA rate, and
+    sampled subcarriers against the oracle."""
+    import torch
+    from paper_1404_0424_amd import workload as W
+    out = {}
+    n, B, S, K, m, snr = 4800, 128, 14, 4, 6, 15.0
+    for U in (48, 64):
+        rng = W.rng_for(9, U)
+        up = W.uplink_frame(rng, n, B, U, S, m, snr)
+        dn = W.downlink_frame(rng, n, B, U, S, m, snr, H=up.H)
+        H = torch.from_numpy(up.H.astype(np.complex64)).to(dev)
+        Y = torch.from_numpy(up.Y.astype(np.complex64)).to(dev)
+        T = torch.from_numpy(dn.T.astype(np.complex64)).to(dev)
+        llr = torch.empty((n, U, S, m), dtype=torch.float32, device=dev)
+        Q = torch.empty((n, B, S), dtype=torch.complex64, device=dev)
+        fd = lambda: api.detect_cg(H, Y, up.n0, up.es, K, m, "approx", "f32", out={"llr": llr})
+        fp = lambda: api.precode_cg(H, T, dn.beta, K, True, "f32", qnorm=False, out=Q)
+        td, tp = kernel_time(fd, reps=10), kernel_time(fp, reps=10)
+        o = api.detect_cg(H, Y, up.n0, up.es, K, m, "approx", "f32", xhat=True,
+                          out={"llr": llr})
+        idx = sample_index(n, 12, 5)
+        samples += [detect_sample(f"wide_128x{U}/detect", idx, up.H, up.Y, up.n0, up.es, K, m, o),
+                    precode_sample(f"wide_128x{U}/precode", idx, up.H, dn.T, dn.beta, K, Q)]
+        del o
+        db = detect_bytes_per_sc(B, U, S, m) * n
+        pb = precode_bytes_per_sc(B, U, S) * n
+        fd_fl = mfma_count_wide(B, U, S, K, "detect") * n * MFMA_FLOPS
+        fp_fl = mfma_count_wide(B, U, S, K, "precode") * n * MFMA_FLOPS
+        out[f"128x{U}"] = {
+            "subcarriers": n, "S": S, "K": K, "qam_bits": m,
+            "detect_ms": td * 1e3, "precode_ms": tp * 1e3,
+            "uplink_solves_per_s": n * S / td, "downlink_solves_per_s": n * S / tp,
+            "detect_hbm_gbs": db / td / 1e9, "precode_hbm_gbs": pb / tp / 1e9,
+            "detect_mfma_frac": fd_fl / td / MFMA_PEAK_FP32,
+            "precode_mfma_frac": fp_fl / tp / MFMA_PEAK_FP32}
+        log(f"U = {U} (128x{U}, {n} subcarriers): detect {td * 1e3:.3f} ms "
+            f"({fd_fl / td / MFMA_PEAK_FP32:.2f} of FP32 MFMA peak issued), precode "
+            f"{tp * 1e3:.3f} ms ({fp_fl / tp / MFMA_PEAK_FP32:.2f})")
+        del H, Y, T, llr, Q
+        torch.cuda.empty_cache()
+    return out
 
 
 def configs_leg(api, autotune, kernel_time, dev, samples):

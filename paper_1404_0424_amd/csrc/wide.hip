@@ -39,6 +39,11 @@ struct WideLds {
   float G[kWideUsers];                       // raw diagonal G_uu
 };
 
+// After the Gram phase A's LDS holds each role's LLR tile (16 users x 16
+// right-hand sides x up to 8 bits).
+static_assert(kWideTiles * 16 * 16 * 8 * sizeof(float) <= sizeof(float2) * kWideUsers * kWideAst,
+              "LLR staging tiles must fit in A's LDS");
+
 // Lane (c, g) of the wavefront in role r: user 16 r + c, right-hand sides
 // s0 + 4 g + j.
 struct WideLane {
@@ -58,10 +63,16 @@ struct WideAcc {
 // k-steps (4 antennas each) per load group: two groups are in registers
 constexpr int kWideUnrDetect = 2;
 constexpr int kWideUnrPrecode = 2;
+// Cache policy of the Gram-phase loads of H and Y: the default one.  Two or
+// three roles load each antenna row of H at different times, and the
+// precoder reads H again for q = H v; marked non-temporal, lines left the
+// caches before their other readers came (detection 1.11 vs 1.12 ms,
+// precoding 1.38 vs 1.45 ms per 19,200 subcarriers of 128x64).
+constexpr int kWideGramCPol = 0;
 
 // One group of 4 UNR antennas: lane (c, g) holds H[b0 + 4 t + g][16 q_j + c]
 // of the NH tiles q_j the role needs (q_0 = r) and Y[b0 + 4 t + g][s0 + c].
-template <int NH, int UNR, bool DO_MF>
+template <int NH, int UNR, bool DO_MF, int CPOL>
 struct WideGroup {
   float2 h[UNR][NH];
   float2 y[UNR];
@@ -72,8 +83,8 @@ struct WideGroup {
     for (int t = 0; t < UNR; ++t) {
       const int b = b0 + 4 * t;
 #pragma unroll
-      for (int j = 0; j < NH; ++j) h[t][j] = bload2(rh, oh[j], (uint32_t)b * U * 8u);
-      if (DO_MF) y[t] = bload2(ry, oy, (uint32_t)b * S * 8u);
+      for (int j = 0; j < NH; ++j) h[t][j] = bload2<CPOL>(rh, oh[j], (uint32_t)b * U * 8u);
+      if (DO_MF) y[t] = bload2<CPOL>(ry, oy, (uint32_t)b * S * 8u);
     }
   }
   template <bool DO_GRAM>
@@ -104,12 +115,12 @@ struct WideGroup {
 
 // The antennas in groups of 4 UNR, the next group's loads in flight while
 // the current group's MFMAs run.
-template <int NH, int UNR, bool DO_GRAM, bool DO_MF>
+template <int NH, int UNR, bool DO_GRAM, bool DO_MF, int CPOL>
 __device__ __forceinline__ void wide_stream(__amdgpu_buffer_rsrc_t rh, const uint32_t (&oh)[3],
                                             __amdgpu_buffer_rsrc_t ry, uint32_t oy, int B, int U,
                                             int S, WideAcc& acc) {
   constexpr int GA = 4 * UNR;                      // antennas per group
-  WideGroup<NH, UNR, DO_MF> g0, g1;
+  WideGroup<NH, UNR, DO_MF, CPOL> g0, g1;
   g0.load(rh, oh, ry, oy, U, S, 0);
   for (int b0 = 0; b0 < B; b0 += 2 * GA) {
     if (b0 + GA < B) g1.load(rh, oh, ry, oy, U, S, b0 + GA);
@@ -123,7 +134,7 @@ __device__ __forceinline__ void wide_stream(__amdgpu_buffer_rsrc_t rh, const uin
 // Role r's Gram tiles (DO_GRAM) and matched filter for right-hand sides
 // s0 .. s0 + 15 (DO_MF).  A role whose users are all padding (16 r >= U)
 // has zero tiles and b.
-template <int UNR, bool DO_GRAM, bool DO_MF>
+template <int UNR, int CPOL, bool DO_GRAM, bool DO_MF>
 __device__ __forceinline__ void wide_gram_mf(const void* Hn, const void* Yn, int B, int U, int S,
                                              int s0, const WideLane& L, WideAcc& acc) {
 #pragma unroll
@@ -143,9 +154,9 @@ __device__ __forceinline__ void wide_gram_mf(const void* Hn, const void* Yn, int
   }
   const int s = s0 + L.c;
   const uint32_t oy = s < S ? (uint32_t)(L.g * S + s) * 8u : kOOB;
-  if (!DO_GRAM) wide_stream<1, UNR, false, DO_MF>(rh, oh, ry, oy, B, U, S, acc);
-  else if (L.r < 2) wide_stream<3, UNR, true, DO_MF>(rh, oh, ry, oy, B, U, S, acc);
-  else wide_stream<2, UNR, true, DO_MF>(rh, oh, ry, oy, B, U, S, acc);
+  if (!DO_GRAM) wide_stream<1, UNR, false, DO_MF, CPOL>(rh, oh, ry, oy, B, U, S, acc);
+  else if (L.r < 2) wide_stream<3, UNR, true, DO_MF, CPOL>(rh, oh, ry, oy, B, U, S, acc);
+  else wide_stream<2, UNR, true, DO_MF, CPOL>(rh, oh, ry, oy, B, U, S, acc);
 }
 
 // Role r's tiles and their conjugate mirrors into A = G + reg I in LDS
@@ -296,16 +307,22 @@ __device__ __forceinline__ void wide_cg_step(CGState<1, ST>& st, const float2 (&
 }
 
 // mu (eq. (14)), rho (eq. (15)), z = xhat / mu and the max-log LLRs (eq. (4))
-// of the wavefront's users for right-hand sides s0 + 4 g + j, and their
-// stores (masked entries dropped by the descriptors' range check).
-template <typename ST, int M_BITS>
+// of the role's users for right-hand sides s0 + 4 g + j, and their stores
+// (masked entries dropped by the descriptors' range check).  STAGE (one
+// chunk of right-hand sides, S <= 16): the role's LLRs, 16 users x S x
+// M_BITS floats contiguous in memory, are assembled in `stg` (LDS of the
+// role, 16 x 16 x M_BITS floats) and written in 16- or 8-byte pieces, so
+// every store instruction covers whole cache lines; scattered pieces would
+// let partly written lines leave L2 and reach HBM more than once.
+template <typename ST, int M_BITS, bool STAGE>
 __device__ __forceinline__ void wide_llr(const DetectParams& prm, int64_t n, int s0,
                                          const float2 (&v)[4], const ST (&tv)[4], const float* Gs,
-                                         const WideLane& L) {
+                                         const WideLane& L, float* __restrict__ stg) {
+  const int U = prm.U, S = prm.S;
   DetectStore<M_BITS> os;
   os.init(prm, n);
   const int u = 16 * L.r + L.c;
-  const bool uok = u < prm.U;
+  const bool uok = u < U;
   const float Guu = Gs[uok ? u : 0];
   const float rho = Guu / prm.n0;
 #pragma unroll
@@ -317,7 +334,39 @@ __device__ __forceinline__ void wide_llr(const DetectParams& prm, int64_t n, int
     const float2 z = make_float2(v[j].x * imu, v[j].y * imu);
     float out[M_BITS];
     llr_maxlog<M_BITS>(z, rho, prm.scale, prm.inv_scale, out);
-    os.store((uok && s < prm.S) ? u * prm.S + s : -1, out, v[j], mu, rho);
+    const int e = (uok && s < S) ? u * S + s : -1;
+    if (STAGE) {
+      if (e >= 0) {
+        float* sp = stg + (L.c * S + s) * M_BITS;
+#pragma unroll
+        for (int q = 0; q < M_BITS; ++q) sp[q] = out[q];
+      }
+      os.store_aux(e, v[j], mu, rho);
+    } else {
+      os.store(e, out, v[j], mu, rho);
+    }
+  }
+  if (STAGE) {
+    wave_lds_sync();
+    const int nu = U - 16 * L.r < 16 ? U - 16 * L.r : 16;    // >= 1: the role has users
+    const int total = nu * S * M_BITS;                       // floats, even
+    const uint32_t per = (uint32_t)(U * S * M_BITS);
+    const __amdgpu_buffer_rsrc_t rl =
+        make_rsrc(prm.llr + (size_t)n * per + (size_t)(16 * L.r) * S * M_BITS,
+                  (uint32_t)total * 4u);
+    if ((total & 3) == 0) {                                  // 16-byte pieces
+      const float4* src = (const float4*)stg;
+      for (int o = L.lane; o < total / 4; o += kWave) {
+        const float4 q = src[o];
+        bstore4(rl, (uint32_t)o * 16u, q.x, q.y, q.z, q.w);
+      }
+    } else {
+      const float2* src = (const float2*)stg;
+      for (int o = L.lane; o < total / 2; o += kWave) {
+        const float2 q = src[o];
+        bstore2(rl, (uint32_t)o * 8u, q.x, q.y);
+      }
+    }
   }
 }
 
@@ -342,10 +391,10 @@ __global__ __launch_bounds__(256, 2) void detect_wide_kernel(DetectParams prm) {
     for (int s0 = 0; s0 < S; s0 += 16) {
       WideAcc acc;
       if (s0 == 0) {
-        wide_gram_mf<kWideUnrDetect, true, true>(Hn, Yn, B, U, S, s0, L, acc);
+        wide_gram_mf<kWideUnrDetect, kWideGramCPol, true, true>(Hn, Yn, B, U, S, s0, L, acc);
         wide_store_a<ST>(acc, lds, prm.reg, L, a, d[0]);
       } else {
-        wide_gram_mf<kWideUnrDetect, false, true>(Hn, Yn, B, U, S, s0, L, acc);
+        wide_gram_mf<kWideUnrDetect, kWideGramCPol, false, true>(Hn, Yn, B, U, S, s0, L, acc);
       }
       float2 b[4];
 #pragma unroll
@@ -362,7 +411,14 @@ __global__ __launch_bounds__(256, 2) void detect_wide_kernel(DetectParams prm) {
         wide_cg_step<ST>(st, a, nk, lds, L, al, be);
         tracker_step<1, ST>(tk, d, al, be);
       }
-      wide_llr<ST, M_BITS>(prm, n, s0, st.v[0], tk.tv[0], lds.G, L);
+      // the LLR tile of each role goes through its part of A's LDS (A is
+      // in registers since the Gram phase; the CG's barriers follow every
+      // read of it)
+      if (16 * L.r < U) {
+        float* stg = (float*)lds.A + L.r * (16 * 16 * M_BITS);
+        if (S <= 16) wide_llr<ST, M_BITS, true>(prm, n, s0, st.v[0], tk.tv[0], lds.G, L, stg);
+        else wide_llr<ST, M_BITS, false>(prm, n, s0, st.v[0], tk.tv[0], lds.G, L, stg);
+      }
     }
     __syncthreads();                                 // LDS of this subcarrier read by all
   }
@@ -393,7 +449,7 @@ __global__ __launch_bounds__(256, 2) void precode_wide_kernel(PrecodeParams prm)
     float d;
     {
       WideAcc acc;
-      wide_gram_mf<kWideUnrPrecode, true, false>(Hn, nullptr, B, U, S, 0, L, acc);
+      wide_gram_mf<kWideUnrPrecode, kWideGramCPol, true, false>(Hn, nullptr, B, U, S, 0, L, acc);
       wide_store_a<ST>(acc, lds, prm.beta, L, a, d);
     }
     const __amdgpu_buffer_rsrc_t rh = make_rsrc(Hn, (uint32_t)B * U * 8u);

@@ -37,6 +37,17 @@ def test_mfma_counts_match_the_instruction_counters():
     assert bench.mfma_count(64, 20, 14, 2, "detect") == 16 * 10 + 16 * 6 + 2 * 4 * 2 * 5
 
 
+def test_wide_mfma_counts_match_the_instruction_counters():
+    # SQ_INSTS_MFMA read 45,465,600 (detection) and 50,380,800 (precoding)
+    # per launch of 19,200 subcarriers of 128x64 (K = 4, S = 14)
+    assert bench.mfma_count_wide(128, 64, 14, 4, "detect") * 19200 == 45465600
+    assert bench.mfma_count_wide(128, 64, 14, 4, "precode") * 19200 == 50380800
+    # U = 40: role 3 has no users (no tiles, no matched filter); the
+    # mat-vec runs over the 10 k-steps of real users in all four roles
+    assert bench.mfma_count_wide(128, 40, 14, 4, "detect") == \
+        32 * (9 + 9 + 6) + 32 * 3 * 3 + 4 * 16 * 10
+
+
 def test_recorded_traffic_only_for_matching_launch():
     for persistent in (False, True):
         rec = bench.recorded_traffic("detect_stream_kernel", "mixed_128x16", 19200, persistent)
