@@ -15,7 +15,7 @@ namespace mimo {
 // compute within the wave as well as across waves.
 // VALU: CG mat-vec on VALU FMAs (schedule variant "stream-valu").
 template <int W, typename IN, typename ST, int M_BITS, bool SMALL, bool VALU = false>
-__global__ __launch_bounds__(256, 2) void detect_stream_kernel(DetectParams prm) {
+__global__ __launch_bounds__(256, 2) void detect_stream_kernel(DetectParams kprm) {
   constexpr int NU = 16 * W;
   constexpr int AST = NU + 2;   // LDS row stride (complex) of A
   using Sub = typename Storage<IN, W>::Sub;
@@ -32,17 +32,20 @@ __global__ __launch_bounds__(256, 2) void detect_stream_kernel(DetectParams prm)
   float2* As = (float2*)W_s[wv];
   float2* Ps = As + NU * AST;
   float* Gs = G_s[wv];
-  const int B = prm.B, U = prm.U, S = prm.S;
   const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
 
   int64_t n = (int64_t)blockIdx.x * kWavesPerBlock + wv;
   Sub cur;
   Blk blk;
-  if (n < prm.n_sc) {
-    cur.init(offset_sc(IN{}, prm.H, n, B, U), offset_sc(IN{}, prm.Y, n, B, S), B, U, S, 0, c, g);
+  if (n < kprm.n_sc) {
+    const int B = kprm.B, U = kprm.U, S = kprm.S;
+    cur.init(offset_sc(IN{}, kprm.H, n, B, U), offset_sc(IN{}, kprm.Y, n, B, S), B, U, S, 0, c,
+             g);
     blk.template load<true>(cur, 0);
   }
-  while (n < prm.n_sc) {
+  while (n < kprm.n_sc) {
+    const DetectParams prm = opaque_sizes(kprm);
+    const int B = prm.B, U = prm.U, S = prm.S;
     const int64_t nn = n + stride;
     const int64_t nc = nn < prm.n_sc ? nn : n;        // descriptors only used if nn < n_sc
     Sub nxt;
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(256, 2) void detect_approx_kernel(DetectParams prm)
   float2* Ps = As + NU * AST;
   for (int64_t n = (int64_t)blockIdx.x * kWavesPerBlock + wv; n < prm.n_sc;
        n += (int64_t)gridDim.x * kWavesPerBlock)
-    detect_one<W, IN, ST, M_BITS>(prm, n, As, Ps, G_s[wv], c, g, W_s[wv]);
+    detect_one<W, IN, ST, M_BITS>(opaque_sizes(prm), n, As, Ps, G_s[wv], c, g, W_s[wv]);
 }
 
 // Batched kernel: frames of different shapes (same user class, QAM order,

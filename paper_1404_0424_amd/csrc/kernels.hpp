@@ -53,6 +53,33 @@ struct GramParams {
   float2* b;            // [n_sc][U][S] or null
 };
 
+// A wave-uniform int hidden from the optimizer.  The kernels pass their
+// sizes through it at the top of each subcarrier iteration: the sizes then
+// change per iteration as far as the compiler can tell, so the per-k-step
+// and per-tile masks and offsets derived from them are recomputed on the
+// scalar unit where they are used, instead of being hoisted out of the
+// subcarrier loop and kept live across it.  Dozens of hoisted values
+// overflow the scalar registers, and each spilled one then costs a VALU
+// lane read at every use.
+__device__ __forceinline__ int opaque_int(int x) {
+  asm volatile("" : "+s"(x));
+  return x;
+}
+__device__ __forceinline__ DetectParams opaque_sizes(DetectParams p) {
+  p.B = opaque_int(p.B);
+  p.U = opaque_int(p.U);
+  p.S = opaque_int(p.S);
+  p.K = opaque_int(p.K);
+  return p;
+}
+__device__ __forceinline__ PrecodeParams opaque_sizes(PrecodeParams p) {
+  p.B = opaque_int(p.B);
+  p.U = opaque_int(p.U);
+  p.S = opaque_int(p.S);
+  p.K = opaque_int(p.K);
+  return p;
+}
+
 // Batched launches: up to kMaxBatch frames of different shapes in one
 // kernel, passed by value in the kernel arguments.
 constexpr int kMaxBatch = 32;

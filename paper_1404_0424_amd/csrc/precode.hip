@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256, 2) void precode_kernel(PrecodeParams prm) {
   const int c = lane & 15, g = lane >> 4;
   for (int64_t n = (int64_t)blockIdx.x * kWavesPerBlock + wv; n < prm.n_sc;
        n += (int64_t)gridDim.x * kWavesPerBlock)
-    precode_one<W, IN, ST>(prm, n, A_s[wv], P_s[wv], G_s[wv], N_s[wv], c, g);
+    precode_one<W, IN, ST>(opaque_sizes(prm), n, A_s[wv], P_s[wv], G_s[wv], N_s[wv], c, g);
 }
 
 // Streaming kernel for S <= 16 (one right-hand-side chunk): the Gram's H
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256, 2) void precode_kernel(PrecodeParams prm) {
 // the last subcarrier), so the compiler's load-counter waits cover exactly
 // the block consumed.  Same arithmetic in the same order as precode_one.
 template <int W, typename IN, typename ST, bool SMALL>
-__global__ __launch_bounds__(256, 2) void precode_stream_kernel(PrecodeParams prm) {
+__global__ __launch_bounds__(256, 2) void precode_stream_kernel(PrecodeParams kprm) {
   constexpr int NU = 16 * W;
   constexpr int AST = NU + 2;
   using Sub = typename Storage<IN, W>::Sub;
@@ -99,17 +99,18 @@ __global__ __launch_bounds__(256, 2) void precode_stream_kernel(PrecodeParams pr
   float2* Ps = P_s[wv];
   float* Gs = G_s[wv];
   float* Ns = N_s[wv];
-  const int B = prm.B, U = prm.U, S = prm.S;
   const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
 
   int64_t n = (int64_t)blockIdx.x * kWavesPerBlock + wv;
   Sub cur;
   Blk blk;
-  if (n < prm.n_sc) {
-    cur.init(offset_sc(IN{}, prm.H, n, B, U), nullptr, B, U, S, 0, c, g);
+  if (n < kprm.n_sc) {
+    cur.init(offset_sc(IN{}, kprm.H, n, kprm.B, kprm.U), nullptr, kprm.B, kprm.U, kprm.S, 0, c, g);
     blk.template load<false>(cur, 0);
   }
-  while (n < prm.n_sc) {
+  while (n < kprm.n_sc) {
+    const PrecodeParams prm = opaque_sizes(kprm);
+    const int B = prm.B, U = prm.U, S = prm.S;
     const int64_t nn = n + stride;
     const int64_t nc = nn < prm.n_sc ? nn : n;
     Sub nxt;
@@ -170,7 +171,7 @@ constexpr int resident_min_blocks() { return sizeof(ST) == 8 ? 2 : 3; }
 
 template <int BMAX, typename IN, typename ST>
 __global__ __launch_bounds__(256, resident_min_blocks<ST>()) void precode_resident_kernel(
-    PrecodeParams prm) {
+    PrecodeParams kprm) {
   constexpr int NU = 16, AST = NU + 2;
   using Sub = typename Storage<IN, 1>::Sub;
   using RB = typename ResidentBlock<IN>::type;
@@ -188,24 +189,25 @@ __global__ __launch_bounds__(256, resident_min_blocks<ST>()) void precode_reside
   float2* H2 = H2_s[wv];
   float* Gs = G_s[wv];
   float* Ns = N_s[wv];
-  const int B = prm.B, U = prm.U, S = prm.S;
   const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
   uint32_t ot[4];                                                      // T[c][4 g + j]
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int s = 4 * g + j;
-    ot[j] = (c < U && s < S) ? (uint32_t)(c * S + s) * 8u : kOOB;
+    ot[j] = (c < kprm.U && s < kprm.S) ? (uint32_t)(c * kprm.S + s) * 8u : kOOB;
   }
 
   int64_t n = (int64_t)blockIdx.x * kWavesPerBlock + wv;
   RB hb[NK];
-  if (n < prm.n_sc) {
+  if (n < kprm.n_sc) {
     Sub cur;
-    cur.init(offset_sc(IN{}, prm.H, n, B, U), nullptr, B, U, S, 0, c, g);
+    cur.init(offset_sc(IN{}, kprm.H, n, kprm.B, kprm.U), nullptr, kprm.B, kprm.U, kprm.S, 0, c, g);
 #pragma unroll
     for (int t = 0; t < NK; ++t) hb[t].template load<false, kOnceCPol>(cur, t * RB::ANT);
   }
-  while (n < prm.n_sc) {
+  while (n < kprm.n_sc) {
+    const PrecodeParams prm = opaque_sizes(kprm);
+    const int B = prm.B, U = prm.U, S = prm.S;
     const int64_t nn = n + stride;
     float2 b[1][4];                                   // b = t
     {

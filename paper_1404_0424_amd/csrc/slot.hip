@@ -61,8 +61,6 @@ __global__ __launch_bounds__(256, kSlotMinBlocks) void slot_resident_kernel(Slot
   __shared__ __align__(16) float W_s[kWavesPerBlock][APH > STG ? APH : STG];
   __shared__ float G_s[kWavesPerBlock][NU];
   __shared__ float N_s[kWavesPerBlock][16];
-  const DetectParams& ul = sp.ul;
-  const PrecodeParams& dl = sp.dl;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const int c = lane & 15, g = lane >> 4;
@@ -72,8 +70,7 @@ __global__ __launch_bounds__(256, kSlotMinBlocks) void slot_resident_kernel(Slot
   float2* Qs = H2 + NU * kPST;                        // output tile of the downlink
   float* Gs = G_s[wv];
   float* Ns = N_s[wv];
-  const int B = ul.B, U = ul.U, Su = ul.S, Sd = dl.S;
-  const int64_t n_sc = ul.n_sc;
+  const int64_t n_sc = sp.ul.n_sc;
   const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
 
   int64_t n = (int64_t)blockIdx.x * kWavesPerBlock + wv;
@@ -81,13 +78,18 @@ __global__ __launch_bounds__(256, kSlotMinBlocks) void slot_resident_kernel(Slot
   float2 yv[NY];
   Sub cur;
   if (n < n_sc) {
-    cur.init(offset_sc(IN{}, ul.H, n, B, U), offset_sc(IN{}, ul.Y, n, B, Su), B, U, Su, 0, c, g);
+    const int B = sp.ul.B, U = sp.ul.U, Su = sp.ul.S;
+    cur.init(offset_sc(IN{}, sp.ul.H, n, B, U), offset_sc(IN{}, sp.ul.Y, n, B, Su), B, U, Su, 0,
+             c, g);
 #pragma unroll
     for (int t = 0; t < NK; ++t) hb[t].template load<false, kOnceCPol>(cur, t * RB::ANT);
 #pragma unroll
     for (int t = 0; t < NY; ++t) yv[t] = load_y_step(cur, t);
   }
   while (n < n_sc) {
+    const DetectParams ul = opaque_sizes(sp.ul);
+    const PrecodeParams dl = opaque_sizes(sp.dl);
+    const int B = ul.B, U = ul.U, Su = ul.S, Sd = dl.S;
     const int64_t nn = n + stride;
     const int64_t nc = nn < n_sc ? nn : n;            // descriptors only used if nn < n_sc
     Sub nxt;

@@ -378,11 +378,12 @@ __device__ __forceinline__ WideLane wide_lane(int64_t n) {
 }
 
 template <typename ST, int M_BITS>
-__global__ __launch_bounds__(256, 2) void detect_wide_kernel(DetectParams prm) {
+__global__ __launch_bounds__(256, 2) void detect_wide_kernel(DetectParams kprm) {
   __shared__ __align__(16) WideLds<ST> lds;
-  const int B = prm.B, U = prm.U, S = prm.S;
-  const int nk = __builtin_amdgcn_readfirstlane((U + 3) >> 2);
-  for (int64_t n = blockIdx.x; n < prm.n_sc; n += gridDim.x) {
+  for (int64_t n = blockIdx.x; n < kprm.n_sc; n += gridDim.x) {
+    const DetectParams prm = opaque_sizes(kprm);
+    const int B = prm.B, U = prm.U, S = prm.S;
+    const int nk = (U + 3) >> 2;
     const WideLane L = wide_lane(n);
     const void* Hn = offset_sc(InC32{}, prm.H, n, B, U);
     const void* Yn = offset_sc(InC32{}, prm.Y, n, B, S);
@@ -437,11 +438,12 @@ __device__ __forceinline__ void wide_load_hrows(__amdgpu_buffer_rsrc_t rh, int U
 }
 
 template <typename ST>
-__global__ __launch_bounds__(256, 2) void precode_wide_kernel(PrecodeParams prm) {
+__global__ __launch_bounds__(256, 2) void precode_wide_kernel(PrecodeParams kprm) {
   __shared__ __align__(16) WideLds<ST> lds;
-  const int B = prm.B, U = prm.U, S = prm.S;
-  const int nk = __builtin_amdgcn_readfirstlane((U + 3) >> 2);
-  for (int64_t n = blockIdx.x; n < prm.n_sc; n += gridDim.x) {
+  for (int64_t n = blockIdx.x; n < kprm.n_sc; n += gridDim.x) {
+    const PrecodeParams prm = opaque_sizes(kprm);
+    const int B = prm.B, U = prm.U, S = prm.S;
+    const int nk = (U + 3) >> 2;
     const WideLane L = wide_lane(n);
     const int u = 16 * L.r + L.c;
     const void* Hn = offset_sc(InC32{}, prm.H, n, B, U);
