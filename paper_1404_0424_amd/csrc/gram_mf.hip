@@ -58,7 +58,7 @@ __global__ __launch_bounds__(256) void gram_mf_kernel(GramParams prm) {
 // written.  Loads are issued on every path (an empty descriptor after the
 // last subcarrier).  Same arithmetic in the same order as gram_mf_kernel.
 template <int W, typename IN, bool HAS_Y>
-__global__ __launch_bounds__(256, W == 1 ? 3 : 2) void gram_mf_stream_kernel(GramParams prm) {
+__global__ __launch_bounds__(256, W == 1 ? 3 : 2) void gram_mf_stream_kernel(GramParams kprm) {
   constexpr int NU = 16 * W;
   constexpr int AST = NU + 2;
   using Sub = typename Storage<IN, W>::Sub;
@@ -70,22 +70,26 @@ __global__ __launch_bounds__(256, W == 1 ? 3 : 2) void gram_mf_stream_kernel(Gra
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const int c = lane & 15, g = lane >> 4;
   float2* As = A_s[wv];
-  const int B = prm.B, U = prm.U, S = prm.S;
   const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
-  auto y_of = [&](int64_t m) { return HAS_Y ? offset_sc(IN{}, prm.Y, m, B, S) : nullptr; };
+  auto y_of = [&](int64_t m, int B, int S) {
+    return HAS_Y ? offset_sc(IN{}, kprm.Y, m, B, S) : nullptr;
+  };
 
   int64_t n = (int64_t)blockIdx.x * kWavesPerBlock + wv;
   Sub cur;
   Blk blk;
-  if (n < prm.n_sc) {
-    cur.init(offset_sc(IN{}, prm.H, n, B, U), y_of(n), B, U, S, 0, c, g);
+  if (n < kprm.n_sc) {
+    const int B = kprm.B, U = kprm.U, S = kprm.S;
+    cur.init(offset_sc(IN{}, kprm.H, n, B, U), y_of(n, B, S), B, U, S, 0, c, g);
     blk.template load<HAS_Y>(cur, 0);
   }
-  while (n < prm.n_sc) {
+  while (n < kprm.n_sc) {
+    const GramParams prm = opaque_sizes(kprm);
+    const int B = prm.B, U = prm.U, S = prm.S;
     const int64_t nn = n + stride;
     const int64_t nc = nn < prm.n_sc ? nn : n;
     Sub nxt;
-    nxt.init(offset_sc(IN{}, prm.H, nc, B, U), y_of(nc), B, U, S, 0, c, g);
+    nxt.init(offset_sc(IN{}, prm.H, nc, B, U), y_of(nc, B, S), B, U, S, 0, c, g);
     if (nn >= prm.n_sc) nxt.disable();
     GramAcc<W> acc;
     acc.clear();

@@ -166,21 +166,24 @@ __global__ __launch_bounds__(64) void detect_inverse_kernel(DetectParams prm) {
 // walks several subcarriers with the Gram's loads streamed (gram_stream).
 // Same arithmetic in the same order as detect_inverse_kernel.
 template <int W, typename IN, int M_BITS, int METHOD>
-__global__ __launch_bounds__(64, W == 2 ? 1 : (METHOD == kInvCholesky ? 4 : 3)) void detect_inverse_stream_kernel(DetectParams prm) {
+__global__ __launch_bounds__(64, W == 2 ? 1 : (METHOD == kInvCholesky ? 4 : 3)) void detect_inverse_stream_kernel(DetectParams kprm) {
   using Sub = typename Storage<IN, W>::Sub;
   using Blk = typename Storage<IN, W>::SmallBlock;
   __shared__ InverseLds<W> sm;
   const int lane = threadIdx.x;
   const int c = lane & 15, g = lane >> 4;
-  const int B = prm.B, U = prm.U, S = prm.S;
   int64_t n = blockIdx.x;
   Sub cur;
   Blk blk;
-  if (n < prm.n_sc) {
-    cur.init(offset_sc(IN{}, prm.H, n, B, U), offset_sc(IN{}, prm.Y, n, B, S), B, U, S, 0, c, g);
+  if (n < kprm.n_sc) {
+    const int B = kprm.B, U = kprm.U, S = kprm.S;
+    cur.init(offset_sc(IN{}, kprm.H, n, B, U), offset_sc(IN{}, kprm.Y, n, B, S), B, U, S, 0, c,
+             g);
     blk.template load<true>(cur, 0);
   }
-  while (n < prm.n_sc) {
+  while (n < kprm.n_sc) {
+    const DetectParams prm = opaque_sizes(kprm);
+    const int B = prm.B, U = prm.U, S = prm.S;
     const int64_t nn = n + gridDim.x;
     const int64_t nc = nn < prm.n_sc ? nn : n;
     Sub nxt;
@@ -251,21 +254,23 @@ __global__ __launch_bounds__(64) void precode_inverse_kernel(PrecodeParams prm) 
 
 // Streaming form for S <= 16 (see detect_inverse_stream_kernel).
 template <int W, typename IN, int METHOD>
-__global__ __launch_bounds__(64, W == 1 ? 4 : 1) void precode_inverse_stream_kernel(PrecodeParams prm) {
+__global__ __launch_bounds__(64, W == 1 ? 4 : 1) void precode_inverse_stream_kernel(PrecodeParams kprm) {
   using Sub = typename Storage<IN, W>::Sub;
   using Blk = typename Storage<IN, W>::SmallBlock;
   __shared__ InverseLds<W> sm;
   const int lane = threadIdx.x;
   const int c = lane & 15, g = lane >> 4;
-  const int B = prm.B, U = prm.U, S = prm.S;
   int64_t n = blockIdx.x;
   Sub cur;
   Blk blk;
-  if (n < prm.n_sc) {
-    cur.init(offset_sc(IN{}, prm.H, n, B, U), nullptr, B, U, S, 0, c, g);
+  if (n < kprm.n_sc) {
+    cur.init(offset_sc(IN{}, kprm.H, n, kprm.B, kprm.U), nullptr, kprm.B, kprm.U, kprm.S, 0, c,
+             g);
     blk.template load<false>(cur, 0);
   }
-  while (n < prm.n_sc) {
+  while (n < kprm.n_sc) {
+    const PrecodeParams prm = opaque_sizes(kprm);
+    const int B = prm.B, U = prm.U, S = prm.S;
     const int64_t nn = n + gridDim.x;
     const int64_t nc = nn < prm.n_sc ? nn : n;
     Sub nxt;

@@ -80,6 +80,13 @@ __device__ __forceinline__ PrecodeParams opaque_sizes(PrecodeParams p) {
   return p;
 }
 
+__device__ __forceinline__ GramParams opaque_sizes(GramParams p) {
+  p.B = opaque_int(p.B);
+  p.U = opaque_int(p.U);
+  p.S = opaque_int(p.S);
+  return p;
+}
+
 // Batched launches: up to kMaxBatch frames of different shapes in one
 // kernel, passed by value in the kernel arguments.
 constexpr int kMaxBatch = 32;
