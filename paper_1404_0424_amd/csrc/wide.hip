@@ -40,7 +40,7 @@ struct WideLds {
 };
 
 // After the Gram phase A's LDS holds each role's LLR tile (16 users x 16
-// right-hand sides x up to 8 bits).
+// right-hand sides x up to 8 bits), or the precoder's 16 x 16 output tile.
 static_assert(kWideTiles * 16 * 16 * 8 * sizeof(float) <= sizeof(float2) * kWideUsers * kWideAst,
               "LLR staging tiles must fit in A's LDS");
 
@@ -528,11 +528,35 @@ __global__ __launch_bounds__(256, 2) void precode_wide_kernel(PrecodeParams kprm
             p3 = mfma4(hc[t].x + hc[t].y, vs[t], p3);
           }
         }
+        if (S <= 16) {
+          // the tile's 16 x S outputs are contiguous in Q: staged in the
+          // role's part of A's LDS (A is in registers since the Gram) and
+          // written in 8-byte pieces, whole lines per store instruction;
+          // rows past B fall outside the descriptor's range
+          float2* Qs = lds.A + L.r * 256;
+          if (s < S) {
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          const int bb = b0 + 4 * L.g + jj;
-          const float qr = p1[jj] - p2[jj], qi = p3[jj] - p1[jj] - p2[jj];
-          bstore2(rq, (bb < B && s < S) ? (uint32_t)(bb * S + s) * 8u : kOOB, qr * scl, qi * scl);
+            for (int jj = 0; jj < 4; ++jj) {
+              const float qr = p1[jj] - p2[jj], qi = p3[jj] - p1[jj] - p2[jj];
+              Qs[(4 * L.g + jj) * S + L.c] = make_float2(qr * scl, qi * scl);
+            }
+          }
+          wave_lds_sync();
+#pragma unroll
+          for (int r4 = 0; r4 < 4; ++r4) {
+            const int e = 64 * r4 + L.lane;
+            const float2 q = Qs[e < 16 * S ? e : 0];
+            bstore2s(rq, e < 16 * S ? (uint32_t)e * 8u : kOOB, (uint32_t)(b0 * S) * 8u, q.x, q.y);
+          }
+          wave_lds_sync();
+        } else {
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) {
+            const int bb = b0 + 4 * L.g + jj;
+            const float qr = p1[jj] - p2[jj], qi = p3[jj] - p1[jj] - p2[jj];
+            bstore2(rq, (bb < B && s < S) ? (uint32_t)(bb * S + s) * 8u : kOOB, qr * scl,
+                    qi * scl);
+          }
         }
         if (b1 < B) {
 #pragma unroll
