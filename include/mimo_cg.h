@@ -99,7 +99,7 @@ typedef enum mimo_status {
  *   b      out, complex64 [n_sc][U][S], or NULL
  * Uses shape->B, U, S, n_sc (K is ignored).
  */
-int mimo_gram_mf(const mimo_shape* shape, const void* H, const void* Y,
+mimo_status mimo_gram_mf(const mimo_shape* shape, const void* H, const void* Y,
                  int in_dtype, float reg, void* A, void* b, void* stream);
 
 /*
@@ -133,7 +133,7 @@ int mimo_gram_mf(const mimo_shape* shape, const void* H, const void* Y,
  * wavefronts per subcarrier, one per 16 users, any B and S); other calls
  * with U > MIMO_MAX_USERS_COMMON return MIMO_EUNSUPPORTED.
  */
-int mimo_detect_cg(const mimo_shape* shape, const void* H, const void* Y,
+mimo_status mimo_detect_cg(const mimo_shape* shape, const void* H, const void* Y,
                    int in_dtype, float n0, float es, int qam_bits,
                    int sinr_mode, int scalar_prec, float* llr, void* xhat,
                    float* mu, float* sinr, void* workspace,
@@ -151,7 +151,7 @@ int mimo_detect_cg(const mimo_shape* shape, const void* H, const void* Y,
  * U beyond MIMO_MAX_USERS_COMMON (up to MIMO_MAX_USERS) with complex64
  * storage only, as mimo_detect_cg.
  */
-int mimo_precode_cg(const mimo_shape* shape, const void* H, const void* T,
+mimo_status mimo_precode_cg(const mimo_shape* shape, const void* H, const void* T,
                     int in_dtype, float beta, int normalize, int scalar_prec,
                     void* Q, float* qnorm, void* workspace,
                     size_t workspace_bytes, void* stream);
@@ -178,7 +178,7 @@ int mimo_precode_cg(const mimo_shape* shape, const void* H, const void* T,
  * as two launches on `stream`.  U up to MIMO_MAX_USERS as mimo_detect_cg
  * and mimo_precode_cg (complex64 storage beyond MIMO_MAX_USERS_COMMON).
  */
-int mimo_detect_precode_cg(const mimo_shape* ul, const mimo_shape* dl, const void* H,
+mimo_status mimo_detect_precode_cg(const mimo_shape* ul, const mimo_shape* dl, const void* H,
                            const void* Y, const void* T, int in_dtype, float n0, float es,
                            int qam_bits, float beta, int normalize, int scalar_prec,
                            float* llr, void* xhat, float* mu, float* sinr, void* Q,
@@ -191,7 +191,7 @@ int mimo_detect_precode_cg(const mimo_shape* ul, const mimo_shape* dl, const voi
  * described above (dst_dtype MIMO_C16 or MIMO_CBF16).  dst holds
  * n*R*C*2 16-bit values.  Storage format only; no method arithmetic.
  */
-int mimo_convert(const void* src, void* dst, int dst_dtype, int64_t n,
+mimo_status mimo_convert(const void* src, void* dst, int dst_dtype, int64_t n,
                  int32_t R, int32_t C, void* stream);
 
 /*
@@ -224,9 +224,9 @@ typedef struct mimo_frame {
   int32_t normalize;     /* precoding */
 } mimo_frame;
 
-int mimo_detect_cg_batch(const mimo_frame* frames, int n_frames, int in_dtype, int qam_bits,
+mimo_status mimo_detect_cg_batch(const mimo_frame* frames, int n_frames, int in_dtype, int qam_bits,
                          int scalar_prec, void* stream);
-int mimo_precode_cg_batch(const mimo_frame* frames, int n_frames, int in_dtype,
+mimo_status mimo_precode_cg_batch(const mimo_frame* frames, int n_frames, int in_dtype,
                           int scalar_prec, void* stream);
 
 /*
@@ -250,16 +250,16 @@ int mimo_precode_cg_batch(const mimo_frame* frames, int n_frames, int in_dtype,
  * mimo_detect_cg.  Precoding: v = X t, q = H_u v (eq. (5) with P of eq. (6)),
  * normalization and qnorm as in mimo_precode_cg.
  */
-int mimo_detect_cholesky(const mimo_shape* shape, const void* H, const void* Y,
+mimo_status mimo_detect_cholesky(const mimo_shape* shape, const void* H, const void* Y,
                          int in_dtype, float n0, float es, int qam_bits,
                          float* llr, void* xhat, float* mu, float* sinr, void* stream);
-int mimo_detect_neumann(const mimo_shape* shape, const void* H, const void* Y,
+mimo_status mimo_detect_neumann(const mimo_shape* shape, const void* H, const void* Y,
                         int in_dtype, float n0, float es, int qam_bits,
                         float* llr, void* xhat, float* mu, float* sinr, void* stream);
-int mimo_precode_cholesky(const mimo_shape* shape, const void* H, const void* T,
+mimo_status mimo_precode_cholesky(const mimo_shape* shape, const void* H, const void* T,
                           int in_dtype, float beta, int normalize, void* Q,
                           float* qnorm, void* stream);
-int mimo_precode_neumann(const mimo_shape* shape, const void* H, const void* T,
+mimo_status mimo_precode_neumann(const mimo_shape* shape, const void* H, const void* T,
                          int in_dtype, float beta, int normalize, void* Q,
                          float* qnorm, void* stream);
 /*
@@ -283,10 +283,10 @@ int mimo_precode_neumann(const mimo_shape* shape, const void* H, const void* T,
  * sides stay in LDS (B/16 x 2 KiB for detection, 3x that for precoding);
  * a B beyond the device's LDS per block returns MIMO_EUNSUPPORTED.
  */
-int mimo_detect_cgls(const mimo_shape* shape, const void* H, const void* Y,
+mimo_status mimo_detect_cgls(const mimo_shape* shape, const void* H, const void* Y,
                      int in_dtype, float n0, float es, int qam_bits, int scalar_prec,
                      float* llr, void* xhat, float* mu, float* sinr, void* stream);
-int mimo_precode_cgls(const mimo_shape* shape, const void* H, const void* T,
+mimo_status mimo_precode_cgls(const mimo_shape* shape, const void* H, const void* T,
                       int in_dtype, float beta, int normalize, int scalar_prec,
                       void* Q, float* qnorm, void* stream);
 /*
@@ -329,8 +329,8 @@ int mimo_precode_cgls(const mimo_shape* shape, const void* H, const void* T,
  * system).  mimo_tune_set is not
  * synchronized with launches already enqueued; it affects later calls.
  */
-int mimo_tune_set(int op, int user_class, int in_dtype, int variant, int blocks_per_cu);
-int mimo_tune_get(int op, int user_class, int in_dtype, int* variant, int* blocks_per_cu);
+mimo_status mimo_tune_set(int op, int user_class, int in_dtype, int variant, int blocks_per_cu);
+mimo_status mimo_tune_get(int op, int user_class, int in_dtype, int* variant, int* blocks_per_cu);
 int mimo_tune_variant_count(int op);
 const char* mimo_tune_variant_name(int op, int variant);   /* NULL if out of range */
 
@@ -338,7 +338,7 @@ const char* mimo_tune_variant_name(int op, int variant);   /* NULL if out of ran
 size_t mimo_workspace_bytes(const mimo_shape* shape, int op, int sinr_mode);
 
 /* Static description of a status code. */
-const char* mimo_status_string(int status);
+const char* mimo_status_string(mimo_status status);
 
 /* Text of the last error recorded by this thread (validation or HIP). */
 const char* mimo_last_error(void);

@@ -15,15 +15,15 @@ namespace {
 
 thread_local char g_last_error[512] = "";
 
-int fail(int status, const char* fmt, ...) {
+mimo_status fail(int status, const char* fmt, ...) {
   va_list ap;
   va_start(ap, fmt);
   vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
   va_end(ap);
-  return status;
+  return static_cast<mimo_status>(status);
 }
 
-int hip_status(hipError_t e, const char* what) {
+mimo_status hip_status(hipError_t e, const char* what) {
   if (e == hipSuccess) return MIMO_OK;
   return fail(MIMO_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
@@ -32,7 +32,7 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 // Calls with U > MIMO_MAX_USERS_COMMON run the four-wavefront kernels, built
 // for complex64 storage.
-int check_wide(int U, int in_dtype) {
+mimo_status check_wide(int U, int in_dtype) {
   if (U > MIMO_MAX_USERS_COMMON && in_dtype != MIMO_C32)
     return fail(MIMO_EUNSUPPORTED, "U=%d > %d needs complex64 storage", U,
                 MIMO_MAX_USERS_COMMON);
@@ -41,7 +41,7 @@ int check_wide(int U, int in_dtype) {
 
 // max_u: the entry point's largest U (MIMO_MAX_USERS for the CG detection
 // and precoding calls, MIMO_MAX_USERS_COMMON for the others).
-int check_shape(const mimo_shape* s, bool need_k, int max_u = MIMO_MAX_USERS_COMMON) {
+mimo_status check_shape(const mimo_shape* s, bool need_k, int max_u = MIMO_MAX_USERS_COMMON) {
   if (!s) return fail(MIMO_EINVAL, "shape is NULL");
   if (s->U < 1) return fail(MIMO_EINVAL, "U=%d < 1", s->U);
   if (s->U > max_u)
@@ -65,7 +65,7 @@ int check_shape(const mimo_shape* s, bool need_k, int max_u = MIMO_MAX_USERS_COM
   return MIMO_OK;
 }
 
-int check_dtype(int in_dtype, int B) {
+mimo_status check_dtype(int in_dtype, int B) {
   if (in_dtype != MIMO_C32 && in_dtype != MIMO_C16 && in_dtype != MIMO_CBF16)
     return fail(MIMO_EINVAL, "in_dtype=%d unknown", in_dtype);
   if (in_dtype != MIMO_C32 && (B % 8) != 0)
@@ -73,7 +73,7 @@ int check_dtype(int in_dtype, int B) {
   return MIMO_OK;
 }
 
-int check_ptr(const void* p, const char* name, bool required) {
+mimo_status check_ptr(const void* p, const char* name, bool required) {
   if (!p) return required ? fail(MIMO_EINVAL, "%s is NULL", name) : MIMO_OK;
   if (!aligned16(p)) return fail(MIMO_EINVAL, "%s is not 16-byte aligned", name);
   return MIMO_OK;
@@ -130,7 +130,7 @@ float qam_scale(float es, int qam_bits) {
 
 #define CHECK(x)              \
   do {                        \
-    const int st_ = (x);      \
+    const mimo_status st_ = (x); \
     if (st_ != MIMO_OK) return st_; \
   } while (0)
 
@@ -194,7 +194,7 @@ const char* mimo_tune_variant_name(int op, int variant) {
   return nullptr;
 }
 
-int mimo_tune_set(int op, int user_class, int in_dtype, int variant, int blocks_per_cu) {
+mimo_status mimo_tune_set(int op, int user_class, int in_dtype, int variant, int blocks_per_cu) {
   g_last_error[0] = 0;
   if (op < 0 || op >= kOps) return fail(MIMO_EINVAL, "op=%d unknown", op);
   if (user_class < 0 || user_class >= kUClasses)
@@ -209,7 +209,7 @@ int mimo_tune_set(int op, int user_class, int in_dtype, int variant, int blocks_
   return MIMO_OK;
 }
 
-int mimo_tune_get(int op, int user_class, int in_dtype, int* variant, int* blocks_per_cu) {
+mimo_status mimo_tune_get(int op, int user_class, int in_dtype, int* variant, int* blocks_per_cu) {
   g_last_error[0] = 0;
   if (op < 0 || op >= kOps || user_class < 0 || user_class >= kUClasses || in_dtype < 0 ||
       in_dtype >= kDtypes || !variant || !blocks_per_cu)
@@ -225,7 +225,7 @@ const char* mimo_version(void) { return "mimo_cg 0.1 gfx950"; }
 
 const char* mimo_last_error(void) { return g_last_error; }
 
-const char* mimo_status_string(int status) {
+const char* mimo_status_string(mimo_status status) {
   switch (status) {
     case MIMO_OK: return "ok";
     case MIMO_EINVAL: return "invalid argument";
@@ -243,7 +243,7 @@ size_t mimo_workspace_bytes(const mimo_shape* shape, int op, int sinr_mode) {
   return 0;   // every kernel keeps its per-subcarrier state in LDS / registers
 }
 
-int mimo_gram_mf(const mimo_shape* shape, const void* H, const void* Y, int in_dtype, float reg,
+mimo_status mimo_gram_mf(const mimo_shape* shape, const void* H, const void* Y, int in_dtype, float reg,
                  void* A, void* b, void* stream) {
   g_last_error[0] = 0;
   CHECK(check_shape(shape, false));
@@ -261,7 +261,7 @@ int mimo_gram_mf(const mimo_shape* shape, const void* H, const void* Y, int in_d
                     "gram_mf launch");
 }
 
-int mimo_detect_cg(const mimo_shape* shape, const void* H, const void* Y, int in_dtype, float n0,
+mimo_status mimo_detect_cg(const mimo_shape* shape, const void* H, const void* Y, int in_dtype, float n0,
                    float es, int qam_bits, int sinr_mode, int scalar_prec, float* llr, void* xhat,
                    float* mu, float* sinr, void* workspace, size_t workspace_bytes,
                    void* stream) {
@@ -304,7 +304,7 @@ int mimo_detect_cg(const mimo_shape* shape, const void* H, const void* Y, int in
   return hip_status(e, "detect_cg launch");
 }
 
-int mimo_precode_cg(const mimo_shape* shape, const void* H, const void* T, int in_dtype,
+mimo_status mimo_precode_cg(const mimo_shape* shape, const void* H, const void* T, int in_dtype,
                     float beta, int normalize, int scalar_prec, void* Q, float* qnorm,
                     void* workspace, size_t workspace_bytes, void* stream) {
   g_last_error[0] = 0;
@@ -334,7 +334,7 @@ int mimo_precode_cg(const mimo_shape* shape, const void* H, const void* T, int i
                     "precode_cg launch");
 }
 
-int mimo_detect_precode_cg(const mimo_shape* ul, const mimo_shape* dl, const void* H,
+mimo_status mimo_detect_precode_cg(const mimo_shape* ul, const mimo_shape* dl, const void* H,
                            const void* Y, const void* T, int in_dtype, float n0, float es,
                            int qam_bits, float beta, int normalize, int scalar_prec,
                            float* llr, void* xhat, float* mu, float* sinr, void* Q,
@@ -395,7 +395,7 @@ int mimo_detect_precode_cg(const mimo_shape* ul, const mimo_shape* dl, const voi
 
 // ---------------------------------------------------------------- Sec. III-F
 // Shared validation of the detection entry points; fills p on success.
-static int detect_args(const mimo_shape* shape, bool need_k, const void* H, const void* Y,
+static mimo_status detect_args(const mimo_shape* shape, bool need_k, const void* H, const void* Y,
                        int in_dtype, float n0, float es, int qam_bits, float* llr, void* xhat,
                        float* mu, float* sinr, mimo::DetectParams& p) {
   CHECK(check_shape(shape, need_k));
@@ -417,7 +417,7 @@ static int detect_args(const mimo_shape* shape, bool need_k, const void* H, cons
   return MIMO_OK;
 }
 
-static int precode_args(const mimo_shape* shape, bool need_k, const void* H, const void* T,
+static mimo_status precode_args(const mimo_shape* shape, bool need_k, const void* H, const void* T,
                         int in_dtype, float beta, int normalize, void* Q, float* qnorm,
                         mimo::PrecodeParams& p) {
   CHECK(check_shape(shape, need_k));
@@ -433,7 +433,7 @@ static int precode_args(const mimo_shape* shape, bool need_k, const void* H, con
   return MIMO_OK;
 }
 
-static int detect_inverse(const mimo_shape* shape, int method, const void* H, const void* Y,
+static mimo_status detect_inverse(const mimo_shape* shape, int method, const void* H, const void* Y,
                           int in_dtype, float n0, float es, int qam_bits, float* llr, void* xhat,
                           float* mu, float* sinr, void* stream) {
   g_last_error[0] = 0;
@@ -447,7 +447,7 @@ static int detect_inverse(const mimo_shape* shape, int method, const void* H, co
                                                  : "detect_neumann launch");
 }
 
-static int precode_inverse(const mimo_shape* shape, int method, const void* H, const void* T,
+static mimo_status precode_inverse(const mimo_shape* shape, int method, const void* H, const void* T,
                            int in_dtype, float beta, int normalize, void* Q, float* qnorm,
                            void* stream) {
   g_last_error[0] = 0;
@@ -460,27 +460,27 @@ static int precode_inverse(const mimo_shape* shape, int method, const void* H, c
                                                  : "precode_neumann launch");
 }
 
-int mimo_detect_cholesky(const mimo_shape* shape, const void* H, const void* Y, int in_dtype,
+mimo_status mimo_detect_cholesky(const mimo_shape* shape, const void* H, const void* Y, int in_dtype,
                          float n0, float es, int qam_bits, float* llr, void* xhat, float* mu,
                          float* sinr, void* stream) {
   return detect_inverse(shape, mimo::kInvCholesky, H, Y, in_dtype, n0, es, qam_bits, llr, xhat,
                         mu, sinr, stream);
 }
 
-int mimo_detect_neumann(const mimo_shape* shape, const void* H, const void* Y, int in_dtype,
+mimo_status mimo_detect_neumann(const mimo_shape* shape, const void* H, const void* Y, int in_dtype,
                         float n0, float es, int qam_bits, float* llr, void* xhat, float* mu,
                         float* sinr, void* stream) {
   return detect_inverse(shape, mimo::kInvNeumann, H, Y, in_dtype, n0, es, qam_bits, llr, xhat,
                         mu, sinr, stream);
 }
 
-int mimo_precode_cholesky(const mimo_shape* shape, const void* H, const void* T, int in_dtype,
+mimo_status mimo_precode_cholesky(const mimo_shape* shape, const void* H, const void* T, int in_dtype,
                           float beta, int normalize, void* Q, float* qnorm, void* stream) {
   return precode_inverse(shape, mimo::kInvCholesky, H, T, in_dtype, beta, normalize, Q, qnorm,
                          stream);
 }
 
-int mimo_precode_neumann(const mimo_shape* shape, const void* H, const void* T, int in_dtype,
+mimo_status mimo_precode_neumann(const mimo_shape* shape, const void* H, const void* T, int in_dtype,
                          float beta, int normalize, void* Q, float* qnorm, void* stream) {
   return precode_inverse(shape, mimo::kInvNeumann, H, T, in_dtype, beta, normalize, Q, qnorm,
                          stream);
@@ -488,7 +488,7 @@ int mimo_precode_neumann(const mimo_shape* shape, const void* H, const void* T, 
 
 // ---------------------------------------------------------------- Sec. III-E
 // CGLS keeps antenna-length vectors of 16 right-hand sides in LDS.
-static int check_cgls_lds(int B, bool precode) {
+static mimo_status check_cgls_lds(int B, bool precode) {
   int dev = 0, limit = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
@@ -501,7 +501,7 @@ static int check_cgls_lds(int B, bool precode) {
   return MIMO_OK;
 }
 
-int mimo_detect_cgls(const mimo_shape* shape, const void* H, const void* Y, int in_dtype,
+mimo_status mimo_detect_cgls(const mimo_shape* shape, const void* H, const void* Y, int in_dtype,
                      float n0, float es, int qam_bits, int scalar_prec, float* llr, void* xhat,
                      float* mu, float* sinr, void* stream) {
   g_last_error[0] = 0;
@@ -516,7 +516,7 @@ int mimo_detect_cgls(const mimo_shape* shape, const void* H, const void* Y, int 
                     "detect_cgls launch");
 }
 
-int mimo_precode_cgls(const mimo_shape* shape, const void* H, const void* T, int in_dtype,
+mimo_status mimo_precode_cgls(const mimo_shape* shape, const void* H, const void* T, int in_dtype,
                       float beta, int normalize, int scalar_prec, void* Q, float* qnorm,
                       void* stream) {
   g_last_error[0] = 0;
@@ -532,15 +532,15 @@ int mimo_precode_cgls(const mimo_shape* shape, const void* H, const void* T, int
 }
 
 // Prefix the message of a failed check with the frame index.
-static int frame_fail(int status, int i) {
+static mimo_status frame_fail(int status, int i) {
   char msg[sizeof(g_last_error)];
   std::memcpy(msg, g_last_error, sizeof(msg));
   return fail(status, "frame %d: %s", i, msg);
 }
 
-static int check_frame(const mimo_frame& f, int i, int in_dtype, bool detect) {
+static mimo_status check_frame(const mimo_frame& f, int i, int in_dtype, bool detect) {
   mimo_shape sh{f.B, f.U, f.S, f.K, f.n_sc};
-  int st = check_shape(&sh, true);
+  mimo_status st = check_shape(&sh, true);
   if (st == MIMO_OK) st = check_dtype(in_dtype, f.B);
   if (st == MIMO_OK) st = check_ptr(f.H, "H", true);
   if (st == MIMO_OK) st = check_ptr(f.Y, detect ? "Y" : "T", true);
@@ -556,7 +556,7 @@ static int check_frame(const mimo_frame& f, int i, int in_dtype, bool detect) {
   return MIMO_OK;
 }
 
-static int build_batch(const mimo_frame* frames, int n_frames, int in_dtype, bool detect,
+static mimo_status build_batch(const mimo_frame* frames, int n_frames, int in_dtype, bool detect,
                        int qam_bits, mimo::BatchArgs& a, int& max_u) {
   if (!frames && n_frames > 0) return fail(MIMO_EINVAL, "frames is NULL");
   if (n_frames < 0 || n_frames > MIMO_MAX_BATCH)
@@ -594,7 +594,7 @@ static int build_batch(const mimo_frame* frames, int n_frames, int in_dtype, boo
   return MIMO_OK;
 }
 
-int mimo_detect_cg_batch(const mimo_frame* frames, int n_frames, int in_dtype, int qam_bits,
+mimo_status mimo_detect_cg_batch(const mimo_frame* frames, int n_frames, int in_dtype, int qam_bits,
                          int scalar_prec, void* stream) {
   g_last_error[0] = 0;
   if (qam_bits != 2 && qam_bits != 4 && qam_bits != 6 && qam_bits != 8)
@@ -612,7 +612,7 @@ int mimo_detect_cg_batch(const mimo_frame* frames, int n_frames, int in_dtype, i
                     "detect_cg_batch launch");
 }
 
-int mimo_precode_cg_batch(const mimo_frame* frames, int n_frames, int in_dtype,
+mimo_status mimo_precode_cg_batch(const mimo_frame* frames, int n_frames, int in_dtype,
                           int scalar_prec, void* stream) {
   g_last_error[0] = 0;
   if (scalar_prec != MIMO_SCALAR_F32 && scalar_prec != MIMO_SCALAR_F64)
@@ -628,7 +628,7 @@ int mimo_precode_cg_batch(const mimo_frame* frames, int n_frames, int in_dtype,
                     "precode_cg_batch launch");
 }
 
-int mimo_convert(const void* src, void* dst, int dst_dtype, int64_t n, int32_t R, int32_t C,
+mimo_status mimo_convert(const void* src, void* dst, int dst_dtype, int64_t n, int32_t R, int32_t C,
                  void* stream) {
   g_last_error[0] = 0;
   if (dst_dtype != MIMO_C16 && dst_dtype != MIMO_CBF16)

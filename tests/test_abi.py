@@ -42,6 +42,28 @@ def test_library_exports_every_declared_symbol():
     assert set(_declared()) <= exported
 
 
+def test_headers_compile_as_c_and_link(tmp_path):
+    """include/*.h are plain C: a C11 translation unit that includes them and
+    calls every compute entry point (returning mimo_status) compiles without
+    warnings and links against the library."""
+    src = tmp_path / "use.c"
+    src.write_text(
+        '#include "mimo_cg.h"\n#include "mimo_serve.h"\n'
+        "int main(void) {\n"
+        "  mimo_shape s = {32, 8, 1, 3, 0};\n"
+        "  mimo_status st = mimo_detect_cg(&s, 0, 0, MIMO_C32, 1.f, 1.f, 4, MIMO_SINR_APPROX,\n"
+        "                                  MIMO_SCALAR_F32, 0, 0, 0, 0, 0, 0, 0);\n"
+        "  st = mimo_precode_cg(&s, 0, 0, MIMO_C32, 0.f, 0, MIMO_SCALAR_F32, 0, 0, 0, 0, 0);\n"
+        "  st = mimo_gram_mf(&s, 0, 0, MIMO_C32, 0.f, 0, 0, 0);\n"
+        "  return mimo_status_string(st) == 0;\n"
+        "}\n")
+    exe = tmp_path / "use"
+    r = subprocess.run(["gcc", "-std=c11", "-Wall", "-Wextra", "-Werror", "-I",
+                        os.path.join(ROOT, "include"), str(src), L.LIB_PATH, "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
 def test_header_constants_match_binding():
     src = open(HEADER).read()
     assert re.search(rf"#define MIMO_MAX_USERS {L.MIMO_MAX_USERS}\b", src)
