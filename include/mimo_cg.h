@@ -47,8 +47,8 @@ extern "C" {
 #endif
 
 #define MIMO_MAX_USERS 64          /* largest U: mimo_detect_cg (approximate SINR),
-                                      mimo_precode_cg, mimo_detect_precode_cg with
-                                      complex64 storage */
+                                      mimo_precode_cg, mimo_detect_precode_cg and
+                                      mimo_gram_mf with complex64 storage */
 #define MIMO_MAX_USERS_COMMON 32   /* largest U of every other call, of 16-bit
                                       storage and of the exact SINR; a larger U
                                       there returns MIMO_EUNSUPPORTED */
@@ -97,7 +97,8 @@ typedef enum mimo_status {
  *   A      out, complex64 [n_sc][U][U]; the upper triangle is computed, the
  *          lower triangle is its conjugate mirror, the diagonal is real
  *   b      out, complex64 [n_sc][U][S], or NULL
- * Uses shape->B, U, S, n_sc (K is ignored).
+ * Uses shape->B, U, S, n_sc (K is ignored).  U beyond MIMO_MAX_USERS_COMMON
+ * (up to MIMO_MAX_USERS) with complex64 storage only.
  */
 mimo_status mimo_gram_mf(const mimo_shape* shape, const void* H, const void* Y,
                  int in_dtype, float reg, void* A, void* b, void* stream);

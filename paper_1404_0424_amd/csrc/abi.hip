@@ -246,8 +246,9 @@ size_t mimo_workspace_bytes(const mimo_shape* shape, int op, int sinr_mode) {
 mimo_status mimo_gram_mf(const mimo_shape* shape, const void* H, const void* Y, int in_dtype, float reg,
                  void* A, void* b, void* stream) {
   g_last_error[0] = 0;
-  CHECK(check_shape(shape, false));
+  CHECK(check_shape(shape, false, MIMO_MAX_USERS));
   CHECK(check_dtype(in_dtype, shape->B));
+  CHECK(check_wide(shape->U, in_dtype));
   if (!(reg >= 0.f) || !std::isfinite(reg)) return fail(MIMO_EINVAL, "reg=%g must be >= 0", reg);
   CHECK(check_ptr(H, "H", true));
   CHECK(check_ptr(Y, "Y", false));
@@ -256,6 +257,8 @@ mimo_status mimo_gram_mf(const mimo_shape* shape, const void* H, const void* Y, 
   if (b && !Y) return fail(MIMO_EINVAL, "b requested without Y");
   if (shape->n_sc == 0) return MIMO_OK;
   mimo::GramParams p{H, Y, shape->B, shape->U, shape->S, shape->n_sc, reg, (float2*)A, (float2*)b};
+  if (shape->U > MIMO_MAX_USERS_COMMON)
+    return hip_status(mimo::launch_gram_mf_wide(p, (hipStream_t)stream), "gram_mf launch");
   return hip_status(mimo::launch_gram_mf(p, in_dtype, get_sched(MIMO_OP_GRAM_MF, shape->U, in_dtype),
                                          (hipStream_t)stream),
                     "gram_mf launch");

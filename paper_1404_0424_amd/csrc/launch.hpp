@@ -37,6 +37,7 @@ hipError_t launch_slot(const SlotParams& p, int scalar_f64, int m_bits, const Sc
 hipError_t launch_detect_wide(const DetectParams& p, int scalar_f64, int m_bits,
                               hipStream_t stream);
 hipError_t launch_precode_wide(const PrecodeParams& p, int scalar_f64, hipStream_t stream);
+hipError_t launch_gram_mf_wide(const GramParams& p, hipStream_t stream);
 hipError_t launch_detect_plain(const DetectParams& p, int scalar_f64, int m_bits,
                                const Schedule& sch, hipStream_t stream);
 hipError_t launch_detect_batch(const BatchArgs& a, int max_u, int in_dtype, int scalar_f64,

@@ -575,6 +575,50 @@ __global__ __launch_bounds__(256, 2) void precode_wide_kernel(PrecodeParams kprm
   }
 }
 
+// Standalone A = G + reg I and b = H^H y (Algorithm 1, initialization) for
+// 32 < U <= 64: the Gram and matched-filter phase of the kernels above, with
+// A assembled in LDS and each role writing its rows of it.
+template <bool HAS_Y>
+__global__ __launch_bounds__(256, 2) void gram_mf_wide_kernel(GramParams kprm) {
+  __shared__ __align__(16) WideLds<float> lds;
+  for (int64_t n = blockIdx.x; n < kprm.n_sc; n += gridDim.x) {
+    const GramParams prm = opaque_sizes(kprm);
+    const int B = prm.B, U = prm.U, S = prm.S;
+    const WideLane L = wide_lane(n);
+    const void* Hn = offset_sc(InC32{}, prm.H, n, B, U);
+    const void* Yn = HAS_Y ? offset_sc(InC32{}, prm.Y, n, B, S) : nullptr;
+    const int nchunk = HAS_Y ? (S + 15) / 16 : 1;
+    for (int ch = 0; ch < nchunk; ++ch) {
+      const int s0 = 16 * ch;
+      WideAcc acc;
+      if (ch == 0) {
+        wide_gram_mf<kWideUnrDetect, kWideGramCPol, true, HAS_Y>(Hn, Yn, B, U, S, s0, L, acc);
+        float2 a[16];
+        float d;
+        wide_store_a<float>(acc, lds, prm.reg, L, a, d);   // the operand reads go unused
+        float2* An = prm.A + (size_t)n * U * U;
+        for (int idx = L.lane; idx < 16 * U; idx += kWave) {
+          const int row = 16 * L.r + idx / U, col = idx % U;
+          if (row < U) An[(size_t)row * U + col] = lds.A[row * kWideAst + col];
+        }
+      } else {
+        wide_gram_mf<kWideUnrDetect, kWideGramCPol, false, HAS_Y>(Hn, Yn, B, U, S, s0, L, acc);
+      }
+      if (HAS_Y && prm.b) {
+        const int u = 16 * L.r + L.c;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int s = s0 + 4 * L.g + j;
+          const float p1 = acc.p1[j], p2 = acc.p2[j];
+          if (u < U && s < S)
+            prm.b[((size_t)n * U + u) * S + s] = make_float2(p1 + p2, acc.p3[j] - p1 + p2);
+        }
+      }
+    }
+    __syncthreads();                                 // A's LDS read by all
+  }
+}
+
 // One workgroup per subcarrier, up to 2^20 workgroups walking the rest.
 static unsigned int wide_grid(int64_t n_sc) {
   return (unsigned int)(n_sc < (1 << 20) ? (n_sc > 0 ? n_sc : 1) : (1 << 20));
@@ -605,6 +649,15 @@ hipError_t launch_precode_wide(const PrecodeParams& p, int scalar_f64, hipStream
     hipLaunchKernelGGL((precode_wide_kernel<double>), grid, block, 0, stream, p);
   else
     hipLaunchKernelGGL((precode_wide_kernel<float>), grid, block, 0, stream, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_mf_wide(const GramParams& p, hipStream_t stream) {
+  const dim3 grid(wide_grid(p.n_sc)), block(kWave * kWideTiles);
+  if (p.Y)
+    hipLaunchKernelGGL((gram_mf_wide_kernel<true>), grid, block, 0, stream, p);
+  else
+    hipLaunchKernelGGL((gram_mf_wide_kernel<false>), grid, block, 0, stream, p);
   return hipGetLastError();
 }
 

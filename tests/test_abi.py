@@ -157,8 +157,8 @@ def test_rhs_count_bounded_by_32bit_offsets(B, U):
 
 def test_users_beyond_32_validation():
     """33 <= U <= MIMO_MAX_USERS passes validation on the CG detection
-    (approximate SINR), precoding and slot calls with complex64 storage (n_sc
-    = 0 here, so nothing runs) and is rejected with MIMO_EUNSUPPORTED by
+    (approximate SINR), precoding, slot and Gram calls with complex64 storage
+    (n_sc = 0 here, so nothing runs) and is rejected with MIMO_EUNSUPPORTED by
     every call that is not built for it."""
     lib = L.lib()
     for U in (33, 48, L.MIMO_MAX_USERS):
@@ -170,7 +170,8 @@ def test_users_beyond_32_validation():
         s = L.shape(128, U, 14, 4, 4)
         assert lib.mimo_precode_cg(s, P, P, 1, 0.1, 1, 0, P2, None, None, 0,
                                    None) == L.MIMO_EUNSUPPORTED
-        assert lib.mimo_gram_mf(s, P, P, 0, 0.5, P2, P2, None) == L.MIMO_EUNSUPPORTED
+        assert lib.mimo_gram_mf(empty, P, P, 0, 0.5, P2, P2, None) == L.MIMO_OK
+        assert lib.mimo_gram_mf(s, P, P, 2, 0.5, P2, P2, None) == L.MIMO_EUNSUPPORTED
         assert lib.mimo_detect_cholesky(s, P, P, 0, 0.5, 1.0, 4, P2, None, None, None,
                                         None) == L.MIMO_EUNSUPPORTED
         assert lib.mimo_detect_neumann(s, P, P, 0, 0.5, 1.0, 4, P2, None, None, None,

@@ -1,4 +1,5 @@
-"""GPU parity of CG-D detection and CG-P precoding for 32 < U <= 64 (the
+"""GPU parity of CG-D detection, CG-P precoding and the standalone Gram and
+matched filter for 32 < U <= 64 (the
 four-wavefront kernels: one workgroup per subcarrier, one 16-user tile per
 wavefront, the CG inner products summed over the wavefronts through LDS).
 
@@ -103,6 +104,26 @@ def test_wide_precoding_matches_oracle(case):
     en = rel_err_scalar(host(qn), ref["qnorm"])
     print(f"{name}: eps_q={eq:.2e} eps_norm={en:.2e}")
     assert eq <= TOL_X and en <= TOL_X, (eq, en)
+
+
+@pytest.mark.parametrize("B,U,S,n", [(128, 33, 14, 23), (100, 48, 17, 9), (256, 64, 40, 5),
+                                     (64, 64, 1, 7)])
+def test_wide_gram_mf_matches_oracle(B, U, S, n):
+    """mimo_gram_mf for 32 < U <= 64: A = H^H H + reg I (exactly Hermitian,
+    real diagonal) and b = H^H y against the oracle, with and without Y."""
+    print(f"wide gram_mf {B}x{U} S={S}", flush=True)
+    f = W.uplink_frame(_rng(f"gram{B}x{U}"), n, B, U, S, 4, 10.0)
+    A, b = api().gram_mf(dev(f.H), dev(f.Y), reg=0.37)
+    torch.cuda.synchronize()
+    A0 = O.regularized_gram(f.H, 0.37)
+    Ag = host(A)
+    eA = np.max(np.linalg.norm(Ag - A0, axis=(1, 2)) / np.linalg.norm(A0, axis=(1, 2)))
+    eb = rel_err_vec(host(b), O.matched_filter(f.H, f.Y), axis=1)
+    assert eA <= 2e-6 and eb <= 2e-6, (eA, eb)
+    assert np.array_equal(Ag, np.conj(np.swapaxes(Ag, 1, 2)))
+    A2, b2 = api().gram_mf(dev(f.H), None, reg=0.0)
+    assert b2 is None
+    assert np.max(np.abs(host(A2) - O.gram(f.H))) <= 2e-6 * np.max(np.abs(A0))
 
 
 def test_wide_zero_receive_vectors():
