@@ -1,6 +1,6 @@
-// CG-D detection and CG-P precoding for 32 < U <= 64 (the paper's U <= B
-// allows any U; Sec. II-A), complex64 storage: one workgroup of four
-// wavefronts per subcarrier.  Wavefront w takes role r = (w + n) mod 4 on
+// CG-D detection, CG-P precoding and the standalone Gram and matched filter
+// for 32 < U <= 64 (the paper's U <= B allows any U; Sec. II-A), complex64
+// storage: one workgroup of four wavefronts per subcarrier.  Wavefront w takes role r = (w + n) mod 4 on
 // subcarrier n and owns users 16 r .. 16 r + 15; the rotation spreads the
 // roles' unequal Gram work evenly over the four SIMDs.
 //
