@@ -186,6 +186,31 @@ mimo_status mimo_detect_precode_cg(const mimo_shape* ul, const mimo_shape* dl, c
                            float* qnorm, void* stream);
 
 /*
+ * mimo_detect_cg_gram, mimo_precode_cg_gram -- the same operations with the
+ * Gram matrix of the channel supplied instead of formed: G = H^H H (Sec.
+ * II-A; = H_d H_d^H by reciprocity, Sec. II-B) of this H, without
+ * regularization, e.g. written once per channel by mimo_gram_mf with reg = 0
+ * and kept while the channel holds (the serving runtime caches it per
+ * channel).  The call adds reg = n0/es (detection) or beta (precoding) to the
+ * diagonal and reads H only for the matched filter b = H^H y or the output
+ * q = H_u v, skipping the Gram's products.
+ *   G  complex64 [n_sc][U][U], Hermitian with a real diagonal and an exactly
+ *      conjugate lower triangle (mimo_gram_mf's layout)
+ * Other arguments, outputs and rules as mimo_detect_cg (approximate SINR)
+ * and mimo_precode_cg; U <= MIMO_MAX_USERS_COMMON.  With a G from
+ * mimo_gram_mf of the same H (and storage type) and U > 8, outputs are
+ * bitwise those of mimo_detect_cg / mimo_precode_cg; at U <= 8 those calls
+ * form the Gram in a packed form that rounds differently.
+ */
+mimo_status mimo_detect_cg_gram(const mimo_shape* shape, const void* G, const void* H,
+                                const void* Y, int in_dtype, float n0, float es, int qam_bits,
+                                int scalar_prec, float* llr, void* xhat, float* mu, float* sinr,
+                                void* stream);
+mimo_status mimo_precode_cg_gram(const mimo_shape* shape, const void* G, const void* H,
+                                 const void* T, int in_dtype, float beta, int normalize,
+                                 int scalar_prec, void* Q, float* qnorm, void* stream);
+
+/*
  * mimo_convert -- channel / receive-vector ingest into reduced precision.
  * Rounds a complex64 array [n][R][C] (R rows = antennas, a multiple of 8)
  * to FP16 or BF16 with round-to-nearest-even and writes the blocked layout
@@ -209,6 +234,7 @@ mimo_status mimo_convert(const void* src, void* dst, int dst_dtype, int64_t n,
  *   precoding:  H [n_sc][B][U] (storage in_dtype), Y = T complex64
  *               [n_sc][U][S], out = Q complex64 [n_sc][B][S],
  *               out2 = qnorm float [n_sc][S] or NULL; uses beta, normalize
+ * A frame with gram != NULL runs as mimo_detect_cg_gram / mimo_precode_cg_gram.
  * Results are bitwise identical to the corresponding single-frame calls.
  */
 #define MIMO_MAX_BATCH 32
@@ -223,6 +249,7 @@ typedef struct mimo_frame {
   float n0, es;          /* detection */
   float beta;            /* precoding */
   int32_t normalize;     /* precoding */
+  const void* gram;      /* cached G of the frame's H (as mimo_detect_cg_gram), or NULL */
 } mimo_frame;
 
 mimo_status mimo_detect_cg_batch(const mimo_frame* frames, int n_frames, int in_dtype, int qam_bits,

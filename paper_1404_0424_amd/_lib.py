@@ -35,7 +35,7 @@ class MimoFrame(ctypes.Structure):
                 ("S", ctypes.c_int32), ("K", ctypes.c_int32), ("H", ctypes.c_void_p),
                 ("Y", ctypes.c_void_p), ("out", ctypes.c_void_p), ("out2", ctypes.c_void_p),
                 ("n0", ctypes.c_float), ("es", ctypes.c_float), ("beta", ctypes.c_float),
-                ("normalize", ctypes.c_int32)]
+                ("normalize", ctypes.c_int32), ("gram", ctypes.c_void_p)]
 
 
 class MimoServerConfig(ctypes.Structure):
@@ -98,6 +98,9 @@ _SIGNATURES = {
     "mimo_precode_cg": (_i, [_shape_p, _vp, _vp, _i, _f, _i, _i, _vp, _vp, _vp, _sz, _vp]),
     "mimo_detect_precode_cg": (_i, [_shape_p, _shape_p, _vp, _vp, _vp, _i, _f, _f, _i, _f, _i,
                                     _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "mimo_detect_cg_gram": (_i, [_shape_p, _vp, _vp, _vp, _i, _f, _f, _i, _i, _vp, _vp, _vp,
+                                 _vp, _vp]),
+    "mimo_precode_cg_gram": (_i, [_shape_p, _vp, _vp, _vp, _i, _f, _i, _i, _vp, _vp, _vp]),
     "mimo_convert": (_i, [_vp, _vp, _i, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _vp]),
     "mimo_workspace_bytes": (_sz, [_shape_p, _i, _i]),
     "mimo_status_string": (ctypes.c_char_p, [_i]),

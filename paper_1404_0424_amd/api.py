@@ -166,6 +166,43 @@ def precode_cg(H, T: torch.Tensor, beta: float, K: int, normalize: bool = False,
     return Q, qn
 
 
+def _gram_arg(G, n, U):
+    _check_c64(G, "G")
+    if tuple(G.shape) != (n, U, U) or not G.is_contiguous():
+        raise ValueError("G must be contiguous complex64 (n_sc, U, U)")
+    return G.data_ptr()
+
+
+def detect_cg_gram(G, H, Y, n0: float, es: float, K: int, qam_bits: int,
+                   scalar_prec: str = "f32", xhat: bool = False, mu: bool = False,
+                   sinr: bool = False, out=None, stream=None) -> dict:
+    """detect_cg (approximate SINR) with the channel's Gram matrix G = H^H H
+    supplied (e.g. gram_mf(H, None, 0.0), kept while the channel holds): the
+    call reads H only for the matched filter."""
+    hp, code, n, B, U = _channel(H)
+    yp, S = _rhs(Y, code, n, B)
+    gp = _gram_arg(G, n, U)
+    res, llr, xh, mu_t, sn = _detect_outputs(H.device, n, U, S, qam_bits, xhat, mu, sinr, out)
+    prec = {"f32": L.MIMO_SCALAR_F32, "f64": L.MIMO_SCALAR_F64}[scalar_prec]
+    L.check(L.lib().mimo_detect_cg_gram(L.shape(B, U, S, K, n), gp, hp, yp, code, float(n0),
+                                        float(es), int(qam_bits), prec, llr.data_ptr(), _ptr(xh),
+                                        _ptr(mu_t), _ptr(sn), _stream(stream)))
+    return res
+
+
+def precode_cg_gram(G, H, T: torch.Tensor, beta: float, K: int, normalize: bool = False,
+                    scalar_prec: str = "f32", qnorm: bool = True, out=None, stream=None):
+    """precode_cg with the channel's Gram matrix G supplied; H is read only
+    for q = H v.  Returns (Q, qnorm)."""
+    hp, code, n, B, U, S, Q, qn = _precode_outputs(H, T, out, qnorm)
+    gp = _gram_arg(G, n, U)
+    prec = {"f32": L.MIMO_SCALAR_F32, "f64": L.MIMO_SCALAR_F64}[scalar_prec]
+    L.check(L.lib().mimo_precode_cg_gram(L.shape(B, U, S, K, n), gp, hp, T.data_ptr(), code,
+                                         float(beta), int(bool(normalize)), prec, Q.data_ptr(),
+                                         _ptr(qn), _stream(stream)))
+    return Q, qn
+
+
 def detect_precode_cg(H, Y, T: torch.Tensor, n0: float, es: float, beta: float, K_ul: int,
                       K_dl: int, qam_bits: int, normalize: bool = False,
                       scalar_prec: str = "f32", xhat: bool = False, mu: bool = False,

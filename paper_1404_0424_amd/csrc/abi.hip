@@ -534,6 +534,43 @@ mimo_status mimo_precode_cgls(const mimo_shape* shape, const void* H, const void
                     "precode_cgls launch");
 }
 
+// ---------------------------------------------------------------- cached Gram
+mimo_status mimo_detect_cg_gram(const mimo_shape* shape, const void* G, const void* H,
+                                const void* Y, int in_dtype, float n0, float es, int qam_bits,
+                                int scalar_prec, float* llr, void* xhat, float* mu, float* sinr,
+                                void* stream) {
+  g_last_error[0] = 0;
+  mimo::DetectParams p;
+  CHECK(detect_args(shape, true, H, Y, in_dtype, n0, es, qam_bits, llr, xhat, mu, sinr, p));
+  if (scalar_prec != MIMO_SCALAR_F32 && scalar_prec != MIMO_SCALAR_F64)
+    return fail(MIMO_EINVAL, "scalar_prec=%d unknown", scalar_prec);
+  CHECK(check_ptr(G, "G", true));
+  if (shape->n_sc == 0) return MIMO_OK;
+  p.gram = (const float2*)G;
+  return hip_status(mimo::launch_detect_approx(p, in_dtype, scalar_prec == MIMO_SCALAR_F64,
+                                               qam_bits, get_sched(MIMO_OP_DETECT, shape->U,
+                                                                   in_dtype),
+                                               (hipStream_t)stream),
+                    "detect_cg_gram launch");
+}
+
+mimo_status mimo_precode_cg_gram(const mimo_shape* shape, const void* G, const void* H,
+                                 const void* T, int in_dtype, float beta, int normalize,
+                                 int scalar_prec, void* Q, float* qnorm, void* stream) {
+  g_last_error[0] = 0;
+  mimo::PrecodeParams p;
+  CHECK(precode_args(shape, true, H, T, in_dtype, beta, normalize, Q, qnorm, p));
+  if (scalar_prec != MIMO_SCALAR_F32 && scalar_prec != MIMO_SCALAR_F64)
+    return fail(MIMO_EINVAL, "scalar_prec=%d unknown", scalar_prec);
+  CHECK(check_ptr(G, "G", true));
+  if (shape->n_sc == 0) return MIMO_OK;
+  p.gram = (const float2*)G;
+  return hip_status(mimo::launch_precode(p, in_dtype, scalar_prec == MIMO_SCALAR_F64,
+                                         get_sched(MIMO_OP_PRECODE, shape->U, in_dtype),
+                                         (hipStream_t)stream),
+                    "precode_cg_gram launch");
+}
+
 // Prefix the message of a failed check with the frame index.
 static mimo_status frame_fail(int status, int i) {
   char msg[sizeof(g_last_error)];
@@ -549,6 +586,7 @@ static mimo_status check_frame(const mimo_frame& f, int i, int in_dtype, bool de
   if (st == MIMO_OK) st = check_ptr(f.Y, detect ? "Y" : "T", true);
   if (st == MIMO_OK) st = check_ptr(f.out, detect ? "llr" : "Q", true);
   if (st == MIMO_OK) st = check_ptr(f.out2, "out2", false);
+  if (st == MIMO_OK) st = check_ptr(f.gram, "gram", false);
   if (st != MIMO_OK) return frame_fail(st, i);
   if (detect) {
     if (!(f.n0 > 0.f) || !std::isfinite(f.n0) || !(f.es > 0.f) || !std::isfinite(f.es))
@@ -575,6 +613,7 @@ static mimo_status build_batch(const mimo_frame* frames, int n_frames, int in_dt
     d.Y = f.Y;
     d.out = f.out;
     d.out2 = f.out2;
+    d.gram = f.gram;
     d.sc_begin = a.total;
     d.n_sc = f.n_sc;
     d.B = f.B;

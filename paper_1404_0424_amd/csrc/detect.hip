@@ -107,7 +107,11 @@ __device__ __forceinline__ void detect_one(const DetectParams& prm, int64_t n, f
   for (int s0 = 0; s0 < S; s0 += 16) {
     GramAcc<W> acc;
     acc.clear();
-    if (s0 == 0) {
+    if (s0 == 0 && prm.gram) {        // cached G: only the matched filter reads H
+      gram_mf<W, false, true>(IN{}, Hn, Yn, B, U, S, s0, c, g, acc);
+      cached_gram_to_operands<W>(prm.gram + (size_t)n * U * U, U, prm.reg, As, Gs, AST, c, g,
+                                 at, d);
+    } else if (s0 == 0) {
       gram_mf<W, true, true>(IN{}, Hn, Yn, B, U, S, s0, c, g, acc);
       gram_to_operands<W>(IN{}, acc, As, Gs, Ps, AST, prm.reg, U, c, g, at, d);
     } else {
@@ -164,7 +168,8 @@ __global__ __launch_bounds__(256, 2) void detect_batch_kernel(BatchArgs args) {
     const int f = find_frame(args, gsc);
     const FrameArgs& F = args.f[f];
     DetectParams prm{F.H, F.Y, F.B, F.U, F.S, F.K, F.n_sc, F.reg, F.n0, F.es, F.scale,
-                     F.inv_scale, (float*)F.out, (float2*)F.out2, nullptr, nullptr};
+                     F.inv_scale, (float*)F.out, (float2*)F.out2, nullptr, nullptr,
+                     (const float2*)F.gram};
     if constexpr (std::is_same<IN, InC32>::value) {
       if (F.U <= 8) {               // packed form, as a single call of this frame runs
         detect_one<1, InC32P, ST, M_BITS>(prm, gsc - F.sc_begin, As, Ps, G_s[wv], c, g,
@@ -271,6 +276,9 @@ hipError_t launch_detect_batch(const BatchArgs& a, int max_u, int in_dtype, int 
 
 hipError_t launch_detect_approx(const DetectParams& p, int in_dtype, int scalar_f64, int m_bits,
                                 const Schedule& sch, hipStream_t stream) {
+  if (p.gram && sch.variant != kDetectGeneric)   // a cached Gram runs the generic kernel
+    return launch_detect_approx(p, in_dtype, scalar_f64, m_bits,
+                                Schedule{kDetectGeneric, sch.blocks_per_cu}, stream);
   if (sch.variant == kDetectPlain && in_dtype == 0)
     return launch_detect_plain(p, scalar_f64, m_bits, sch, stream);
   if (sch.variant == kDetectSplit) {

@@ -189,6 +189,19 @@ __device__ __forceinline__ void cg_llr_epilogue(const DetectParams& prm, int64_t
   llr_stage<W, ST, M_BITS, BUF, STAGE, FIXED_STORES>(prm, n, s0, st.v, tk.tv, Gs, c, g, stg);
 }
 
+// A cached Gram matrix (load_cached_gram) -> LDS A, A^T operand and
+// diagonal d = A_ii, as gram_to_operands gives for a Gram formed here.
+template <int W>
+__device__ __forceinline__ void cached_gram_to_operands(const float2* Gn, int U, float reg,
+                                                        float2* As, float* Gs, int ast, int c,
+                                                        int g, AOperand<W>& at, float (&d)[W]) {
+  load_cached_gram<W>(Gn, U, reg, As, Gs, ast, 16 * g + c);
+  wave_lds_sync();
+  at.load(As, ast, c, g, U);
+#pragma unroll
+  for (int w = 0; w < W; ++w) d[w] = As[(16 * w + c) * ast + 16 * w + c].x;
+}
+
 // Gram tiles -> LDS A, A^T operand and diagonal d = A_ii.
 template <int W, typename IN>
 __device__ __forceinline__ void gram_to_operands(IN tag, const GramAcc<W>& acc, float2* As,

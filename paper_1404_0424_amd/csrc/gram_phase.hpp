@@ -582,6 +582,28 @@ __device__ __forceinline__ void store_gram_lds(const GramAcc<W>& acc, float2* As
     }
 }
 
+// A = G + reg I from a cached Gram matrix Gn (complex64 [U][U], Hermitian
+// with a real diagonal and an exactly conjugate lower triangle, as
+// mimo_gram_mf writes it with reg = 0) into the wave's LDS copy, entry for
+// entry the values store_gram_lds writes for a Gram formed from the same H:
+// padding users (>= U) get zero rows and columns (an imaginary -0 below the
+// diagonal, where the mirror negates a zero) and reg on the diagonal; Gd
+// receives G_ii.
+template <int W>
+__device__ __forceinline__ void load_cached_gram(const float2* __restrict__ Gn, int U, float reg,
+                                                 float2* As, float* Gd, int ast, int lane) {
+  constexpr int NU = 16 * W;
+  for (int idx = lane; idx < NU * NU; idx += kWave) {
+    const int r = idx / NU, col = idx % NU;
+    float2 v = (r < U && col < U) ? Gn[r * U + col] : make_float2(0.f, r > col ? -0.f : 0.f);
+    if (r == col) {
+      Gd[r] = v.x;
+      v = make_float2(v.x + reg, 0.f);
+    }
+    As[r * ast + col] = v;
+  }
+}
+
 // The split form accumulates -Im G on every tile (no M - M^T step); the
 // upper triangle and a real diagonal are written as for the others.
 template <int W>

@@ -22,6 +22,7 @@ struct DetectParams {
   float2* xhat;         // [n_sc][U][S] or null
   float* mu;            // [n_sc][U][S] or null
   float* sinr;          // [n_sc][U][S] or null
+  const float2* gram;   // [n_sc][U][U] cached G = H^H H of this H, or null (formed from H)
 };
 
 struct PrecodeParams {
@@ -33,6 +34,7 @@ struct PrecodeParams {
   int normalize;
   float2* Q;            // [n_sc][B][S]
   float* qnorm;         // [n_sc][S] or null
+  const float2* gram;   // [n_sc][U][U] cached G = H_d H_d^H of this H, or null
 };
 
 // One uplink + downlink slot on a reciprocal channel: detection and
@@ -95,6 +97,7 @@ struct FrameArgs {
   const void* Y;        // detect: Y [n_sc][B][S]; precode: T complex64 [n_sc][U][S]
   void* out;            // detect: llr; precode: Q
   void* out2;           // detect: xhat or null; precode: qnorm or null
+  const void* gram;     // cached G, complex64 [n_sc][U][U], or null
   int64_t sc_begin;     // first global subcarrier of the frame
   int64_t n_sc;
   int B, U, S, K;

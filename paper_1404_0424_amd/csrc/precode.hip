@@ -29,10 +29,14 @@ __device__ __forceinline__ void precode_one(const PrecodeParams& prm, int64_t n,
   for (int s0 = 0; s0 < S; s0 += 16) {
     // ---- A = H_d H_d^H + beta I = G + beta I (Algorithm 1, initialization)
     if (s0 == 0) {
-      GramAcc<W> acc;
-      acc.clear();
-      gram_mf<W, true, false>(IN{}, Hn, nullptr, B, U, S, 0, c, g, acc);
-      store_gram(IN{}, acc, As, Gs, (float*)Ps, AST, beta, c, g);
+      if (prm.gram) {                 // cached G: H is read only for q = H v
+        load_cached_gram<W>(prm.gram + (size_t)n * U * U, U, beta, As, Gs, AST, 16 * g + c);
+      } else {
+        GramAcc<W> acc;
+        acc.clear();
+        gram_mf<W, true, false>(IN{}, Hn, nullptr, B, U, S, 0, c, g, acc);
+        store_gram(IN{}, acc, As, Gs, (float*)Ps, AST, beta, c, g);
+      }
       wave_lds_sync();
       at.load(As, AST, c, g, U);
     }
@@ -264,7 +268,7 @@ __global__ __launch_bounds__(256, 2) void precode_batch_kernel(BatchArgs args) {
     const int f = find_frame(args, gsc);
     const FrameArgs& F = args.f[f];
     PrecodeParams prm{F.H, (const float2*)F.Y, F.B, F.U, F.S, F.K, F.n_sc, F.beta,
-                      F.normalize, (float2*)F.out, (float*)F.out2};
+                      F.normalize, (float2*)F.out, (float*)F.out2, (const float2*)F.gram};
     if constexpr (std::is_same<IN, InC32>::value) {
       if (F.U <= 8) {               // packed form, as a single call of this frame runs
         precode_one<1, InC32P, ST>(prm, gsc - F.sc_begin, A_s[wv], P_s[wv], G_s[wv], N_s[wv], c,
@@ -349,6 +353,9 @@ hipError_t launch_precode_batch(const BatchArgs& a, int max_u, int in_dtype, int
 
 hipError_t launch_precode(const PrecodeParams& p, int in_dtype, int scalar_f64,
                           const Schedule& sch, hipStream_t stream) {
+  if (p.gram && sch.variant != kPrecodeGeneric)  // a cached Gram runs the generic kernel
+    return launch_precode(p, in_dtype, scalar_f64, Schedule{kPrecodeGeneric, sch.blocks_per_cu},
+                          stream);
   if (sch.variant == kPrecodeSplit) {
     if (split_eligible(in_dtype, p.U, p.S, p.B, true))
       return launch_precode_split(p, scalar_f64, sch, stream);

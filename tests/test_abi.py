@@ -191,6 +191,31 @@ def test_users_beyond_32_validation():
         assert b"U=" in lib.mimo_last_error()
 
 
+def test_cached_gram_validation():
+    """mimo_detect_cg_gram / mimo_precode_cg_gram validate like the direct
+    calls and require an aligned G; U beyond 32 is not built for them."""
+    lib = L.lib()
+    s = L.shape(32, 8, 2, 3, 4)
+    det = lambda sh, G, **kw: lib.mimo_detect_cg_gram(sh, G, P, P, 0, kw.get("n0", 0.5), 1.0,
+                                                       kw.get("m", 4), 0, P2, None, None, None,
+                                                       None)
+    pre = lambda sh, G, **kw: lib.mimo_precode_cg_gram(sh, G, P, P, 0, kw.get("beta", 0.1), 1, 0,
+                                                        P2, None, None)
+    for fn in (det, pre):
+        assert fn(s, None) == L.MIMO_EINVAL
+        assert fn(s, P + 8) == L.MIMO_EINVAL
+        assert fn(L.shape(32, 8, 2, 3, 0), P) == L.MIMO_OK
+        assert fn(L.shape(128, 33, 2, 3, 4), P) == L.MIMO_EUNSUPPORTED
+        assert fn(L.shape(4, 8, 2, 3, 4), P) == L.MIMO_EINVAL             # B < U
+    assert det(s, P, n0=0.0) == L.MIMO_EINVAL
+    assert det(s, P, m=5) == L.MIMO_EUNSUPPORTED
+    assert pre(s, P, beta=-1.0) == L.MIMO_EINVAL
+    fr = (L.MimoFrame * 1)()
+    fr[0] = L.MimoFrame(4, 32, 8, 2, 3, P, P, P2, None, 0.5, 1.0, 0.0, 0, P + 4)
+    assert lib.mimo_detect_cg_batch(ctypes.addressof(fr), 1, 0, 4, 0, None) == L.MIMO_EINVAL
+    assert b"gram" in lib.mimo_last_error()
+
+
 def test_zero_subcarriers_is_a_noop():
     assert _detect(L.shape(32, 8, 14, 3, 0)) == L.MIMO_OK
 
