@@ -501,17 +501,24 @@ struct Storage<InBF16, W> {
 };
 
 // Whole Gram / matched filter of one subcarrier without cross-subcarrier
-// prefetch (used by the generic kernels).
+// prefetch (used by the generic and batched kernels): half-size blocks in
+// two register buffers, the next block's loads in flight while the current
+// block's MFMAs run.  The k-steps are accumulated in the same order as a
+// single-buffer walk, so the values are the same.
 template <int W, bool DO_GRAM, bool DO_MF, typename IN>
 __device__ __forceinline__ void gram_mf(IN tag, const void* Hn, const void* Yn, int B, int U,
                                         int S, int s0, int c, int g, GramAcc<W>& acc) {
   typename Storage<IN, W>::Sub sb;
   sb.init(Hn, DO_MF ? Yn : nullptr, B, U, S, s0, c, g);
-  using Blk = typename Storage<IN, W>::Block;
-  for (int b0 = 0; b0 < B; b0 += Blk::ANT) {
-    Blk blk;
-    blk.template load<DO_MF>(sb, b0);
-    blk.template mma<DO_GRAM, DO_MF>(acc);
+  using Blk = typename Storage<IN, W>::SmallBlock;
+  Blk cur, nxt;
+  cur.template load<DO_MF>(sb, 0);
+  for (int b0 = 0; b0 < B; b0 += 2 * Blk::ANT) {
+    if (b0 + Blk::ANT < B) nxt.template load<DO_MF>(sb, b0 + Blk::ANT);
+    cur.template mma<DO_GRAM, DO_MF>(acc);
+    if (b0 + Blk::ANT >= B) break;
+    if (b0 + 2 * Blk::ANT < B) cur.template load<DO_MF>(sb, b0 + 2 * Blk::ANT);
+    nxt.template mma<DO_GRAM, DO_MF>(acc);
   }
   if (DO_MF) finish_mf(tag, acc);
 }
