@@ -221,18 +221,23 @@ def main():
         log(f"{label}: {wall * 1e3:.3f} ms/step ({ker * 1e3:.3f} ms between the step's events)")
         return wall, ker
 
-    def kernel_time(fn, reps=20):
+    def kernel_time(fn, reps=20, batches=3):
         """Average duration of back-to-back launches between two events on
-        the stream the kernels run on (torch's current stream)."""
+        the stream the kernels run on (torch's current stream); the median
+        over ``batches`` such groups of ``reps`` launches, so that one host
+        stall while the queue runs dry does not set the figure."""
         fn()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps / 1e3
+        ts = []
+        for _ in range(batches):
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / reps / 1e3)
+        return sorted(ts)[len(ts) // 2]
 
     from paper_1404_0424_amd import autotune
     tuned = {}

@@ -190,10 +190,9 @@ mimo_status mimo_detect_precode_cg(const mimo_shape* ul, const mimo_shape* dl, c
  * Gram matrix of the channel supplied instead of formed: G = H^H H (Sec.
  * II-A; = H_d H_d^H by reciprocity, Sec. II-B) of this H, without
  * regularization, e.g. written once per channel by mimo_gram_mf with reg = 0
- * and kept while the channel holds (the serving runtime caches it per
- * channel).  The call adds reg = n0/es (detection) or beta (precoding) to the
- * diagonal and reads H only for the matched filter b = H^H y or the output
- * q = H_u v, skipping the Gram's products.
+ * and kept while the channel holds.  The call adds reg = n0/es (detection) or
+ * beta (precoding) to the diagonal and reads H only for the matched filter
+ * b = H^H y or the output q = H_u v, skipping the Gram's products.
  *   G  complex64 [n_sc][U][U], Hermitian with a real diagonal and an exactly
  *      conjugate lower triangle (mimo_gram_mf's layout)
  * Other arguments, outputs and rules as mimo_detect_cg (approximate SINR)
