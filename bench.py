@@ -914,7 +914,7 @@ def serving_leg(n_frames, skip, native=False):
             return SV.UplinkRequest(f.ch_id, data[f.ch_id][0], n0, 1.0, f.m, 3)
         return SV.DownlinkRequest(f.ch_id, data[f.ch_id][1], n0, 3, True)
 
-    def run(rate, frames_n, dtype="c32", budget=16 << 30):
+    def run(rate, frames_n, dtype="c32", budget=16 << 30, gram=False):
         frames = W.serving_frames(W.rng_for(4, 1 + int(rate)), 16, frames_n, rate)
         # the native server's consumer reads no outputs (they return to the
         # pool at completion) and submits pre-marshalled requests without
@@ -923,7 +923,10 @@ def serving_leg(n_frames, skip, native=False):
                                keep_outputs=False) if native
                else SV.Server(ex, hbm_budget=budget, n_slots=4))
         for c in chans:
-            srv.register_channel(c.ch_id, c.H, dtype)
+            if gram:
+                srv.register_channel(c.ch_id, c.H, dtype, gram=True)
+            else:
+                srv.register_channel(c.ch_id, c.H, dtype)
         reqs = [srv.prepare(request(f)) if native else request(f) for f in frames]
         submit = (lambda r: srv.submit(r, future=False)) if native else srv.submit
         # warm up every shape class once
@@ -1035,6 +1038,15 @@ def serving_leg(n_frames, skip, native=False):
     log(f"{tag}serving saturation, BF16 channel storage: {sat16['frames_per_s']:.0f} frames/s, "
         f"{sat16['solves_per_s']:.3g} solves/s")
     out["saturation_bf16"] = sat16
+    if native:
+        # each channel registered with its Gram matrix, formed once: the
+        # frames of channels with U > 8 skip the Gram's products (outputs
+        # bitwise unchanged)
+        satg = run(0.0, n_frames, gram=True)
+        satg["vs_ideal_batches"] = satg["solves_per_s"] / ideal["solves_per_s"]
+        log(f"{tag}serving saturation, cached Gram per channel: {satg['frames_per_s']:.0f} "
+            f"frames/s, {satg['solves_per_s']:.3g} solves/s, p50 {satg['p50_ms']:.3f} ms")
+        out["saturation_cached_gram"] = satg
     sys.setswitchinterval(old_switch)
     return out
 

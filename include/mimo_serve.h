@@ -9,7 +9,8 @@
  * mimo_cg.h entry points do (the server calls them).  Nothing here changes
  * the arithmetic: a frame's outputs are bitwise those of a single
  * mimo_detect_cg / mimo_precode_cg call on the same inputs (a GPU test
- * checks this alone and in a mix).
+ * checks this alone and in a mix), also when the channel was registered with
+ * its Gram matrix (mimo_server_register_channel_gram).
  *
  * Memory.  mimo_server_create allocates one device pool of cfg.hbm_budget
  * bytes; the server allocates nothing else on the device.  Registered
@@ -117,9 +118,24 @@ int mimo_server_create(const mimo_server_config* cfg, int device, mimo_server** 
 int mimo_server_destroy(mimo_server* s);
 
 /* H: [n_sc][B][U] in storage type in_dtype (complex64, or the blocked
- * 16-bit layout of mimo_convert), device, caller-owned while registered. */
+ * 16-bit layout of mimo_convert), device, caller-owned while registered.
+ * Registering an id again replaces its channel; requests already submitted
+ * keep the arrays registered when they were submitted, which must stay valid
+ * until those requests complete. */
 int mimo_server_register_channel(mimo_server* s, int64_t ch_id, const void* H, int in_dtype,
                                  int64_t n_sc, int32_t B, int32_t U);
+/* The same with the channel's Gram matrix G = H^H H (Sec. II-A; the downlink's
+ * H_d H_d^H by reciprocity, Sec. II-B): complex64 [n_sc][U][U] as
+ * mimo_gram_mf writes it with reg = 0 from this H, device, caller-owned and
+ * complete (like H) before the first request on the channel is submitted.
+ * Uplink frames with the approximate SINR and downlink frames of channels
+ * with U > 8 then run as mimo_detect_cg_gram / mimo_precode_cg_gram, which
+ * skip the Gram's products; their outputs are bitwise those of the direct
+ * calls.  Exact-SINR frames and channels with U <= 8 ignore G.  G's bytes
+ * count against the budget with H's.  G = NULL is mimo_server_register_channel. */
+int mimo_server_register_channel_gram(mimo_server* s, int64_t ch_id, const void* H,
+                                      const void* G, int in_dtype, int64_t n_sc, int32_t B,
+                                      int32_t U);
 int mimo_server_unregister_channel(mimo_server* s, int64_t ch_id);
 
 /* Queue a request; *req_id receives its id (> 0).  `ready_stream` (a

@@ -123,6 +123,8 @@ _SIGNATURES = {
     "mimo_server_destroy": (_i, [_vp]),
     "mimo_server_register_channel": (_i, [_vp, ctypes.c_int64, _vp, _i, ctypes.c_int64,
                                           ctypes.c_int32, ctypes.c_int32]),
+    "mimo_server_register_channel_gram": (_i, [_vp, ctypes.c_int64, _vp, _vp, _i, ctypes.c_int64,
+                                               ctypes.c_int32, ctypes.c_int32]),
     "mimo_server_unregister_channel": (_i, [_vp, ctypes.c_int64]),
     "mimo_server_submit_uplink": (_i, [_vp, ctypes.POINTER(MimoUplinkReq), _vp,
                                        ctypes.POINTER(ctypes.c_int64)]),

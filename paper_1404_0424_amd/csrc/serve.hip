@@ -113,8 +113,15 @@ struct Channel {
   int dtype;
   int64_t n_sc;
   int B, U;
-  int64_t bytes;
+  int64_t bytes;                // H and G, counted against the budget
+  const void* G;                // caller's G = H^H H, or NULL
 };
+
+// Frames that read the channel's cached Gram: batched ones (approximate SINR
+// uplink, every downlink) of channels with more than 8 users, where the
+// cached form is bitwise the direct one (at U <= 8 the direct kernels form a
+// packed Gram instead).
+const void* frame_gram(const Channel& ch) { return ch.U > 8 ? ch.G : nullptr; }
 
 struct Req {
   int64_t id = 0;
@@ -327,6 +334,7 @@ void mimo_server::run_launch(Launch* L) {
       fr.U = r->ch.U;
       fr.S = r->S();
       fr.H = r->ch.H;
+      fr.gram = frame_gram(r->ch);
       fr.out = ptr(r->out_off);
       if (r->kind == 0) {
         fr.K = r->up.K;
@@ -616,9 +624,16 @@ int mimo_server_destroy(mimo_server* s) {
 
 int mimo_server_register_channel(mimo_server* s, int64_t ch_id, const void* H, int in_dtype,
                                  int64_t n_sc, int32_t B, int32_t U) {
+  return mimo_server_register_channel_gram(s, ch_id, H, nullptr, in_dtype, n_sc, B, U);
+}
+
+int mimo_server_register_channel_gram(mimo_server* s, int64_t ch_id, const void* H,
+                                      const void* G, int in_dtype, int64_t n_sc, int32_t B,
+                                      int32_t U) {
   mimo::set_last_error("");
   if (!s) return fail(MIMO_EINVAL, "server is NULL");
   if (!H || ((uintptr_t)H & 15u)) return fail(MIMO_EINVAL, "H is NULL or not 16-byte aligned");
+  if ((uintptr_t)G & 7u) return fail(MIMO_EINVAL, "G is not 8-byte aligned");
   if (in_dtype != MIMO_C32 && in_dtype != MIMO_C16 && in_dtype != MIMO_CBF16)
     return fail(MIMO_EINVAL, "in_dtype=%d unknown", in_dtype);
   if (U > MIMO_MAX_USERS_COMMON && U <= B && B <= MIMO_MAX_ANTENNAS)
@@ -626,14 +641,14 @@ int mimo_server_register_channel(mimo_server* s, int64_t ch_id, const void* H, i
   if (n_sc < 1 || U < 1 || U > MIMO_MAX_USERS_COMMON || B < U || B > MIMO_MAX_ANTENNAS ||
       (in_dtype != MIMO_C32 && B % 8))
     return fail(MIMO_EINVAL, "bad channel shape n_sc=%lld B=%d U=%d", (long long)n_sc, B, U);
-  const int64_t bytes = n_sc * B * U * (in_dtype == MIMO_C32 ? 8 : 4);
+  const int64_t bytes = n_sc * B * U * (in_dtype == MIMO_C32 ? 8 : 4) + (G ? n_sc * U * U * 8 : 0);
   std::lock_guard<std::mutex> lk(s->mu);
   auto it = s->channels.find(ch_id);
   const int64_t old = it == s->channels.end() ? 0 : it->second.bytes;
   if (s->channel_bytes - old + bytes + (int64_t)s->pool.used() > s->cfg.hbm_budget)
     return fail(MIMO_EUNSUPPORTED, "channel %lld (%lld bytes) exceeds the HBM budget",
                 (long long)ch_id, (long long)bytes);
-  s->channels[ch_id] = Channel{H, in_dtype, n_sc, B, U, bytes};
+  s->channels[ch_id] = Channel{H, in_dtype, n_sc, B, U, bytes, G};
   s->channel_bytes += bytes - old;
   return MIMO_OK;
 }

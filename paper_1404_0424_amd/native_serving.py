@@ -73,9 +73,11 @@ class NativeServer:
         self._thread.start()
 
     # ------------------------------------------------------------ channels
-    def register_channel(self, ch_id, H, dtype: str = "c32") -> None:
+    def register_channel(self, ch_id, H, dtype: str = "c32", gram: bool = False) -> None:
         """Keep H (n_sc, B, U) on the device (in ``dtype`` storage) for later
-        requests."""
+        requests.  ``gram``: also form its Gram matrix G = H^H H once
+        (mimo_gram_mf, reg = 0) and register it, so that the frames of this
+        channel skip the Gram's products (mimo_server_register_channel_gram)."""
         from . import api
         t = self.torch
         Hd = H if isinstance(H, t.Tensor) else t.from_numpy(
@@ -87,14 +89,16 @@ class NativeServer:
         else:
             store = api.convert(Hd, dtype)
             ptr = store.data.data_ptr()
+        G = api.gram_mf(store, None, 0.0)[0] if gram else None
         t.cuda.synchronize(self.dev)
         with self._lock:
             cid = self._channels[ch_id][0] if ch_id in self._channels else self._next_ch
             if ch_id not in self._channels:
                 self._next_ch += 1
-            L.check(self._lib.mimo_server_register_channel(self._h, cid, ptr, _DTYPES[dtype], n, B,
-                                                           U))
-            self._channels[ch_id] = (cid, store, dtype, (n, B, U))
+            L.check(self._lib.mimo_server_register_channel_gram(
+                self._h, cid, ptr, G.data_ptr() if G is not None else None, _DTYPES[dtype], n, B,
+                U))
+            self._channels[ch_id] = (cid, store, dtype, (n, B, U), G)
 
     def unregister_channel(self, ch_id) -> None:
         with self._lock:
@@ -163,7 +167,10 @@ class NativeServer:
         with self._lock:
             st = p.fn(self._h, p.ref, stream, ctypes.byref(rid))
             if st == L.MIMO_OK:
-                self._pending[rid.value] = (fut, p.req, p.keep)
+                # the request runs on the channel arrays registered now: keep
+                # them alive until it completes, even if the channel is
+                # registered again or dropped meanwhile
+                self._pending[rid.value] = (fut, p.req, (p.keep, self._channels.get(p.req.ch_id)))
         if st != L.MIMO_OK:
             try:
                 L.check(st)

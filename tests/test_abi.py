@@ -408,6 +408,7 @@ def test_server_validation_without_a_gpu():
     dn = L.MimoDownlinkReq()
     assert lib.mimo_server_destroy(None) == L.MIMO_EINVAL
     assert lib.mimo_server_register_channel(None, 1, P, 0, 1, 8, 4) == L.MIMO_EINVAL
+    assert lib.mimo_server_register_channel_gram(None, 1, P, P, 0, 1, 8, 4) == L.MIMO_EINVAL
     assert lib.mimo_server_unregister_channel(None, 1) == L.MIMO_EINVAL
     assert lib.mimo_server_submit_uplink(None, ctypes.byref(up), None, ctypes.byref(rid)) == L.MIMO_EINVAL
     assert lib.mimo_server_submit_downlink(None, ctypes.byref(dn), None, ctypes.byref(rid)) == L.MIMO_EINVAL

@@ -112,6 +112,58 @@ def test_exact_sinr_and_xhat_requests(setup):
     assert rel_err_vec(X, ref["xhat"], axis=1) <= TOL_X
 
 
+def test_registered_gram_is_bitwise_the_direct_calls(setup):
+    """Channels registered with their Gram matrix (mimo_server_register_channel_gram):
+    batched uplink and downlink frames of U > 8 read G instead of forming it,
+    exact-SINR frames and U <= 8 ignore it; every result is bitwise the
+    single direct call's, also after the channel is registered again with
+    another H (and its G), and the channel bytes count G."""
+    NS, SV, rng, chans = setup
+    from paper_1404_0424_amd import api
+    print("native serving: registered Gram", flush=True)
+    srv = NS.NativeServer(hbm_budget=4 << 30, n_slots=3)
+    base = srv.cache_bytes
+    for i, H in chans.items():
+        srv.register_channel(i, H, "c32", gram=True)
+    n_h = sum(H.shape[0] * H.shape[1] * H.shape[2] * 8 for H in chans.values())
+    n_g = sum(H.shape[0] * H.shape[2] ** 2 * 8 for H in chans.values())
+    assert srv.cache_bytes - base == n_h + n_g
+    srv.register_channel("h16", chans[5], "bf16", gram=True)
+    jobs = []
+    for i in chans:
+        jobs.append((i, "c32") + _uplink(SV, rng, chans[i], i))
+        jobs.append((i, "c32") + _downlink(SV, rng, chans[i], i))
+    jobs.append((4, "c32") + _uplink(SV, rng, chans[4], 4, sinr_mode="exact"))
+    jobs.append(("h16", "bf16") + _uplink(SV, rng, chans[5], "h16"))
+    jobs.append(("h16", "bf16") + _downlink(SV, rng, chans[5], "h16"))
+    futs = [srv.submit(j[2]) for j in jobs]
+    outs = []
+    for f in futs:
+        o = f.result(timeout=60).outputs
+        outs.append(host(o["llr"] if "llr" in o else o["Q"]))
+    # the same channel id registered again with another H: its new G is used
+    H2 = W.iid_channel(rng, *chans[1].shape)
+    srv.register_channel(1, H2, "c32", gram=True)
+    up2, _ = _uplink(SV, rng, H2, 1)
+    dn2, _ = _downlink(SV, rng, H2, 1)
+    o_up2 = host(srv.submit(up2).result(timeout=60).outputs["llr"])
+    o_dn2 = host(srv.submit(dn2).result(timeout=60).outputs["Q"])
+    srv.close()
+    for (ch, dt, req, _), out in zip(jobs, outs):
+        H = dev(chans[5] if ch == "h16" else chans[ch])
+        if dt != "c32":
+            H = api.convert(H, dt)
+        if isinstance(req, SV.UplinkRequest):
+            Yin = req.Y if dt == "c32" else api.convert(req.Y, dt)
+            ref = api.detect_cg(H, Yin, req.n0, 1.0, 3, 6, req.sinr_mode)["llr"]
+        else:
+            ref = api.precode_cg(H, req.T, 0.3, 3, True)[0]
+        assert np.array_equal(out.view(np.uint32), host(ref).view(np.uint32)), (ch, type(req))
+    Hd2 = dev(H2)
+    assert np.array_equal(o_up2, host(api.detect_cg(Hd2, up2.Y, up2.n0, 1.0, 3, 6)["llr"]))
+    assert np.array_equal(o_dn2, host(api.precode_cg(Hd2, dn2.T, 0.3, 3, True)[0]))
+
+
 def test_small_budget_16bit_channel_and_pool_release(setup):
     NS, SV, rng, chans = setup
     print("native serving: small budget, 16-bit channel", flush=True)
