@@ -164,6 +164,34 @@ def test_registered_gram_is_bitwise_the_direct_calls(setup):
     assert np.array_equal(o_dn2, host(api.precode_cg(Hd2, dn2.T, 0.3, 3, True)[0]))
 
 
+def test_channel_replaced_while_requests_are_queued(setup):
+    """A request runs on the channel arrays registered when it was submitted:
+    the binding keeps them alive after the channel id is registered again,
+    even when their memory would otherwise be handed out and overwritten."""
+    NS, SV, rng, chans = setup
+    from paper_1404_0424_amd import api
+    print("native serving: channel replaced while queued", flush=True)
+    H_old = chans[2]
+    srv = NS.NativeServer(hbm_budget=1 << 30, n_slots=2)
+    srv.register_channel("r", H_old, "c32", gram=True)
+    srv.pause()
+    up, _ = _uplink(SV, rng, H_old, "r")
+    fut = srv.submit(up)
+    srv.register_channel("r", W.iid_channel(rng, *H_old.shape), "c32", gram=True)
+    gc.collect()
+    n, B, U = H_old.shape
+    # same-size blocks: the caching allocator hands out freed ones first
+    junk = [torch.full((n, B, U), 7.0 + 7.0j, dtype=torch.complex64, device="cuda"),
+            torch.full((n, U, U), 7.0 + 7.0j, dtype=torch.complex64, device="cuda")]
+    torch.cuda.synchronize()
+    srv.resume()
+    out = host(fut.result(timeout=60).outputs["llr"])
+    srv.close()
+    del junk
+    ref = api.detect_cg(dev(H_old), up.Y, up.n0, 1.0, 3, 6)["llr"]
+    assert np.array_equal(out, host(ref))
+
+
 def test_small_budget_16bit_channel_and_pool_release(setup):
     NS, SV, rng, chans = setup
     print("native serving: small budget, 16-bit channel", flush=True)
