@@ -744,6 +744,8 @@ def configs_leg(api, autotune, kernel_time, dev, samples):
                 autotune.tune("detect", wl.U, 0, fd, exclude=x3)
                 autotune.tune("precode", wl.U, 0, fp, exclude=x3)
                 autotune.tune("slot", wl.U, 0, fs, exclude=x3)
+            for _ in range(5):         # the device idled while the inputs were drawn
+                fd(), fp(), fs()
             td, tp, ts = kernel_time(fd, reps=10), kernel_time(fp, reps=10), kernel_time(fs, reps=10)
             sv, sb = autotune.get_schedule("slot", wl.U, 0)
             dsaved, psaved = autotune.get_schedule("detect", wl.U, 0), autotune.get_schedule(
