@@ -205,6 +205,7 @@ def main():
 
     def timed(Hx, Yx, label, separate=False):
         run = run_separate if separate else run_slot
+        gpu_warm([lambda: run(Hx, Yx, 1)], 0.1)
         run(Hx, Yx, args.warmup)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -225,8 +226,9 @@ def main():
         """Average duration of back-to-back launches between two events on
         the stream the kernels run on (torch's current stream); the median
         over ``batches`` such groups of ``reps`` launches, so that one host
-        stall while the queue runs dry does not set the figure."""
-        fn()
+        stall while the queue runs dry does not set the figure.  The device
+        first runs ``fn`` for a while (gpu_warm)."""
+        gpu_warm([fn], 0.03)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         ts = []
@@ -613,6 +615,24 @@ def oracle_errors(samples, O):
     return out
 
 
+def gpu_warm(fns, seconds):
+    """Keep the device busy with ``fns`` (round robin, synchronized every few
+    calls so that the queue stays short) for ``seconds`` of wall time.  After
+    an idle spell (inputs drawn on the host) launches run 10-20% slower for
+    the first few tens of milliseconds of work, until the clocks are back up;
+    untimed."""
+    import torch
+    t0 = time.perf_counter()
+    i = 0
+    while True:
+        fns[i % len(fns)]()
+        i += 1
+        if i % 8 == 0:
+            torch.cuda.synchronize()
+            if time.perf_counter() - t0 >= seconds:
+                break
+
+
 def mfma_count(B, U, S, K, op):
     """v_mfma_f32_16x16x4_f32 instructions per subcarrier issued by the
     complex64 kernels: Gram tiles (3 per k-step on a diagonal tile, 4 off
@@ -744,8 +764,7 @@ def configs_leg(api, autotune, kernel_time, dev, samples):
                 autotune.tune("detect", wl.U, 0, fd, exclude=x3)
                 autotune.tune("precode", wl.U, 0, fp, exclude=x3)
                 autotune.tune("slot", wl.U, 0, fs, exclude=x3)
-            for _ in range(5):         # the device idled while the inputs were drawn
-                fd(), fp(), fs()
+            gpu_warm([fd, fp, fs], 0.15)   # the device idled while the inputs were drawn
             td, tp, ts = kernel_time(fd, reps=10), kernel_time(fp, reps=10), kernel_time(fs, reps=10)
             sv, sb = autotune.get_schedule("slot", wl.U, 0)
             dsaved, psaved = autotune.get_schedule("detect", wl.U, 0), autotune.get_schedule(

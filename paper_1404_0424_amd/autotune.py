@@ -74,10 +74,29 @@ def time_call(fn, reps: int = 5, warmup: int = 2) -> float:
     return e0.elapsed_time(e1) / reps / 1e3
 
 
+def _warm(fn, seconds: float) -> None:
+    """Run ``fn`` for ``seconds`` of wall time (synchronized every few calls)
+    so that the first candidate is not timed while the device clocks are
+    still coming up from an idle spell."""
+    import time
+
+    import torch
+    t0 = time.perf_counter()
+    i = 0
+    while True:
+        fn()
+        i += 1
+        if i % 8 == 0:
+            torch.cuda.synchronize()
+            if time.perf_counter() - t0 >= seconds:
+                break
+
+
 def tune(op: str, U: int, dtype_code: int, fn, reps: int = 5, log=None, exclude=()) -> dict:
     """Time ``fn`` (which launches ``op`` on fixed inputs) under every
     candidate schedule (variants named in ``exclude`` left out), install the
     fastest, return the measurements."""
+    _warm(fn, 0.1)
     results = []
     for v, name in enumerate(variants(op)):
         if name in BASELINE_VARIANTS or name in exclude:
