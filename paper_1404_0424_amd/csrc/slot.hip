@@ -38,15 +38,22 @@ __device__ __forceinline__ float2 load_y_step(const Sub& sb, int t) {
   return bload2(sb.ry, sb.oy, (uint32_t)(4 * t) * sb.S * 8u);
 }
 
-// Register budget: 2 waves per SIMD.  The channel (64 VGPRs at B = 128) is
-// held from the Gram to the output stage and the next subcarrier's is in
-// flight during the uplink stage, ~190 VGPRs in all; a 3-wave budget (168)
-// spills and measured slower (260 vs 253 us per 19,200 subcarriers of
-// 128x16 at K = 4).
-constexpr int kSlotMinBlocks = 2;
+// Register budget.  The channel (64 VGPRs at B = 128) is held from the Gram
+// to the output stage and the next subcarrier's is in flight during the
+// uplink stage: 174 VGPRs with FP32 CG scalars, 2 waves per SIMD.  A 3-wave
+// budget (168) costs 0-24 bytes per lane of spills with FP32 scalars and was
+// faster: 226-230 against 239-241 us per 19,200 subcarriers of 128x16 at
+// K = 4, 64-QAM, each at its best grid (same-box A/B, the device kept busy
+// before each timing; 242 against 246 us with 256-QAM).  With FP64 scalars
+// (92-116 bytes), the packed U <= 8 form (52-84) and the bf16-split Gram
+// (24-48) the 3-wave budget spills more, so those keep 2 waves (at B <= 64
+// every form fits 3 waves anyway).
+template <typename IN, typename ST>
+constexpr int slot_min_blocks() { return std::is_same<IN, InC32>::value && sizeof(ST) == 4 ? 3 : 2; }
 
 template <int BMAX, typename IN, typename ST, int M_BITS>
-__global__ __launch_bounds__(256, kSlotMinBlocks) void slot_resident_kernel(SlotParams sp) {
+__global__ __launch_bounds__(256, (slot_min_blocks<IN, ST>())) void slot_resident_kernel(
+    SlotParams sp) {
   constexpr int NU = 16, AST = NU + 2;
   using Sub = typename Storage<IN, 1>::Sub;
   using RB = typename ResidentBlock<IN>::type;
