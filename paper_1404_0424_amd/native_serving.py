@@ -89,7 +89,8 @@ class NativeServer:
         else:
             store = api.convert(Hd, dtype)
             ptr = store.data.data_ptr()
-        G = api.gram_mf(store, None, 0.0)[0] if gram else None
+        # (channels of up to 8 users form a packed Gram per frame and ignore G)
+        G = api.gram_mf(store, None, 0.0)[0] if gram and U > 8 else None
         t.cuda.synchronize(self.dev)
         with self._lock:
             cid = self._channels[ch_id][0] if ch_id in self._channels else self._next_ch

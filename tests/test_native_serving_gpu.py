@@ -126,7 +126,7 @@ def test_registered_gram_is_bitwise_the_direct_calls(setup):
     for i, H in chans.items():
         srv.register_channel(i, H, "c32", gram=True)
     n_h = sum(H.shape[0] * H.shape[1] * H.shape[2] * 8 for H in chans.values())
-    n_g = sum(H.shape[0] * H.shape[2] ** 2 * 8 for H in chans.values())
+    n_g = sum(H.shape[0] * H.shape[2] ** 2 * 8 for H in chans.values() if H.shape[2] > 8)
     assert srv.cache_bytes - base == n_h + n_g
     srv.register_channel("h16", chans[5], "bf16", gram=True)
     jobs = []
