@@ -166,6 +166,13 @@ def precode_cg(H, T: torch.Tensor, beta: float, K: int, normalize: bool = False,
     return Q, qn
 
 
+def _gram_ptr(frame, n, U):
+    """Device pointer of a batched frame's optional cached Gram (5th entry)."""
+    if len(frame) < 5 or frame[4] is None:
+        return None
+    return _gram_arg(frame[4], n, U)
+
+
 def _gram_arg(G, n, U):
     _check_c64(G, "G")
     if tuple(G.shape) != (n, U, U) or not G.is_contiguous():
@@ -251,15 +258,17 @@ def _views(dev, dtype, shapes):
 def detect_cg_batch(frames, K: int | list, qam_bits: int, scalar_prec: str = "f32",
                     xhat: bool = False, stream=None) -> list[dict]:
     """Detect up to MIMO_MAX_BATCH frames of different shapes in one launch.
-    ``frames`` is a list of (H, Y, n0, es) with the same storage type; K is
-    one value or one per frame.  Returns one output dict per frame (views of
-    one allocation per output kind)."""
+    ``frames`` is a list of (H, Y, n0, es) or (H, Y, n0, es, G) with the same
+    storage type (G: the frame's cached Gram matrix, as detect_cg_gram takes
+    it); K is one value or one per frame.  Returns one output dict per frame
+    (views of one allocation per output kind)."""
     if not frames:
         return []
     Ks = K if isinstance(K, (list, tuple)) else [K] * len(frames)
     arr = (L.MimoFrame * len(frames))()
     code0, dims = None, []
-    for H, Y, n0, es in frames:
+    for fr in frames:
+        H, Y = fr[0], fr[1]
         hp, code, n, B, U = _channel(H)
         if code0 is None:
             code0 = code
@@ -272,9 +281,10 @@ def detect_cg_batch(frames, K: int | list, qam_bits: int, scalar_prec: str = "f3
     xhs = (_views(dev, torch.complex64, [(n, U, S) for _, _, n, _, U, S in dims]) if xhat
            else [None] * len(frames))
     outs = []
-    for i, ((hp, yp, n, B, U, S), (_, _, n0, es), k) in enumerate(zip(dims, frames, Ks)):
+    for i, ((hp, yp, n, B, U, S), fr, k) in enumerate(zip(dims, frames, Ks)):
+        n0, es = fr[2], fr[3]
         arr[i] = L.MimoFrame(n, B, U, S, int(k), hp, yp, llrs[i].data_ptr(), _ptr(xhs[i]),
-                             float(n0), float(es), 0.0, 0)
+                             float(n0), float(es), 0.0, 0, _gram_ptr(fr, n, U))
         outs.append({"llr": llrs[i], "xhat": xhs[i]} if xhat else {"llr": llrs[i]})
     prec = {"f32": L.MIMO_SCALAR_F32, "f64": L.MIMO_SCALAR_F64}[scalar_prec]
     L.check(L.lib().mimo_detect_cg_batch(ctypes.addressof(arr), len(frames), code0,
@@ -285,14 +295,16 @@ def detect_cg_batch(frames, K: int | list, qam_bits: int, scalar_prec: str = "f3
 def precode_cg_batch(frames, K: int | list, scalar_prec: str = "f32", qnorm: bool = False,
                      stream=None) -> list[tuple]:
     """Precode up to MIMO_MAX_BATCH frames in one launch.  ``frames`` is a
-    list of (H, T, beta, normalize).  Returns (Q, qnorm) per frame (views of
-    one allocation per output kind)."""
+    list of (H, T, beta, normalize) or (H, T, beta, normalize, G) (G: the
+    frame's cached Gram matrix).  Returns (Q, qnorm) per frame (views of one
+    allocation per output kind)."""
     if not frames:
         return []
     Ks = K if isinstance(K, (list, tuple)) else [K] * len(frames)
     arr = (L.MimoFrame * len(frames))()
     code0, dims = None, []
-    for H, T, beta, normalize in frames:
+    for fr in frames:
+        H, T = fr[0], fr[1]
         hp, code, n, B, U = _channel(H)
         if code0 is None:
             code0 = code
@@ -307,9 +319,11 @@ def precode_cg_batch(frames, K: int | list, scalar_prec: str = "f32", qnorm: boo
     qns = (_views(dev, torch.float32, [(n, S) for _, n, _, _, S in dims]) if qnorm
            else [None] * len(frames))
     outs = []
-    for i, ((hp, n, B, U, S), (_, T, beta, normalize), k) in enumerate(zip(dims, frames, Ks)):
+    for i, ((hp, n, B, U, S), fr, k) in enumerate(zip(dims, frames, Ks)):
+        T, beta, normalize = fr[1], fr[2], fr[3]
         arr[i] = L.MimoFrame(n, B, U, S, int(k), hp, T.data_ptr(), Qs[i].data_ptr(),
-                             _ptr(qns[i]), 0.0, 0.0, float(beta), int(bool(normalize)))
+                             _ptr(qns[i]), 0.0, 0.0, float(beta), int(bool(normalize)),
+                             _gram_ptr(fr, n, U))
         outs.append((Qs[i], qns[i]))
     prec = {"f32": L.MIMO_SCALAR_F32, "f64": L.MIMO_SCALAR_F64}[scalar_prec]
     L.check(L.lib().mimo_precode_cg_batch(ctypes.addressof(arr), len(frames), code0, prec,

@@ -143,3 +143,79 @@ def test_random_configuration(i):
             assert rel_err_vec(host(og["xhat"]), ref["xhat"], axis=1) <= TOL_X
             assert rel_err_vec(host(Qg), pref["Q"], axis=1) <= TOL_X
     print(f"case {i}: eps_L={el:.2e} eps_x={ex:.2e} eps_q={eq:.2e}", flush=True)
+
+
+N_BATCHES = 16
+
+
+def draw_batch(i):
+    """A batch of 2-8 frames of one kernel class (users 1-16 or 17-32, one
+    storage type, QAM order and scalar precision), each with its own shape,
+    K and SNR; about half carry their cached Gram matrix."""
+    rng = np.random.default_rng(8000 + i)
+    wide = bool(rng.random() < 0.5)
+    storage = "c32" if rng.random() < 0.7 else str(rng.choice(["f16", "bf16"]))
+    b = dict(storage=storage, m=int(rng.choice([2, 4, 6, 8])),
+             scalar=str(rng.choice(["f32", "f64"])), frames=[])
+    for _ in range(int(rng.integers(2, 9))):
+        U = int(rng.integers(17, 33) if wide else rng.integers(1, 17))
+        B = int(rng.integers(U, 257))
+        if storage != "c32":
+            B = max(8, -(-B // 8) * 8)
+        b["frames"].append(dict(U=U, B=B, n=int(rng.integers(1, 6)), S=int(rng.integers(1, 41)),
+                                K=min(U, int(rng.integers(1, 7))),
+                                snr=float(rng.uniform(0.0, 25.0)),
+                                gram=bool(rng.random() < 0.5),
+                                normalize=bool(rng.random() < 0.7)))
+    return b
+
+
+BATCHES = [draw_batch(i) for i in range(N_BATCHES)]
+
+
+@pytest.mark.parametrize("i", range(N_BATCHES),
+                         ids=[f"{i}-{len(b['frames'])}frames_{b['storage']}_{b['scalar']}_m{b['m']}"
+                              for i, b in enumerate(BATCHES)])
+def test_random_batch_equals_single_calls(i):
+    """mimo_detect_cg_batch / mimo_precode_cg_batch over a random mix of
+    frames: each frame bitwise its single call (detect_cg or detect_cg_gram,
+    precode_cg or precode_cg_gram as the frame carries G)."""
+    b = BATCHES[i]
+    print(f"random batch {i}: {b}", flush=True)
+    rng = np.random.default_rng(10000 + i)
+    A = api()
+    dt, m, scalar = b["storage"], b["m"], b["scalar"]
+    ups, dfr, pfr = [], [], []
+    for f in b["frames"]:
+        up = W.uplink_frame(rng, f["n"], f["B"], f["U"], f["S"], m, f["snr"])
+        dn = W.downlink_frame(rng, f["n"], f["B"], f["U"], f["S"], 4, f["snr"], H=up.H)
+        H, Y, T = dev(up.H), dev(up.Y), dev(dn.T)
+        if dt != "c32":
+            H, Y = A.convert(H, dt), A.convert(Y, dt)
+        G = A.gram_mf(H, None, 0.0)[0] if f["gram"] else None
+        ups.append((H, Y, T, G, up, dn))
+        dfr.append((H, Y, up.n0, up.es, G))
+        pfr.append((H, T, dn.beta, f["normalize"], G))
+    Ks = [f["K"] for f in b["frames"]]
+    dets = A.detect_cg_batch(dfr, Ks, m, scalar)
+    pres = A.precode_cg_batch(pfr, Ks, scalar, qnorm=True)
+    torch.cuda.synchronize()
+    for j, (f, (H, Y, T, G, up, dn)) in enumerate(zip(b["frames"], ups)):
+        if G is not None:
+            d1 = A.detect_cg_gram(G, H, Y, up.n0, up.es, f["K"], m, scalar)
+            Q1, q1 = A.precode_cg_gram(G, H, T, dn.beta, f["K"], f["normalize"], scalar)
+        else:
+            d1 = A.detect_cg(H, Y, up.n0, up.es, f["K"], m, "approx", scalar)
+            Q1, q1 = A.precode_cg(H, T, dn.beta, f["K"], f["normalize"], scalar)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(dets[j]["llr"]).view(np.uint32),
+                              host(d1["llr"]).view(np.uint32)), j
+        assert np.array_equal(host(pres[j][0]).view(np.uint32), host(Q1).view(np.uint32)), j
+        assert np.array_equal(host(pres[j][1]).view(np.uint32), host(q1).view(np.uint32)), j
+    # and the oracle on the first frame
+    f, (H, Y, T, G, up, dn) = b["frames"][0], ups[0]
+    Hq, Yq = _quantized(up.H, dt), _quantized(up.Y, dt)
+    assert llr_err(host(dets[0]["llr"]), O.detect_cg(Hq, Yq, up.n0, up.es, f["K"], m,
+                                                     "approx")["llr"]) <= TOL_L
+    assert rel_err_vec(host(pres[0][0]), O.precode_cg(Hq, dn.T, dn.beta, f["K"],
+                                                      f["normalize"])["Q"], axis=1) <= TOL_X
