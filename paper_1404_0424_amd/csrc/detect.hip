@@ -14,7 +14,10 @@ namespace mimo {
 // before the CG / LLR phase of the current one, so HBM latency overlaps
 // compute within the wave as well as across waves.
 // VALU: CG mat-vec on VALU FMAs (schedule variant "stream-valu").
-template <int W, typename IN, typename ST, int M_BITS, bool SMALL, bool VALU = false>
+// CACHED: A from the cached Gram matrix prm.gram (the blocks feed only the
+// matched filter), as detect_one's cached branch.
+template <int W, typename IN, typename ST, int M_BITS, bool SMALL, bool VALU = false,
+          bool CACHED = false>
 __global__ __launch_bounds__(256, 2) void detect_stream_kernel(DetectParams kprm) {
   constexpr int NU = 16 * W;
   constexpr int AST = NU + 2;   // LDS row stride (complex) of A
@@ -69,7 +72,7 @@ __global__ __launch_bounds__(256, 2) void detect_stream_kernel(DetectParams kprm
     Blk alt;
     for (int b0 = 0;; b0 += 2 * Blk::ANT) {
       alt.template load<true>(cur, b0 + Blk::ANT);
-      blk.template mma<true, true>(acc);
+      blk.template mma<!CACHED, true>(acc);
       const bool more2 = b0 + 2 * Blk::ANT < B;
       if (kUncondMem<IN>)
         blk.template load<true>(more2 ? cur : nxt, more2 ? b0 + 2 * Blk::ANT : 0);
@@ -77,13 +80,17 @@ __global__ __launch_bounds__(256, 2) void detect_stream_kernel(DetectParams kprm
         blk.template load<true>(cur, b0 + 2 * Blk::ANT);
       else if (nn < prm.n_sc)
         blk.template load<true>(nxt, 0);
-      alt.template mma<true, true>(acc);
+      alt.template mma<!CACHED, true>(acc);
       if (!more2) break;                           // blk holds the next subcarrier's block 0
     }
     finish_mf(IN{}, acc);
     AOperand<W> at;
     float d[W];
-    gram_to_operands<W>(IN{}, acc, As, Gs, Ps, AST, prm.reg, U, c, g, at, d);
+    if constexpr (CACHED)
+      cached_gram_to_operands<W>(prm.gram + (size_t)n * U * U, U, prm.reg, As, Gs, AST, c, g,
+                                 at, d);
+    else
+      gram_to_operands<W>(IN{}, acc, As, Gs, Ps, AST, prm.reg, U, c, g, at, d);
     cg_llr_epilogue<W, ST, M_BITS, kUncondMem<IN>, true, false, VALU>(prm, n, 0, acc, at, d, Gs,
                                                                        Ps, c, g, W_s[wv]);
     n = nn;
@@ -186,6 +193,14 @@ static void launch_one(const DetectParams& p, const Schedule& sch, hipStream_t s
   const dim3 grid(sched_grid(p.n_sc, sch)), block(kWave * kWavesPerBlock);
   if (p.S > 16 || sch.variant == kDetectGeneric || sch.variant == kDetectPlain)
     hipLaunchKernelGGL((detect_approx_kernel<W, IN, ST, M>), grid, block, 0, stream, p);
+  else if (p.gram) {                   // cached Gram: launch_detect_approx leaves the two forms
+    if (sch.variant == kDetectStream)
+      hipLaunchKernelGGL((detect_stream_kernel<W, IN, ST, M, false, false, true>), grid, block, 0,
+                         stream, p);
+    else
+      hipLaunchKernelGGL((detect_stream_kernel<W, IN, ST, M, true, false, true>), grid, block, 0,
+                         stream, p);
+  }
   else if (sch.variant == kDetectStreamSmall)
     hipLaunchKernelGGL((detect_stream_kernel<W, IN, ST, M, true>), grid, block, 0, stream, p);
   else if (sch.variant == kDetectValu) {
@@ -276,9 +291,12 @@ hipError_t launch_detect_batch(const BatchArgs& a, int max_u, int in_dtype, int 
 
 hipError_t launch_detect_approx(const DetectParams& p, int in_dtype, int scalar_f64, int m_bits,
                                 const Schedule& sch, hipStream_t stream) {
-  if (p.gram && sch.variant != kDetectGeneric)   // a cached Gram runs the generic kernel
+  // a cached Gram runs the generic kernel or the streaming forms (others map to
+  // stream-small)
+  if (p.gram && sch.variant != kDetectGeneric && sch.variant != kDetectStream &&
+      sch.variant != kDetectStreamSmall)
     return launch_detect_approx(p, in_dtype, scalar_f64, m_bits,
-                                Schedule{kDetectGeneric, sch.blocks_per_cu}, stream);
+                                Schedule{kDetectStreamSmall, sch.blocks_per_cu}, stream);
   if (sch.variant == kDetectPlain && in_dtype == 0)
     return launch_detect_plain(p, scalar_f64, m_bits, sch, stream);
   if (sch.variant == kDetectSplit) {

@@ -85,7 +85,9 @@ __global__ __launch_bounds__(256, 2) void precode_kernel(PrecodeParams prm) {
 // current one.  Loads are issued on every path (an empty descriptor after
 // the last subcarrier), so the compiler's load-counter waits cover exactly
 // the block consumed.  Same arithmetic in the same order as precode_one.
-template <int W, typename IN, typename ST, bool SMALL>
+// CACHED: A from the cached Gram matrix prm.gram; no block loads at all (H is
+// read only for q = H v), as precode_one's cached branch.
+template <int W, typename IN, typename ST, bool SMALL, bool CACHED = false>
 __global__ __launch_bounds__(256, 2) void precode_stream_kernel(PrecodeParams kprm) {
   constexpr int NU = 16 * W;
   constexpr int AST = NU + 2;
@@ -110,7 +112,7 @@ __global__ __launch_bounds__(256, 2) void precode_stream_kernel(PrecodeParams kp
   Blk blk;
   if (n < kprm.n_sc) {
     cur.init(offset_sc(IN{}, kprm.H, n, kprm.B, kprm.U), nullptr, kprm.B, kprm.U, kprm.S, 0, c, g);
-    blk.template load<false>(cur, 0);
+    if constexpr (!CACHED) blk.template load<false>(cur, 0);
   }
   while (n < kprm.n_sc) {
     const PrecodeParams prm = opaque_sizes(kprm);
@@ -122,21 +124,25 @@ __global__ __launch_bounds__(256, 2) void precode_stream_kernel(PrecodeParams kp
     if (nn >= prm.n_sc) nxt.disable();
     const void* Hn = offset_sc(IN{}, prm.H, n, B, U);
     // ---- A = H_d H_d^H + beta I = G + beta I (Algorithm 1, initialization)
-    GramAcc<W> acc;
-    acc.clear();
-    Blk alt;
-    // pairs of blocks; an odd count's last partner lies past B and reads
-    // zero, adding exact zeros (one loop exit, so nothing after the Gram
-    // waits for the next subcarrier's block in flight)
-    for (int b0 = 0;; b0 += 2 * Blk::ANT) {
-      alt.template load<false>(cur, b0 + Blk::ANT);
-      blk.template mma<true, false>(acc);
-      const bool more2 = b0 + 2 * Blk::ANT < B;
-      blk.template load<false>(more2 ? cur : nxt, more2 ? b0 + 2 * Blk::ANT : 0);
-      alt.template mma<true, false>(acc);
-      if (!more2) break;
+    if constexpr (CACHED) {
+      load_cached_gram<W>(prm.gram + (size_t)n * U * U, U, prm.beta, As, Gs, AST, lane);
+    } else {
+      GramAcc<W> acc;
+      acc.clear();
+      Blk alt;
+      // pairs of blocks; an odd count's last partner lies past B and reads
+      // zero, adding exact zeros (one loop exit, so nothing after the Gram
+      // waits for the next subcarrier's block in flight)
+      for (int b0 = 0;; b0 += 2 * Blk::ANT) {
+        alt.template load<false>(cur, b0 + Blk::ANT);
+        blk.template mma<true, false>(acc);
+        const bool more2 = b0 + 2 * Blk::ANT < B;
+        blk.template load<false>(more2 ? cur : nxt, more2 ? b0 + 2 * Blk::ANT : 0);
+        alt.template mma<true, false>(acc);
+        if (!more2) break;
+      }
+      store_gram(IN{}, acc, As, Gs, (float*)Ps, AST, prm.beta, c, g);
     }
-    store_gram(IN{}, acc, As, Gs, (float*)Ps, AST, prm.beta, c, g);
     wave_lds_sync();
     AOperand<W> at;
     at.load(As, AST, c, g, U);
@@ -173,7 +179,8 @@ __global__ __launch_bounds__(256, 2) void precode_stream_kernel(PrecodeParams kp
 template <typename ST>
 constexpr int resident_min_blocks() { return sizeof(ST) == 8 ? 2 : 3; }
 
-template <int BMAX, typename IN, typename ST>
+// CACHED: A from the cached Gram matrix prm.gram; H is still held for q = H v.
+template <int BMAX, typename IN, typename ST, bool CACHED = false>
 __global__ __launch_bounds__(256, resident_min_blocks<ST>()) void precode_resident_kernel(
     PrecodeParams kprm) {
   constexpr int NU = 16, AST = NU + 2;
@@ -220,12 +227,16 @@ __global__ __launch_bounds__(256, resident_min_blocks<ST>()) void precode_reside
       for (int j = 0; j < 4; ++j) b[0][j] = bload2(rt, ot[j], 0u);
     }
     // ---- A = H_d H_d^H + beta I = G + beta I (Algorithm 1, initialization)
-    GramAcc<1> acc;
-    acc.clear();
+    if constexpr (CACHED) {
+      load_cached_gram<1>(prm.gram + (size_t)n * U * U, U, prm.beta, As, Gs, AST, lane);
+    } else {
+      GramAcc<1> acc;
+      acc.clear();
 #pragma unroll
-    for (int t = 0; t < NK; ++t)
-      if (t * RB::ANT < B) hb[t].template mma<true, false>(acc);
-    store_gram(IN{}, acc, As, Gs, (float*)Ps, AST, prm.beta, c, g);
+      for (int t = 0; t < NK; ++t)
+        if (t * RB::ANT < B) hb[t].template mma<true, false>(acc);
+      store_gram(IN{}, acc, As, Gs, (float*)Ps, AST, prm.beta, c, g);
+    }
     wave_lds_sync();
     AOperand<1> at;
     at.load(As, AST, c, g, U);
@@ -283,7 +294,21 @@ __global__ __launch_bounds__(256, 2) void precode_batch_kernel(BatchArgs args) {
 template <int W, typename IN, typename ST>
 static void launch_one(const PrecodeParams& p, const Schedule& sch, hipStream_t stream) {
   const dim3 grid(sched_grid(p.n_sc, sch)), block(kWave * kWavesPerBlock);
-  if (sch.variant == kPrecodeResident && resident_fits<W>(p)) {
+  if (p.gram && p.S <= 16 && sch.variant != kPrecodeGeneric) {   // cached Gram
+    if (sch.variant == kPrecodeResident && resident_fits<W>(p)) {
+      if (p.B <= 64)
+        hipLaunchKernelGGL((precode_resident_kernel<64, IN, ST, true>), grid, block, 0, stream, p);
+      else
+        hipLaunchKernelGGL((precode_resident_kernel<128, IN, ST, true>), grid, block, 0, stream,
+                           p);
+    } else if (sch.variant == kPrecodeStream) {
+      hipLaunchKernelGGL((precode_stream_kernel<W, IN, ST, false, true>), grid, block, 0, stream,
+                         p);
+    } else {
+      hipLaunchKernelGGL((precode_stream_kernel<W, IN, ST, true, true>), grid, block, 0, stream,
+                         p);
+    }
+  } else if (sch.variant == kPrecodeResident && resident_fits<W>(p)) {
     if (p.B <= 64)
       hipLaunchKernelGGL((precode_resident_kernel<64, IN, ST>), grid, block, 0, stream, p);
     else
@@ -353,8 +378,13 @@ hipError_t launch_precode_batch(const BatchArgs& a, int max_u, int in_dtype, int
 
 hipError_t launch_precode(const PrecodeParams& p, int in_dtype, int scalar_f64,
                           const Schedule& sch, hipStream_t stream) {
-  if (p.gram && sch.variant != kPrecodeGeneric)  // a cached Gram runs the generic kernel
-    return launch_precode(p, in_dtype, scalar_f64, Schedule{kPrecodeGeneric, sch.blocks_per_cu},
+  // a cached Gram runs the generic, streaming or resident kernels (the bf16-split
+  // form has no Gram to split: resident; split: stream-small)
+  if (p.gram && (sch.variant == kPrecodeSplit || sch.variant == kPrecodeX3))
+    return launch_precode(p, in_dtype, scalar_f64,
+                          Schedule{sch.variant == kPrecodeX3 ? kPrecodeResident
+                                                             : kPrecodeStreamSmall,
+                                   sch.blocks_per_cu},
                           stream);
   if (sch.variant == kPrecodeSplit) {
     if (split_eligible(in_dtype, p.U, p.S, p.B, true))
