@@ -43,7 +43,7 @@ __device__ __forceinline__ float2 load_y_step(const Sub& sb, int t) {
 // uplink stage: 174 VGPRs with FP32 CG scalars, 2 waves per SIMD.  A 3-wave
 // budget (168) costs 0-24 bytes per lane of spills with FP32 scalars and was
 // faster: 226-230 against 239-241 us per 19,200 subcarriers of 128x16 at
-// K = 4, 64-QAM, each at its best grid (same-box A/B, the device kept busy
+// K = 4, 64-QAM, each at its best grid (A/B on one device, kept busy
 // before each timing; 242 against 246 us with 256-QAM).  With FP64 scalars
 // (92-116 bytes), the packed U <= 8 form (52-84) and the bf16-split Gram
 // (24-48) the 3-wave budget spills more, so those keep 2 waves (at B <= 64
