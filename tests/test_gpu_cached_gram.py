@@ -150,3 +150,46 @@ def test_batched_frames_with_and_without_gram():
         torch.cuda.synchronize()
         assert np.array_equal(_bits(llrs[i]), _bits(d["llr"])), i
         assert np.array_equal(_bits(Qs[i]), _bits(Q)), i
+
+
+@pytest.mark.parametrize("B,U,S,dt", [(128, 16, 14, "c32"), (96, 12, 9, "c32"), (128, 32, 14, "c32"),
+                                      (64, 16, 14, "bf16"), (100, 5, 14, "c32")])
+def test_cached_gram_every_schedule(B, U, S, dt):
+    """The cached-Gram calls under every schedule form that takes G (generic,
+    stream, stream-small; for precoding also the H-resident kernel), each
+    bitwise the direct call under the same schedule for U > 8 and within the
+    oracle's tolerance at U <= 8; the other forms fall back to one of these."""
+    print(f"cached gram schedules {B}x{U} {dt}", flush=True)
+    from paper_1404_0424_amd import autotune as T
+    up, dn = _frames(f"sched{B}x{U}{dt}", 23, B, U, S, 6, 12.0)
+    A = api()
+    H, Y, T_ = dev(up.H), dev(up.Y), dev(dn.T)
+    code = 0
+    if dt != "c32":
+        H, Y = A.convert(H, dt), A.convert(Y, dt)
+        code = {"f16": 1, "bf16": 2}[dt]
+    G, _ = A.gram_mf(H, None, reg=0.0)
+    saved = {op: T.get_schedule(op, U, code) for op in ("detect", "precode")}
+    ref = O.detect_cg(up.H, up.Y, up.n0, up.es, 4, 6, "approx") if dt == "c32" else None
+    try:
+        for op, names in (("detect", T.variants("detect")), ("precode", T.variants("precode"))):
+            for v, name in enumerate(names):
+                for bpc in (0, 4):
+                    T.set_schedule(op, U, code, v, bpc)
+                    if op == "detect":
+                        a = host(A.detect_cg(H, Y, up.n0, up.es, 4, 6)["llr"])
+                        b = host(A.detect_cg_gram(G, H, Y, up.n0, up.es, 4, 6)["llr"])
+                    else:
+                        a = host(A.precode_cg(H, T_, dn.beta, 4, True)[0])
+                        b = host(A.precode_cg_gram(G, H, T_, dn.beta, 4, True)[0])
+                    torch.cuda.synchronize()
+                    if U > 8 and name in ("generic", "stream", "stream-small", "resident"):
+                        assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), (op, name, bpc)
+                    elif op == "detect" and ref is not None:
+                        assert llr_err(b, ref["llr"]) <= TOL_L, (op, name, bpc)
+                    elif ref is not None:
+                        pref = O.precode_cg(up.H, dn.T, dn.beta, 4, True)
+                        assert rel_err_vec(b, pref["Q"], axis=1) <= TOL_X, (op, name, bpc)
+    finally:
+        for op, (v, b) in saved.items():
+            T.set_schedule(op, U, code, v, b)
