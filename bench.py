@@ -460,7 +460,10 @@ def main():
                     H16, Y16, n0, es, K, m, "approx", scalar, out={"llr": llr}))
                 autotune.tune("precode", wl.U, H16.dtype_code, lambda: api.precode_cg(
                     H16, T, beta, K, normalize=True, scalar_prec=scalar, qnorm=False, out=Q))
+                autotune.tune("slot", wl.U, H16.dtype_code, lambda: slot_call(H16, Y16),
+                              exclude=autotune.X3_VARIANTS)
             w2, d2, p2 = timed(H16, Y16, dt, separate=True)
+            w3, s3 = timed(H16, Y16, f"{dt} slot")
             o = api.detect_cg(H16, Y16, n0, es, K, m, "approx", scalar, xhat=True,
                               out={"llr": llr})
             api.precode_cg(H16, T, beta, K, normalize=True, scalar_prec=scalar, qnorm=False,
@@ -477,6 +480,8 @@ def main():
                             "llr_gbit_s": llr_bits / w2 / 1e9,
                             "detect_kernel_ms": d2 * 1e3, "detect_hbm_gbs": b16 / d2 / 1e9,
                             "precode_kernel_ms": p2 * 1e3,
+                            "slot_ms_per_step": w3 * 1e3, "slot_solves_per_s": solves / w3,
+                            "slot_kernel_ms": s3 * 1e3,
                             "storage": f"{dt} H and Y, FP32 accumulate and CG"}
             del H16, Y16
         # exact in-loop SINR (parity mode, Sec. III-C-1): one U x U x U complex

@@ -384,7 +384,7 @@ mimo_status mimo_detect_precode_cg(const mimo_shape* ul, const mimo_shape* dl, c
   const mimo::Schedule sch = get_sched(MIMO_OP_SLOT, ul->U, in_dtype);
   if ((sch.variant == mimo::kSlotFused || sch.variant == mimo::kSlotFusedX3) &&
       mimo::slot_eligible(p, in_dtype))
-    return hip_status(mimo::launch_slot(p, f64, qam_bits, sch, (hipStream_t)stream),
+    return hip_status(mimo::launch_slot(p, in_dtype, f64, qam_bits, sch, (hipStream_t)stream),
                       "detect_precode_cg launch");
   CHECK(hip_status(mimo::launch_detect_approx(p.ul, in_dtype, f64, qam_bits,
                                               get_sched(MIMO_OP_DETECT, ul->U, in_dtype),

@@ -27,11 +27,12 @@ hipError_t launch_detect_split(const DetectParams& p, int scalar_f64, int m_bits
                                const Schedule& sch, hipStream_t stream);
 hipError_t launch_precode_split(const PrecodeParams& p, int scalar_f64, const Schedule& sch,
                                 hipStream_t stream);
-// Uplink + downlink slot in one H-resident kernel (complex64, U <= 16,
-// S <= 16 in both directions, B <= 128); other calls take two launches.
+// Uplink + downlink slot in one H-resident kernel (complex64 or 16-bit
+// storage, U <= 16, S <= 16 in both directions, B <= 128); other calls take
+// two launches.
 bool slot_eligible(const SlotParams& p, int in_dtype);
-hipError_t launch_slot(const SlotParams& p, int scalar_f64, int m_bits, const Schedule& sch,
-                       hipStream_t stream);
+hipError_t launch_slot(const SlotParams& p, int in_dtype, int scalar_f64, int m_bits,
+                       const Schedule& sch, hipStream_t stream);
 // Four wavefronts per subcarrier, one 16-user tile each (complex64,
 // 32 < U <= 64, approximate SINR; any B and S).
 hipError_t launch_detect_wide(const DetectParams& p, int scalar_f64, int m_bits,

@@ -38,6 +38,32 @@ __device__ __forceinline__ float2 load_y_step(const Sub& sb, int t) {
   return bload2(sb.ry, sb.oy, (uint32_t)(4 * t) * sb.S * 8u);
 }
 
+// 16-bit storage: the Y parts (re, im) of the 32-antenna block q for lane
+// (c, g), in the operand order of Block16 (as its load with the matched
+// filter reads them).
+template <typename V8>
+__device__ __forceinline__ void load_y_block16(const Sub16<1>& sb, int q, V8& yr, V8& yi) {
+  const uint32_t kb = (uint32_t)(4 * q);              // first 8-antenna block of the step
+  yr = __builtin_bit_cast(V8, bload4(sb.ry, sb.oy, kb * 2u * sb.S * 16u));
+  yi = __builtin_bit_cast(V8, bload4(sb.ry, sb.oy, (kb * 2u + 1u) * sb.S * 16u));
+}
+
+template <typename IN>
+struct SlotY16 {                                      // complex64 forms: Y through the ring
+  static constexpr bool on = false;
+  using V8 = float;
+};
+template <>
+struct SlotY16<InF16> {
+  static constexpr bool on = true;
+  using V8 = h8;
+};
+template <>
+struct SlotY16<InBF16> {
+  static constexpr bool on = true;
+  using V8 = bf8;
+};
+
 // Register budget.  The channel (64 VGPRs at B = 128) is held from the Gram
 // to the output stage and the next subcarrier's is in flight during the
 // uplink stage: 174 VGPRs with FP32 CG scalars, 2 waves per SIMD.  A 3-wave
@@ -61,6 +87,10 @@ __global__ __launch_bounds__(256, (slot_min_blocks<IN, ST>())) void slot_residen
   constexpr int KS = RB::ANT / 4;               // k-steps (4 antennas) per block
   constexpr int NKS = BMAX / 4;                 // k-steps of Y per subcarrier
   constexpr int NY = 8;                         // k-steps of Y in flight (16, 32: no faster)
+  // 16-bit storage: the whole subcarrier's Y (NK blocks, 32 VGPRs at B = 128)
+  // is held like its channel instead of the complex64 ring
+  constexpr bool Y16 = SlotY16<IN>::on;
+  using V8 = typename SlotY16<IN>::V8;
   // per wave: A, P, the second H tile buffer and the output tile (float2),
   // reused as the uplink LLR staging tile
   constexpr int APH = 2 * (NU * AST + 2 * NU * kPST + 16 * 16);       // floats
@@ -82,7 +112,8 @@ __global__ __launch_bounds__(256, (slot_min_blocks<IN, ST>())) void slot_residen
 
   int64_t n = (int64_t)blockIdx.x * kWavesPerBlock + wv;
   RB hb[NK];
-  float2 yv[NY];
+  float2 yv[Y16 ? 1 : NY];
+  V8 y16r[Y16 ? NK : 1], y16i[Y16 ? NK : 1];
   Sub cur;
   if (n < n_sc) {
     const int B = sp.ul.B, U = sp.ul.U, Su = sp.ul.S;
@@ -90,8 +121,13 @@ __global__ __launch_bounds__(256, (slot_min_blocks<IN, ST>())) void slot_residen
              c, g);
 #pragma unroll
     for (int t = 0; t < NK; ++t) hb[t].template load<false, kOnceCPol>(cur, t * RB::ANT);
+    if constexpr (Y16) {
 #pragma unroll
-    for (int t = 0; t < NY; ++t) yv[t] = load_y_step(cur, t);
+      for (int q = 0; q < NK; ++q) load_y_block16(cur, q, y16r[q], y16i[q]);
+    } else {
+#pragma unroll
+      for (int t = 0; t < NY; ++t) yv[t] = load_y_step(cur, t);
+    }
   }
   while (n < n_sc) {
     const DetectParams ul = opaque_sizes(sp.ul);
@@ -117,17 +153,27 @@ __global__ __launch_bounds__(256, (slot_min_blocks<IN, ST>())) void slot_residen
     acc.clear();
 #pragma unroll
     for (int q = 0; q < NK; ++q) {
-      if (q * RB::ANT < B) {
-        hb[q].template mma<true, false>(acc);
-        RB blk = hb[q];                               // with the block's Y k-steps from the ring
+      if constexpr (Y16) {
+        if (q * RB::ANT < B) {
+          hb[q].template mma<true, false>(acc);
+          RB blk = hb[q];                             // with the block's held Y parts
+          blk.yr[0] = y16r[q];
+          blk.yi[0] = y16i[q];
+          blk.template mma<false, true>(acc);
+        }
+      } else {
+        if (q * RB::ANT < B) {
+          hb[q].template mma<true, false>(acc);
+          RB blk = hb[q];                             // with the block's Y k-steps from the ring
 #pragma unroll
-        for (int e = 0; e < KS; ++e) blk.y[e] = yv[(q * KS + e) % NY];
-        blk.template mma<false, true>(acc);
-      }
+          for (int e = 0; e < KS; ++e) blk.y[e] = yv[(q * KS + e) % NY];
+          blk.template mma<false, true>(acc);
+        }
 #pragma unroll
-      for (int e = 0; e < KS; ++e) {
-        const int t = q * KS + e;
-        if (t + NY < NKS) yv[t % NY] = load_y_step(cur, t + NY);
+        for (int e = 0; e < KS; ++e) {
+          const int t = q * KS + e;
+          if (t + NY < NKS) yv[t % NY] = load_y_step(cur, t + NY);
+        }
       }
     }
     finish_mf(IN{}, acc);
@@ -171,8 +217,13 @@ __global__ __launch_bounds__(256, (slot_min_blocks<IN, ST>())) void slot_residen
       cg_step<1, ST>(su, at, Ps, c, g, al, be);
       tracker_step<1, ST>(tk, d, al, be);
     }
+    if constexpr (Y16) {
 #pragma unroll
-    for (int t = 0; t < NY; ++t) yv[t] = load_y_step(nxt, t);
+      for (int q = 0; q < NK; ++q) load_y_block16(nxt, q, y16r[q], y16i[q]);
+    } else {
+#pragma unroll
+      for (int t = 0; t < NY; ++t) yv[t] = load_y_step(nxt, t);
+    }
     llr_stage<1, ST, M_BITS, true, true>(ul, n, 0, su.v, tk.tv, Gs, c, g, W_s[wv]);
     n = nn;
     cur = nxt;
@@ -180,7 +231,8 @@ __global__ __launch_bounds__(256, (slot_min_blocks<IN, ST>())) void slot_residen
 }
 
 bool slot_eligible(const SlotParams& p, int in_dtype) {
-  return in_dtype == 0 && p.ul.U <= 16 && p.ul.S <= 16 && p.dl.S <= 16 && p.ul.B <= 128;
+  return in_dtype >= 0 && in_dtype <= 2 && p.ul.U <= 16 && p.ul.S <= 16 && p.dl.S <= 16 &&
+         p.ul.B <= 128;
 }
 
 template <int BMAX, typename IN, typename ST>
@@ -211,8 +263,10 @@ static hipError_t launch_st(const SlotParams& p, int f64, int m_bits, const Sche
              : launch_b<IN, float>(p, m_bits, sch, stream);
 }
 
-hipError_t launch_slot(const SlotParams& p, int scalar_f64, int m_bits, const Schedule& sch,
-                       hipStream_t stream) {
+hipError_t launch_slot(const SlotParams& p, int in_dtype, int scalar_f64, int m_bits,
+                       const Schedule& sch, hipStream_t stream) {
+  if (in_dtype == 1) return launch_st<InF16>(p, scalar_f64, m_bits, sch, stream);
+  if (in_dtype == 2) return launch_st<InBF16>(p, scalar_f64, m_bits, sch, stream);
   if (sch.variant == kSlotFusedX3) return launch_st<InC32X3>(p, scalar_f64, m_bits, sch, stream);
   if (p.ul.U <= 8) return launch_st<InC32P>(p, scalar_f64, m_bits, sch, stream);
   return launch_st<InC32>(p, scalar_f64, m_bits, sch, stream);

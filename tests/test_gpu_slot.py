@@ -143,7 +143,7 @@ def test_slot_matches_separate_and_oracle(case):
 
 
 # calls the fused kernel does not cover run as two launches: U > 16, S > 16,
-# B > 128, 16-bit storage; the "separate" variant always does
+# B > 128; the "separate" variant always does
 FALLBACK = [
     ("128x20_two_tiles", 30, 128, 20, 14, 14, 4, 4, 6, 15.0),
     ("64x8_S20_ul", 25, 64, 8, 20, 5, 3, 3, 4, 10.0),
@@ -182,6 +182,39 @@ def test_slot_separate_variant_and_16bit_storage():
     Yr = O.dequantize_bf16(O.quantize_bf16(up.Y))
     assert llr_err(c[0]["llr"], O.detect_cg(Hr, Yr, up.n0, up.es, K, m)["llr"]) <= TOL_L
     assert rel_err_vec(c[1], O.precode_cg(Hr, dn.T, beta, K, True)["Q"], axis=1) <= TOL_X
+
+
+# 16-bit channel storage in the fused kernel: (name, n_sc, B, U, S_ul, S_dl, K_ul, K_dl,
+# qam_bits, storage, scalar, optional outputs, blocks_per_cu)
+CASES16 = [
+    ("128x16_bf16", 37, 128, 16, 14, 14, 4, 4, 6, "bf16", "f32", True, 0),
+    ("128x16_f16_persistent", 211, 128, 16, 14, 9, 4, 5, 6, "f16", "f32", False, 3),
+    ("64x12_f16_B64", 29, 64, 12, 5, 16, 3, 4, 4, "f16", "f32", True, 0),
+    ("96x8_bf16_f64", 23, 96, 8, 16, 1, 5, 3, 8, "bf16", "f64", True, 2),
+    ("120x5_f16_ragged", 17, 120, 5, 3, 7, 2, 6, 2, "f16", "f32", False, 0),
+]
+
+
+@pytest.mark.parametrize("case", CASES16, ids=[c[0] for c in CASES16])
+def test_slot_16bit_fused(case):
+    """The fused kernel with FP16/BF16 channel and receive-vector storage:
+    bitwise the two separate 16-bit calls, and the oracle on the same rounded
+    inputs."""
+    name, n, B, U, Su, Sd, Ku, Kd, m, dt, scalar, aux, bpc = case
+    print(f"slot 16-bit {name}", flush=True)
+    up, dn = _frames(name, n, B, U, Su, Sd, m, 15.0)
+    beta = up.n0 / up.es
+    A = api()
+    Hq, Yq, T = A.convert(dev(up.H), dt), A.convert(dev(up.Y), dt), dev(dn.T)
+    fused = _run_slot(Hq, Yq, T, up, beta, Ku, Kd, m, True, scalar, aux, "fused", bpc,
+                      Hq.dtype_code)
+    sep = _run_separate(Hq, Yq, T, up, beta, Ku, Kd, m, True, scalar, aux)
+    _same(fused, sep)
+    deq = O.dequantize_f16 if dt == "f16" else O.dequantize_bf16
+    qz = O.quantize_f16 if dt == "f16" else O.quantize_bf16
+    Hr, Yr = deq(qz(up.H)), deq(qz(up.Y))
+    assert llr_err(fused[0]["llr"], O.detect_cg(Hr, Yr, up.n0, up.es, Ku, m)["llr"]) <= TOL_L
+    assert rel_err_vec(fused[1], O.precode_cg(Hr, dn.T, beta, Kd, True)["Q"], axis=1) <= TOL_X
 
 
 def test_slot_full_size_sampled():
